@@ -1,0 +1,788 @@
+/*
+ * CPU oracle of the 3D propagation hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow and written to be checked by eye against the method:
+ *   - section 3 / Fig. 1 of the paper: a candidate carries all of its state;
+ *     each cycle runs the integration module (deflection in the magnetic
+ *     field, position, direction and trajectory length), then interaction
+ *     modules (continuous loss, stochastic interactions that decide per step
+ *     whether an interaction happens and reset all interaction state after
+ *     one), then boundary / observer modules; the active flag is checked after
+ *     every cycle.  Secondaries live with their parent until processed.
+ *   - section 6: 3D propagation through a turbulent field (the field array is
+ *     an input).
+ * Everything the paper leaves open (integrator, interpolation, controller,
+ * tables, random stream) follows the readings listed with each function.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no -ffast-math,
+ * no FMA contraction) so every FP64 operation is one correctly rounded IEEE
+ * operation in the order written.
+ */
+#include "crp_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define C_LIGHT 299792458.0
+
+/* ----------------------------------------------------------------------- */
+/* Small vector helpers, fixed evaluation order.                           */
+/* ----------------------------------------------------------------------- */
+static void cross_d(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot_d(const double a[3], const double b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+static void cross_f(const float a[3], const float b[3], float c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static float dot_f(const float a[3], const float b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+/* ----------------------------------------------------------------------- */
+/* Field: periodic trilinear interpolation on a vertex-centred grid.       */
+/* The paper only says grids give fast lookup of precomputed fields        */
+/* (section 4, magnetic field techniques); trilinear on the periodic       */
+/* vertex grid is this project's reading.                                  */
+/* ----------------------------------------------------------------------- */
+static double grid_value(const or_grid* g, int64_t i, int64_t j, int64_t k, int c)
+{
+    int64_t off = ((i * g->n[1] + j) * g->n[2] + k) * 3 + c;
+    if (g->dtype == OR_GRID_F64)
+        return ((const double*)g->data)[off];
+    return (double)((const float*)g->data)[off];
+}
+
+/* Cell index pair and fractional offset along one axis (FP64 in all modes). */
+static void axis_cell(const or_grid* g, int a, double p, int64_t idx[2], double* t)
+{
+    double inv = 1.0 / g->spacing;
+    double f = (p - g->origin[a]) * inv;
+    double fl = floor(f);
+    int64_t i = (int64_t)fl;
+    int64_t n = g->n[a];
+    int64_t i0 = ((i % n) + n) % n;
+    idx[0] = i0;
+    idx[1] = (i0 + 1) % n;
+    *t = f - fl;
+}
+
+static void field_fp64(const or_grid* g, const double p[3], double B[3])
+{
+    int64_t idx[3][2];
+    double w[3][2];
+    for (int a = 0; a < 3; ++a) {
+        double t;
+        axis_cell(g, a, p[a], idx[a], &t);
+        w[a][0] = 1.0 - t;
+        w[a][1] = t;
+    }
+    for (int c = 0; c < 8; ++c) {
+        int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        double wt = (w[0][dx] * w[1][dy]) * w[2][dz];
+        for (int comp = 0; comp < 3; ++comp) {
+            double v = grid_value(g, idx[0][dx], idx[1][dy], idx[2][dz], comp);
+            if (c == 0)
+                B[comp] = wt * v;
+            else
+                B[comp] = B[comp] + wt * v;
+        }
+    }
+}
+
+/* Precision form: offsets in FP64, weights and accumulation in FP32. */
+static void field_mix(const or_grid* g, const double p[3], float B[3])
+{
+    int64_t idx[3][2];
+    float w[3][2];
+    for (int a = 0; a < 3; ++a) {
+        double t;
+        axis_cell(g, a, p[a], idx[a], &t);
+        float tf = (float)t;
+        w[a][0] = 1.0f - tf;
+        w[a][1] = tf;
+    }
+    for (int c = 0; c < 8; ++c) {
+        int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        float wt = (w[0][dx] * w[1][dy]) * w[2][dz];
+        for (int comp = 0; comp < 3; ++comp) {
+            float v = (float)grid_value(g, idx[0][dx], idx[1][dy], idx[2][dz], comp);
+            if (c == 0)
+                B[comp] = wt * v;
+            else
+                B[comp] = B[comp] + wt * v;
+        }
+    }
+}
+
+void oracle_eval_field(const or_grid* grid, int32_t mode, int64_t n, const double* pos,
+                       double* B)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (mode == OR_MIX) {
+            float bf[3];
+            field_mix(grid, pos + 3 * i, bf);
+            for (int c = 0; c < 3; ++c)
+                B[3 * i + c] = (double)bf[c];
+        } else {
+            field_fp64(grid, pos + 3 * i, B + 3 * i);
+        }
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Integration module: Cash-Karp embedded Runge-Kutta 4(5) (Cash & Karp,   */
+/* ACM TOMS 16 (1990) 201) on the ultra-relativistic Lorentz-force system  */
+/* dx/ds = u, du/ds = kappa (u x B(x)), kappa = Z c / E_eV, s = path.      */
+/* Local extrapolation: the 5th-order solution is propagated; the error is */
+/* the Euclidean norm of the direction difference of the embedded pair.    */
+/* ----------------------------------------------------------------------- */
+static const double CK_A[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0},
+};
+/* 5th-order weights (stages 2 and 5 have zero weight). */
+static const double CK_B[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0,
+                               512.0 / 1771.0};
+/* Difference between the 5th-order weights and the embedded 4th-order ones
+ * (2825/27648, 0, 18575/48384, 13525/55296, 277/14336, 1/4), each exact
+ * rational difference rounded once. */
+static const double CK_E[6] = {-277.0 / 64512.0, 0.0, 6925.0 / 370944.0,
+                               -6925.0 / 202752.0, -277.0 / 14336.0, 277.0 / 7084.0};
+
+static void deriv_fp64(const or_grid* g, double kappa, const double y[6], double k[6])
+{
+    double B[3], c[3];
+    field_fp64(g, y, B);
+    cross_d(y + 3, B, c);
+    k[0] = y[3];
+    k[1] = y[4];
+    k[2] = y[5];
+    k[3] = kappa * c[0];
+    k[4] = kappa * c[1];
+    k[5] = kappa * c[2];
+}
+
+static double ck_attempt_fp64(const or_grid* g, double kappa, const double y[6], double h,
+                              double y5[6])
+{
+    double K[6][6];
+    double ys[6];
+    deriv_fp64(g, kappa, y, K[0]);
+    for (int i = 1; i < 6; ++i) {
+        for (int q = 0; q < 6; ++q) {
+            double s = CK_A[i][0] * K[0][q];
+            for (int j = 1; j < i; ++j)
+                s = s + CK_A[i][j] * K[j][q];
+            ys[q] = y[q] + h * s;
+        }
+        deriv_fp64(g, kappa, ys, K[i]);
+    }
+    for (int q = 0; q < 6; ++q) {
+        double s = CK_B[0] * K[0][q];
+        s = s + CK_B[2] * K[2][q];
+        s = s + CK_B[3] * K[3][q];
+        s = s + CK_B[5] * K[5][q];
+        y5[q] = y[q] + h * s;
+    }
+    double e[3];
+    for (int q = 0; q < 3; ++q) {
+        double s = CK_E[0] * K[0][3 + q];
+        s = s + CK_E[2] * K[2][3 + q];
+        s = s + CK_E[3] * K[3][3 + q];
+        s = s + CK_E[4] * K[4][3 + q];
+        s = s + CK_E[5] * K[5][3 + q];
+        e[q] = s;
+    }
+    return h * sqrt(dot_d(e, e));
+}
+
+/* Precision form.  The stage increments G_i = h f(y_i) are carried in FP32:
+ * G_i^x = h u_i and G_i^u = (h kappa) (u_i x B(x_i)), with h and h*kappa
+ * formed in FP64 and rounded once; each is O(1) or O(step) in magnitude, so no
+ * FP32 underflow occurs for nG fields.  Stage sums, the 5th-order increment,
+ * the direction, the field and the error norm are FP32; positions stay FP64
+ * and receive the FP32 offset. */
+static void incr_mix(const or_grid* g, float hf, float hk, const double x[3], const float u[3],
+                     float G[6])
+{
+    float B[3], c[3];
+    field_mix(g, x, B);
+    cross_f(u, B, c);
+    G[0] = hf * u[0];
+    G[1] = hf * u[1];
+    G[2] = hf * u[2];
+    G[3] = hk * c[0];
+    G[4] = hk * c[1];
+    G[5] = hk * c[2];
+}
+
+static double ck_attempt_mix(const or_grid* g, double kappa_d, const double x[3],
+                             const double u_d[3], double h_d, double x5[3], double u5_d[3])
+{
+    float A[6][5], Bw[6], Ew[6];
+    for (int i = 0; i < 6; ++i) {
+        for (int j = 0; j < 5; ++j)
+            A[i][j] = (float)CK_A[i][j];
+        Bw[i] = (float)CK_B[i];
+        Ew[i] = (float)CK_E[i];
+    }
+    float hf = (float)h_d;
+    float hk = (float)(h_d * kappa_d);
+    float u[3] = {(float)u_d[0], (float)u_d[1], (float)u_d[2]};
+    float G[6][6];
+    double xs[3];
+    float us[3];
+    incr_mix(g, hf, hk, x, u, G[0]);
+    for (int i = 1; i < 6; ++i) {
+        float s[6];
+        for (int q = 0; q < 6; ++q) {
+            float acc = A[i][0] * G[0][q];
+            for (int j = 1; j < i; ++j)
+                acc = acc + A[i][j] * G[j][q];
+            s[q] = acc;
+        }
+        for (int q = 0; q < 3; ++q) {
+            xs[q] = x[q] + (double)s[q];
+            us[q] = u[q] + s[3 + q];
+        }
+        incr_mix(g, hf, hk, xs, us, G[i]);
+    }
+    for (int q = 0; q < 6; ++q) {
+        float s = Bw[0] * G[0][q];
+        s = s + Bw[2] * G[2][q];
+        s = s + Bw[3] * G[3][q];
+        s = s + Bw[5] * G[5][q];
+        if (q < 3)
+            x5[q] = x[q] + (double)s;
+        else
+            u5_d[q - 3] = (double)(u[q - 3] + s);
+    }
+    float e[3];
+    for (int q = 0; q < 3; ++q) {
+        float s = Ew[0] * G[0][3 + q];
+        s = s + Ew[2] * G[2][3 + q];
+        s = s + Ew[3] * G[3][3 + q];
+        s = s + Ew[4] * G[4][3 + q];
+        s = s + Ew[5] * G[5][3 + q];
+        e[q] = s;
+    }
+    return (double)sqrtf(dot_f(e, e));
+}
+
+void oracle_ck_attempt(const or_grid* grid, int32_t mode, const double x[3], const double u[3],
+                       double kappa, double h, double x5[3], double u5[3], double* err)
+{
+    if (mode == OR_MIX) {
+        double uf[3] = {(double)(float)u[0], (double)(float)u[1], (double)(float)u[2]};
+        *err = ck_attempt_mix(grid, kappa, x, uf, h, x5, u5);
+        return;
+    }
+    double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]}, y5[6];
+    *err = ck_attempt_fp64(grid, kappa, y, h, y5);
+    for (int q = 0; q < 3; ++q) {
+        x5[q] = y5[q];
+        u5[q] = y5[3 + q];
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Step-size controller factor: floor(1024 * 0.95 * r^(-1/5)) / 1024 as the */
+/* largest integer k with k^5 * r <= (0.95*1024)^5, evaluated in FP64 in a  */
+/* fixed order, so the result does not depend on the libm pow used for the  */
+/* first guess.                                                             */
+/* ----------------------------------------------------------------------- */
+static int ctrl_pred(int32_t k, double r)
+{
+    double c1 = 0.95 * 1024.0;
+    double c5 = (((c1 * c1) * c1) * c1) * c1;
+    double kd = (double)k;
+    double k5 = (((kd * kd) * kd) * kd) * kd;
+    return k5 * r <= c5;
+}
+
+int32_t oracle_ctrl_k(double r)
+{
+    const int32_t KMAX = 5121;
+    double g = (0.95 * 1024.0) * pow(r, -0.2);
+    int32_t k = g > (double)KMAX ? KMAX : (int32_t)floor(g);
+    while (k < KMAX && ctrl_pred(k + 1, r))
+        ++k;
+    while (k > 0 && !ctrl_pred(k, r))
+        --k;
+    return k;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Tables: linear interpolation in E between log-spaced nodes, clamped     */
+/* outside; the bracketing node is found by bisection.                     */
+/* ----------------------------------------------------------------------- */
+double oracle_table_lookup(const or_tables* tab, int32_t which, double eps)
+{
+    const double* v = which == 0 ? tab->tpi : (which == 1 ? tab->tn : tab->bp);
+    const double* e = tab->e;
+    int n = tab->n;
+    if (eps <= e[0])
+        return v[0];
+    if (eps >= e[n - 1])
+        return v[n - 1];
+    int lo = 0, hi = n - 1; /* e[lo] <= eps < e[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (e[mid] <= eps)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    double t = (eps - e[lo]) / (e[lo + 1] - e[lo]);
+    return v[lo] + t * (v[lo + 1] - v[lo]);
+}
+
+/* Species scaling of per-nucleon tables: rates scale with A at eps = E/A;
+ * the nucleon-loss channel needs A >= 2; the loss rate scales with Z^2/A. */
+void oracle_rates(const or_tables* tab, int32_t A, int32_t Z, double E, double out[4])
+{
+    double eps = E / (double)A;
+    double rpi = (double)A * oracle_table_lookup(tab, 0, eps);
+    double rn = A >= 2 ? (double)A * oracle_table_lookup(tab, 1, eps) : 0.0;
+    double zz = (double)(Z * Z) / (double)A;
+    out[0] = rpi;
+    out[1] = rn;
+    out[2] = rpi + rn;
+    out[3] = zz * oracle_table_lookup(tab, 2, eps);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Counter-based random numbers: Philox4x64-10 (Salmon, Moraes, Dror and   */
+/* Shaw, SC'11): 10 rounds of two 64x64->128 multiplications with a Weyl   */
+/* key schedule.                                                           */
+/* ----------------------------------------------------------------------- */
+void oracle_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Optical depth to the next interaction: -ln U with U = ((w>>11)+1) 2^-53 in
+ * (0,1], rounded to a multiple of 2^-24 and at least 2^-24. */
+double oracle_texp(uint64_t w)
+{
+    double U = (double)((w >> 11) + 1) * 0x1p-53;
+    double t = -log(U);
+    double q = floor(t * 16777216.0 + 0.5) * 0x1p-24;
+    return q < 0x1p-24 ? 0x1p-24 : q;
+}
+
+static void draw(uint64_t seed, uint32_t id, uint32_t lineage, uint32_t m, uint64_t w[4])
+{
+    uint64_t key[2] = {seed, ((uint64_t)id << 32) | (uint64_t)lineage};
+    uint64_t ctr[4] = {(uint64_t)m, 0, 0, 0};
+    oracle_philox4x64(ctr, key, w);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Candidate and the module cycle.                                         */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+    double x[3], u[3], E, L, Lmax, hctrl, tau, u0[3], E0;
+    uint32_t id, lineage, m, nsteps, nrej;
+    int32_t A, Z, status;
+    int64_t cycles;
+} cand_t;
+
+typedef struct {
+    cand_t* v;
+    int64_t n, cap;
+} stack_t_;
+
+static void push(stack_t_* s, const cand_t* c)
+{
+    if (s->n == s->cap) {
+        s->cap = s->cap ? 2 * s->cap : 16;
+        s->v = (cand_t*)realloc(s->v, (size_t)s->cap * sizeof(cand_t));
+    }
+    s->v[s->n++] = *c;
+}
+
+enum { LIM_CTRL = 0, LIM_TRAJ = 1, LIM_INTER = 2, LIM_LOSS = 3, LIM_OBS = 4 };
+
+static double dist_obs(const or_config* cfg, const double x[3])
+{
+    double d[3] = {x[0] - cfg->obs[0], x[1] - cfg->obs[1], x[2] - cfg->obs[2]};
+    return sqrt(dot_d(d, d));
+}
+
+static void emit_finished(or_finished* fin, int64_t* n_fin, const cand_t* c, or_counts* cnt)
+{
+    int64_t k;
+#pragma omp atomic capture
+    k = (*n_fin)++;
+    if (k >= fin->cap) {
+        cnt->fin_dropped++;
+        return;
+    }
+    fin->id[k] = c->id;
+    fin->lineage[k] = c->lineage;
+    fin->m[k] = c->m;
+    fin->nsteps[k] = c->nsteps;
+    fin->nrej[k] = c->nrej;
+    fin->status[k] = c->status;
+    fin->A[k] = c->A;
+    fin->Z[k] = c->Z;
+    fin->E[k] = c->E;
+    fin->L[k] = c->L;
+    fin->E0[k] = c->E0;
+    for (int q = 0; q < 3; ++q) {
+        fin->x[3 * k + q] = c->x[q];
+        fin->u[3 * k + q] = c->u[q];
+        fin->u0[3 * k + q] = c->u0[q];
+    }
+}
+
+static void emit_neutral(or_neutral* neu, int64_t* n_neu, const cand_t* c, double dE,
+                         or_counts* cnt)
+{
+    int64_t k;
+#pragma omp atomic capture
+    k = (*n_neu)++;
+    if (k >= neu->cap) {
+        cnt->neu_dropped++;
+        return;
+    }
+    neu->id[k] = c->id;
+    neu->lineage[k] = c->lineage;
+    neu->m[k] = c->m;
+    neu->chan[k] = OR_CHAN_PI;
+    neu->E[k] = dE;
+    for (int q = 0; q < 3; ++q) {
+        neu->x[3 * k + q] = c->x[q];
+        neu->u[3 * k + q] = c->u[q];
+    }
+}
+
+/* Runs one candidate until its active flag drops (or the cycle cap). */
+static void run_candidate(const or_config* cfg, const or_grid* g, const or_tables* tab,
+                          cand_t* c, stack_t_* spawn, or_finished* fin, int64_t* n_fin,
+                          or_neutral* neu, int64_t* n_neu, or_counts* cnt)
+{
+    const int mix = cfg->precision == OR_MIX;
+    while (c->status == OR_ACTIVE) {
+        if (cfg->max_cycles > 0 && c->cycles >= cfg->max_cycles)
+            break;
+        /* interaction and loss rates at the start of the cycle */
+        double rt[4];
+        oracle_rates(tab, c->A, c->Z, c->E, rt);
+        double R = rt[2], beta = rt[3];
+
+        /* step proposal: controller step, then physical limits */
+        double h = c->hctrl;
+        int flag = LIM_CTRL;
+        if (c->Lmax - c->L < h) {
+            h = c->Lmax - c->L;
+            flag = LIM_TRAJ;
+        }
+        if (R > 0.0 && c->tau / R < h) {
+            h = c->tau / R;
+            flag = LIM_INTER;
+        }
+        if (beta > 0.0 && cfg->eps_loss / beta < h) {
+            h = cfg->eps_loss / beta;
+            flag = LIM_LOSS;
+        }
+        if (cfg->obs_r > 0.0) {
+            double d = dist_obs(cfg, c->x);
+            double half = 0.5 * cfg->obs_r;
+            double hob = d - half;
+            if (hob < half)
+                hob = half;
+            if (hob < h) {
+                h = hob;
+                flag = LIM_OBS;
+            }
+        }
+
+        /* integration module: adaptive Cash-Karp with retries */
+        double kappa = ((double)c->Z * C_LIGHT) / c->E;
+        double x5[3], u5[3], r;
+        for (;;) {
+            double err;
+            cnt->attempts++;
+            if (mix) {
+                err = ck_attempt_mix(g, kappa, c->x, c->u, h, x5, u5);
+            } else {
+                double y[6] = {c->x[0], c->x[1], c->x[2], c->u[0], c->u[1], c->u[2]}, y5[6];
+                err = ck_attempt_fp64(g, kappa, y, h, y5);
+                for (int q = 0; q < 3; ++q) {
+                    x5[q] = y5[q];
+                    u5[q] = y5[3 + q];
+                }
+            }
+            r = err / cfg->tol;
+            if (r <= 1.0 || h <= cfg->hmin) {
+                if (r > 1.0)
+                    cnt->forced++;
+                break;
+            }
+            cnt->rejects++;
+            c->nrej++;
+            double fac = (double)oracle_ctrl_k(r) / 1024.0;
+            if (fac < 0.1)
+                fac = 0.1;
+            h = h * fac;
+            if (h < cfg->hmin)
+                h = cfg->hmin;
+            flag = LIM_CTRL;
+        }
+        /* next controller step */
+        {
+            double fac = 5.0;
+            if (r > 0.0) {
+                fac = (double)oracle_ctrl_k(r) / 1024.0;
+                if (fac > 5.0)
+                    fac = 5.0;
+            }
+            double hn = h * fac;
+            if (hn < cfg->hmin)
+                hn = cfg->hmin;
+            if (hn > cfg->hmax)
+                hn = cfg->hmax;
+            c->hctrl = hn;
+        }
+        /* accept: position, direction, trajectory length */
+        for (int q = 0; q < 3; ++q)
+            c->x[q] = x5[q];
+        if (cfg->renormalize) {
+            if (mix) {
+                float uf[3] = {(float)u5[0], (float)u5[1], (float)u5[2]};
+                float nrm = sqrtf(dot_f(uf, uf));
+                for (int q = 0; q < 3; ++q)
+                    c->u[q] = (double)(uf[q] / nrm);
+            } else {
+                double nrm = sqrt(dot_d(u5, u5));
+                for (int q = 0; q < 3; ++q)
+                    c->u[q] = u5[q] / nrm;
+            }
+        } else {
+            for (int q = 0; q < 3; ++q)
+                c->u[q] = u5[q];
+        }
+        c->L = c->L + h;
+        c->nsteps++;
+        cnt->steps++;
+
+        /* continuous loss: E <- E * P22(beta h), the (2,2) Pade form of exp(-z) */
+        {
+            double z = beta * h;
+            double z2 = z * z;
+            double num = (12.0 - 6.0 * z) + z2;
+            double den = (12.0 + 6.0 * z) + z2;
+            c->E = c->E * (num / den);
+        }
+
+        /* stochastic interactions: optical-depth clock */
+        c->tau = c->tau - R * h;
+        if (flag == LIM_INTER || c->tau <= 0.0) {
+            c->m++;
+            uint64_t w[4];
+            draw(cfg->seed, c->id, c->lineage, c->m, w);
+            double Eint = c->E;
+            double rr[4];
+            oracle_rates(tab, c->A, c->Z, Eint, rr);
+            double ppi = rr[0], pn = rr[1], P = ppi + pn;
+            cnt->events++;
+            if (P > 0.0) {
+                double Uc = (double)(w[0] >> 11) * 0x1p-53;
+                if (Uc * P < ppi) {
+                    /* pion-like: one nucleon loses kappa_pi of its energy */
+                    double dE = (cfg->kappa_pi * Eint) / (double)c->A;
+                    c->E = Eint - dE;
+                    cnt->inter_pi++;
+                    cnt->neutral_sec++;
+                    emit_neutral(neu, n_neu, c, dE, cnt);
+                } else {
+                    /* nucleon loss: a proton leaves if protons outnumber
+                     * neutrons, else a neutron (decaying at once to a
+                     * proton of the same energy) */
+                    int32_t pout = (2 * c->Z > c->A) ? 1 : 0;
+                    int32_t Aold = c->A;
+                    double Esec = Eint / (double)Aold;
+                    c->Z -= pout;
+                    c->A -= 1;
+                    c->E = Eint - Esec;
+                    cnt->inter_n++;
+                    cnt->charged_sec++;
+                    cand_t s;
+                    memset(&s, 0, sizeof s);
+                    for (int q = 0; q < 3; ++q) {
+                        s.x[q] = c->x[q];
+                        s.u[q] = c->u[q];
+                        s.u0[q] = c->u0[q];
+                    }
+                    s.E = Esec;
+                    s.L = c->L;
+                    s.Lmax = c->Lmax;
+                    s.hctrl = cfg->hmin;
+                    s.E0 = c->E0;
+                    s.id = c->id;
+                    s.lineage = c->m;
+                    s.m = 0;
+                    s.A = 1;
+                    s.Z = 1;
+                    s.status = OR_ACTIVE;
+                    uint64_t ws[4];
+                    draw(cfg->seed, s.id, s.lineage, 0, ws);
+                    s.tau = oracle_texp(ws[1]);
+                    push(spawn, &s);
+                }
+            } else {
+                cnt->null_events++;
+            }
+            /* reset of all interaction state after an interaction */
+            c->tau = oracle_texp(w[1]);
+        }
+
+        /* boundary and observer modules; first match wins */
+        c->cycles++;
+        if (cfg->obs_r > 0.0 && dist_obs(cfg, c->x) <= cfg->obs_r)
+            c->status = OR_OBSERVED;
+        else if (flag == LIM_TRAJ || c->L >= c->Lmax)
+            c->status = OR_MAX_TRAJ;
+        else if (c->E < cfg->e_floor)
+            c->status = OR_ENERGY_FLOOR;
+    }
+    switch (c->status) {
+    case OR_OBSERVED:
+        cnt->observed++;
+        cnt->finished++;
+        break;
+    case OR_MAX_TRAJ:
+        cnt->max_traj++;
+        cnt->finished++;
+        break;
+    case OR_ENERGY_FLOOR:
+        cnt->energy_floor++;
+        cnt->finished++;
+        break;
+    default:
+        cnt->still_active++;
+        break;
+    }
+    emit_finished(fin, n_fin, c, cnt);
+}
+
+static void add_counts(or_counts* dst, const or_counts* src)
+{
+    const int64_t* s = (const int64_t*)src;
+    int64_t* d = (int64_t*)dst;
+    for (size_t i = 0; i < sizeof(or_counts) / sizeof(int64_t); ++i) {
+#pragma omp atomic
+        d[i] += s[i];
+    }
+}
+
+int oracle_propagate(const or_config* cfg, const or_grid* grid, const or_tables* tab,
+                     int64_t n, const uint32_t* id, const int32_t* A, const int32_t* Z,
+                     const double* E, const double* pos, const double* dir,
+                     const double* lmax, int nthreads,
+                     or_finished* fin, or_neutral* neu, or_counts* counts,
+                     int64_t* n_fin, int64_t* n_neu)
+{
+    int used = 1;
+    memset(counts, 0, sizeof *counts);
+    *n_fin = 0;
+    *n_neu = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads)
+#endif
+    {
+#ifdef _OPENMP
+#pragma omp single
+        used = omp_get_num_threads();
+#endif
+        or_counts local;
+        memset(&local, 0, sizeof local);
+        stack_t_ spawn = {NULL, 0, 0};
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t i = 0; i < n; ++i) {
+            cand_t c;
+            memset(&c, 0, sizeof c);
+            for (int q = 0; q < 3; ++q) {
+                c.x[q] = pos[3 * i + q];
+                c.u[q] = dir[3 * i + q];
+                if (cfg->precision == OR_MIX)
+                    c.u[q] = (double)(float)c.u[q];
+                c.u0[q] = c.u[q];
+            }
+            c.E = E[i];
+            c.E0 = E[i];
+            c.L = 0.0;
+            c.Lmax = lmax[i];
+            c.hctrl = cfg->hmin;
+            c.id = id[i];
+            c.lineage = 0;
+            c.m = 0;
+            c.A = A[i];
+            c.Z = Z[i];
+            c.status = OR_ACTIVE;
+            uint64_t w[4];
+            draw(cfg->seed, c.id, 0, 0, w);
+            c.tau = oracle_texp(w[1]);
+            run_candidate(cfg, grid, tab, &c, &spawn, fin, n_fin, neu, n_neu, &local);
+            /* secondaries after their parent, last in first out */
+            while (spawn.n > 0) {
+                cand_t s = spawn.v[--spawn.n];
+                run_candidate(cfg, grid, tab, &s, &spawn, fin, n_fin, neu, n_neu, &local);
+            }
+        }
+        free(spawn.v);
+        add_counts(counts, &local);
+    }
+    return used;
+}
