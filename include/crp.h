@@ -1,0 +1,236 @@
+/*
+ * crp.h -- C-ABI of the MI355X propagation library (libcrp.so).
+ *
+ * The library steps cosmic-ray candidates (nuclei) through a periodic
+ * magnetic-field grid on one GPU.  Each candidate carries all of its own
+ * state (paper, section 3, "cosmic ray candidate and modules"), so candidates
+ * are independent lanes of one persistent GPU kernel.  Every cycle of a
+ * candidate runs, in the order of Fig. 1 of the paper:
+ *   1. integration: an adaptive Cash-Karp 4(5) step of the Lorentz force
+ *      dx/ds = u, du/ds = (Z c / E) u x B(x), with B from periodic trilinear
+ *      interpolation of the grid;
+ *   2. interactions: a continuous relative energy loss (pair-production-like)
+ *      and stochastic interactions decided per step by an optical-depth clock
+ *      that is reset after every interaction (section 3);
+ *   3. boundary / observer checks: detection inside an observer sphere, the
+ *      maximum trajectory length, an energy floor; the active flag is checked
+ *      after each cycle.
+ * Secondaries: a nucleon-loss event spawns a charged proton candidate that is
+ * propagated in the same run; a pion-like event emits a neutral record.
+ *
+ * Units at this ABI: metres, eV, tesla; rates in 1/m.
+ * Threading: one context per host thread; calls on one context must not
+ * overlap.  All functions return a crp_status; no C++ exception crosses the
+ * ABI.  After an error, crp_last_error(ctx) describes it.
+ */
+#ifndef CRP_H
+#define CRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRP_OK = 0,
+    CRP_INCOMPLETE = 1,   /* propagate: cycle budget used up with candidates left */
+    CRP_EOVERFLOW = 2,    /* read: more records remain than fit in the buffer    */
+    CRP_EINVAL = -1,      /* invalid argument (nothing was changed)               */
+    CRP_EDEVICE = -2,     /* HIP runtime error                                    */
+    CRP_ENOMEM = -3,      /* device allocation failed                             */
+    CRP_ESTATE = -4,      /* call not valid in this state (e.g. no field/tables)  */
+    CRP_EQUEUE = -5       /* queue capacity exceeded (inject, or spawned secondaries
+                             dropped during propagate; see crp_counters)          */
+} crp_status;
+
+enum { CRP_FP64 = 0, CRP_MIX = 1 };                     /* stage precision        */
+enum { CRP_FIELD_GRID = 0, CRP_FIELD_NEURAL = 1 };      /* field source           */
+enum { CRP_F32 = 0, CRP_F64 = 1 };                      /* grid element type      */
+enum { CRP_LAYOUT_LINEAR = 0, CRP_LAYOUT_CORNER = 1 };  /* grid layout in HBM     */
+enum { CRP_ACTIVE = 0, CRP_OBSERVED = 1, CRP_MAX_TRAJ = 2, CRP_ENERGY_FLOOR = 3 };
+enum { CRP_CHAN_PI = 0, CRP_CHAN_N = 1 };
+
+/* Run configuration (copied at crp_create). */
+typedef struct {
+    int32_t precision;        /* CRP_FP64: every operation FP64.  CRP_MIX: RK stage
+                                 increments, field interpolation and direction in
+                                 FP32; position, length, step control, energy and
+                                 interactions in FP64. */
+    int32_t field_mode;       /* CRP_FIELD_GRID or CRP_FIELD_NEURAL (needs crp_nf_*) */
+    int32_t renormalize;      /* 1: |u| renormalised after every accepted step */
+    int32_t device;           /* HIP device ordinal */
+    double tol;               /* direction error tolerance per step */
+    double hmin, hmax;        /* step-size controller bounds, m (0 < hmin <= hmax) */
+    double eps_loss;          /* max relative continuous loss per step (> 0) */
+    double kappa_pi;          /* energy fraction of one nucleon lost in a pion-like event */
+    double e_floor;           /* candidates below this energy (eV) stop */
+    double obs_center[3];     /* observer sphere centre, m */
+    double obs_radius;        /* observer radius, m; 0 disables the observer */
+    uint64_t seed;            /* Philox4x64-10 key word 0 */
+    int64_t queue_capacity;   /* max pending + spawned candidates per propagate (> 0) */
+    int64_t neutral_capacity; /* max undrained neutral records (> 0) */
+} crp_config;
+
+/* Kernel launch shape of the persistent propagation kernel. */
+typedef struct {
+    int32_t block;            /* threads per block: 64, 128, 256 or 512 */
+    int32_t blocks_per_cu;    /* persistent blocks per compute unit (>= 1) */
+    int32_t quantum;          /* attempts between refills of idle lanes (>= 1) */
+    int32_t layout;           /* CRP_LAYOUT_LINEAR or CRP_LAYOUT_CORNER */
+} crp_launch;
+
+/* Caller-allocated host arrays for finished candidates ([n] or [n][3]). */
+typedef struct {
+    uint32_t *id, *lineage, *m, *nsteps, *nrej;
+    int32_t *status, *A, *Z;
+    double *E, *x, *u, *L, *u0, *E0;
+} crp_finished_soa;
+
+/* Caller-allocated host arrays for neutral secondary records. */
+typedef struct {
+    uint32_t *id, *lineage, *m;
+    int32_t* chan;
+    double *E, *x, *u;
+} crp_neutral_soa;
+
+/* Cumulative integer bookkeeping since crp_create (or crp_reset_counters). */
+typedef struct {
+    int64_t finished, observed, max_traj, energy_floor;
+    int64_t steps, attempts, rejects, forced;
+    int64_t events, null_events, inter_pi, inter_n;
+    int64_t charged_sec, neutral_sec;
+    int64_t queue_dropped, neutral_dropped;
+    int64_t pending;          /* candidates waiting for the next propagate */
+    int64_t finished_unread, neutral_unread;
+} crp_counters;
+
+typedef struct crp_ctx crp_ctx;
+
+/* Creates a context on cfg->device.  stream: a hipStream_t borrowed for all
+ * work of this context (NULL: the default stream).  The library allocates and
+ * owns every device buffer it uses.  Errors: CRP_EINVAL (bad config),
+ * CRP_EDEVICE, CRP_ENOMEM. */
+crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out);
+void crp_destroy(crp_ctx* ctx);
+
+/* Field grid: [nx][ny][nz][3] tesla, C order, vertex (i,j,k) at
+ * origin + (i,j,k) * spacing, periodic with period n * spacing on each axis
+ * (section 4 of the paper: precomputed grids for fast lookup; trilinear
+ * interpolation is this library's reading).  dtype: CRP_F32 or CRP_F64.
+ * on_device = 0: host data is copied.  on_device = 1: the device pointer is
+ * used in place until replaced or the context is destroyed (the caller keeps
+ * it alive).  Errors: CRP_EINVAL (dims < 2, > 2^20, bad dtype/spacing),
+ * CRP_ENOMEM. */
+crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int32_t on_device,
+                              int64_t nx, int64_t ny, int64_t nz, double spacing_m,
+                              const double origin_m[3]);
+
+/* Interaction tables per nucleon at eps = E/A on n strictly increasing nodes
+ * (eV): pion-like rate, nucleon-loss-like rate, proton relative loss rate
+ * (all 1/m, >= 0).  A nucleus (A, Z) uses R_pi = A t_pi(E/A),
+ * R_N = A t_n(E/A) if A >= 2 else 0, beta = Z^2/A beta_p(E/A); values are
+ * linear in E between nodes and clamped outside.  2 <= n <= 1024.  Copied.
+ * Errors: CRP_EINVAL. */
+crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e_nodes_eV,
+                          const double* t_pi_per_m, const double* t_n_per_m,
+                          const double* beta_p_per_m);
+
+/* Appends n candidates (all-or-nothing) to the pending queue: id (unique per
+ * context, the caller's contract), 1 <= Z <= A <= 255, E > 0 (eV), pos [n][3]
+ * (m), dir [n][3] with | |dir| - 1 | <= 1e-12, lmax > 0 (m, trajectory
+ * length limit); values finite; |pos| + lmax < 2^30 grid cells.  Pointers are
+ * host memory (on_device = 0) or device memory (on_device = 1).  Injected
+ * candidates start with L = 0, step h_min, event count 0, lineage 0.
+ * Errors: CRP_EINVAL (first bad index in crp_last_error; only checked for
+ * host input), CRP_EQUEUE (capacity), CRP_ESTATE (no grid yet). */
+crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t* A,
+                      const int32_t* Z, const double* E_eV, const double* pos_m,
+                      const double* dir, const double* lmax_m, int32_t on_device);
+
+/* Propagates every pending candidate, and every secondary spawned meanwhile,
+ * until it stops or has run max_cycles cycles in this call (max_cycles <= 0:
+ * no limit).  Runs on the context stream and returns after it completes.
+ * Returns CRP_INCOMPLETE if candidates remain pending (call again to
+ * continue; the result is identical to an uninterrupted run).
+ * Errors: CRP_ESTATE (no field or tables), CRP_EQUEUE (secondaries dropped
+ * for lack of queue capacity), CRP_EDEVICE. */
+crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles);
+
+/* Copies up to cap finished records into out and removes them from the
+ * library; *n_out receives the count.  Order is unspecified: records are keyed
+ * by (id, lineage).  Returns CRP_EOVERFLOW (informational) if more remain. */
+crp_status crp_read_finished(crp_ctx* ctx, int64_t cap, const crp_finished_soa* out,
+                             int64_t* n_out);
+
+/* Same for neutral records, keyed by (id, lineage, m). */
+crp_status crp_read_neutral(crp_ctx* ctx, int64_t cap, const crp_neutral_soa* out,
+                            int64_t* n_out);
+
+/* Copies up to cap pending (interrupted) candidates as records with status
+ * CRP_ACTIVE, without removing them. */
+crp_status crp_peek_pending(crp_ctx* ctx, int64_t cap, const crp_finished_soa* out,
+                            int64_t* n_out);
+
+crp_status crp_counts(crp_ctx* ctx, crp_counters* out);
+crp_status crp_reset_counters(crp_ctx* ctx);
+
+/* Field at n positions pos [n][3] (m) into B [n][3] (T), with the stepper's
+ * own interpolation: mode CRP_FP64 (FP64 weights), CRP_MIX (FP32 weights and
+ * sums) or CRP_FIELD_NEURAL + 16 (the trained network).  Pointers are host
+ * (on_device = 0) or device memory.  Errors: CRP_ESTATE, CRP_EINVAL. */
+crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* B_T,
+                          int32_t mode, int32_t on_device);
+
+/* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
+ * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra
+ * device memory (built on first use). */
+crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);
+crp_status crp_get_launch(crp_ctx* ctx, crp_launch* launch);
+
+/* Autotuner: times `trials` candidate launch shapes on a copy of the pending
+ * queue (restored after each trial, so the pending work is unchanged), keeps
+ * the fastest in the context and appends it to cache_path (NULL: no file)
+ * under a key of (device name, grid shape, dtype, precision, field mode).
+ * best_rate: accepted steps per second of the chosen shape. */
+crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path,
+                    crp_launch* best, double* best_rate);
+
+/* Timing of the last crp_propagate: summed duration of its propagation
+ * kernel launches (HIP events on the context stream), ms, and launch count. */
+crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches);
+
+/* Checkpoint: pending candidates, undrained records and counters.  The blob
+ * is allocated by the library and released with crp_free. */
+crp_status crp_snapshot(crp_ctx* ctx, void** blob, size_t* bytes);
+crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes);
+void crp_free(void* p);
+
+/* ---- neural field (learned stand-in for the trilinear gather) ----------
+ * Network: xhat = frac((x - origin) / (n * spacing)); gamma = [cos 2pi F xhat,
+ * sin 2pi F xhat] (F: 64 x 3 integers); four 128-wide ReLU layers; linear 3
+ * outputs; B = b_scale * out.  Weights are FP32 masters, used as bfloat16 in
+ * the matrix products with FP32 accumulation.  Parameter order in flat
+ * buffers: W1 [128][128], b1 [128], ..., W4, b4, W5 [3][128], b5 [3]. */
+#define CRP_NF_NPARAM 66435
+crp_status crp_nf_init(crp_ctx* ctx, const int32_t* freq_64x3, const float* params,
+                       double b_scale_T);
+crp_status crp_nf_get_params(crp_ctx* ctx, float* params);
+/* Forward and MSE gradient at n points (host arrays): target in units of
+ * b_scale; writes out [n][3] and grad [CRP_NF_NPARAM]; loss = mean |out - t|^2. */
+crp_status crp_nf_loss_grad(crp_ctx* ctx, int64_t n, const double* pos_m, const float* target,
+                            float* out, float* grad, double* loss);
+/* Trains on points drawn uniformly in one period of the grid with targets from
+ * the grid's trilinear field: steps Adam updates (beta1 0.9, beta2 0.999,
+ * eps 1e-8) of batch points, cosine learning rate lr0 -> lr1.  loss_out[steps]
+ * (nullable) receives each step's loss. */
+crp_status crp_nf_train(crp_ctx* ctx, int64_t steps, int64_t batch, double lr0, double lr1,
+                        uint64_t seed, float* loss_out);
+
+const char* crp_last_error(const crp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRP_H */

@@ -1,0 +1,410 @@
+"""Thin ctypes binding of libcrp.so (include/crp.h): argument marshalling only.
+
+Every step of the propagation runs in the HIP kernels of libcrp; this module
+converts numpy arrays / torch tensors into pointers and status codes into
+exceptions.  PyTorch is used only for device memory and the HIP stream.  If the
+library is missing the import fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrp.so")
+
+OK, INCOMPLETE, EOVERFLOW = 0, 1, 2
+STATUS_NAMES = {0: "CRP_OK", 1: "CRP_INCOMPLETE", 2: "CRP_EOVERFLOW", -1: "CRP_EINVAL",
+                -2: "CRP_EDEVICE", -3: "CRP_ENOMEM", -4: "CRP_ESTATE", -5: "CRP_EQUEUE"}
+FP64, MIX = 0, 1
+FIELD_GRID, FIELD_NEURAL = 0, 1
+EVAL_NEURAL = 16 + FIELD_NEURAL
+F32, F64 = 0, 1
+LAYOUT_LINEAR, LAYOUT_CORNER = 0, 1
+ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR = 0, 1, 2, 3
+NF_NPARAM = 66435
+
+EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_tables", "crp_inject",
+           "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_peek_pending",
+           "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_set_launch",
+           "crp_get_launch", "crp_tune", "crp_last_timing", "crp_snapshot", "crp_restore",
+           "crp_free", "crp_nf_init", "crp_nf_get_params", "crp_nf_loss_grad", "crp_nf_train",
+           "crp_last_error")
+
+
+class CrpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("field_mode", C.c_int32), ("renormalize", C.c_int32),
+                ("device", C.c_int32), ("tol", C.c_double), ("hmin", C.c_double),
+                ("hmax", C.c_double), ("eps_loss", C.c_double), ("kappa_pi", C.c_double),
+                ("e_floor", C.c_double), ("obs_center", C.c_double * 3),
+                ("obs_radius", C.c_double), ("seed", C.c_uint64),
+                ("queue_capacity", C.c_int64), ("neutral_capacity", C.c_int64)]
+
+
+class Launch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("quantum", C.c_int32),
+                ("layout", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.POINTER
+
+
+class FinishedSoA(C.Structure):
+    _fields_ = [(k, _P(C.c_uint32)) for k in ("id", "lineage", "m", "nsteps", "nrej")] + \
+               [(k, _P(C.c_int32)) for k in ("status", "A", "Z")] + \
+               [(k, _P(C.c_double)) for k in ("E", "x", "u", "L", "u0", "E0")]
+
+
+class NeutralSoA(C.Structure):
+    _fields_ = [("id", _P(C.c_uint32)), ("lineage", _P(C.c_uint32)), ("m", _P(C.c_uint32)),
+                ("chan", _P(C.c_int32)), ("E", _P(C.c_double)), ("x", _P(C.c_double)),
+                ("u", _P(C.c_double))]
+
+
+COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts",
+                "rejects", "forced", "events", "null_events", "inter_pi", "inter_n",
+                "charged_sec", "neutral_sec", "queue_dropped", "neutral_dropped", "pending",
+                "finished_unread", "neutral_unread")
+
+
+class Counters(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in COUNT_FIELDS]
+
+
+_lib = None
+
+
+def load():
+    """Loads libcrp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_1307_2643_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    sig = {
+        "crp_create": ([_P(Config), vp, _P(vp)], C.c_int),
+        "crp_destroy": ([vp], None),
+        "crp_set_field_grid": ([vp, vp, i32, i32, i64, i64, i64, dbl, vp], C.c_int),
+        "crp_set_tables": ([vp, i32, vp, vp, vp, vp], C.c_int),
+        "crp_inject": ([vp, i64, vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
+        "crp_propagate": ([vp, i64], C.c_int),
+        "crp_read_finished": ([vp, i64, _P(FinishedSoA), _P(i64)], C.c_int),
+        "crp_read_neutral": ([vp, i64, _P(NeutralSoA), _P(i64)], C.c_int),
+        "crp_peek_pending": ([vp, i64, _P(FinishedSoA), _P(i64)], C.c_int),
+        "crp_counts": ([vp, _P(Counters)], C.c_int),
+        "crp_reset_counters": ([vp], C.c_int),
+        "crp_eval_field": ([vp, i64, vp, vp, i32, i32], C.c_int),
+        "crp_set_launch": ([vp, _P(Launch)], C.c_int),
+        "crp_get_launch": ([vp, _P(Launch)], C.c_int),
+        "crp_tune": ([vp, i64, C.c_char_p, _P(Launch), _P(dbl)], C.c_int),
+        "crp_last_timing": ([vp, _P(dbl), _P(i64)], C.c_int),
+        "crp_snapshot": ([vp, _P(vp), _P(C.c_size_t)], C.c_int),
+        "crp_restore": ([vp, vp, C.c_size_t], C.c_int),
+        "crp_free": ([vp], None),
+        "crp_nf_init": ([vp, vp, vp, dbl], C.c_int),
+        "crp_nf_get_params": ([vp, vp], C.c_int),
+        "crp_nf_loss_grad": ([vp, i64, vp, vp, vp, vp, _P(dbl)], C.c_int),
+        "crp_nf_train": ([vp, i64, i64, dbl, dbl, C.c_uint64, vp], C.c_int),
+        "crp_last_error": ([vp], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    """Pointer of a numpy array or torch tensor (host or device)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+FIN_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "nsteps": np.uint32,
+              "nrej": np.uint32, "status": np.int32, "A": np.int32, "Z": np.int32,
+              "E": np.float64, "x": np.float64, "u": np.float64, "L": np.float64,
+              "u0": np.float64, "E0": np.float64}
+NEU_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "chan": np.int32,
+              "E": np.float64, "x": np.float64, "u": np.float64}
+VEC3 = ("x", "u", "u0")
+
+
+def _alloc(fields, n):
+    return {k: np.zeros((n, 3) if k in VEC3 else n, dtype=dt) for k, dt in fields.items()}
+
+
+def _fill(struct_cls, arrs):
+    s = struct_cls()
+    for k, t in struct_cls._fields_:
+        setattr(s, k, arrs[k].ctypes.data_as(t))
+    return s
+
+
+@dataclass
+class Params:
+    precision: int = FP64
+    field_mode: int = FIELD_GRID
+    renormalize: int = 1
+    device: int = 0
+    tol: float = 1e-4
+    hmin: float = 3.0856775814913673e20      # 10 kpc
+    hmax: float = 3.0856775814913673e22      # 1 Mpc
+    eps_loss: float = 0.1
+    kappa_pi: float = 0.2
+    e_floor: float = 1e16
+    obs_center: tuple = (0.0, 0.0, 0.0)
+    obs_radius: float = 0.0
+    seed: int = 1
+    queue_capacity: int = 1 << 16
+    neutral_capacity: int = 1 << 16
+
+
+class Context:
+    """One libcrp context.  `stream`: a torch.cuda.Stream (or None: default)."""
+
+    def __init__(self, params: Params, stream=None):
+        self.L = load()
+        c = Config()
+        for k, _ in Config._fields_:
+            v = getattr(params, k)
+            if k == "obs_center":
+                for a in range(3):
+                    c.obs_center[a] = float(v[a])
+            else:
+                setattr(c, k, v)
+        self.params = params
+        h = C.c_void_p()
+        sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+        self._keep = []
+        st = self.L.crp_create(C.byref(c), sp, C.byref(h))
+        if st != OK:
+            raise CrpError(st, "crp_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.crp_destroy(self.h)
+            self.h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st, ok=(OK,)):
+        if st not in ok:
+            msg = self.L.crp_last_error(self.h)
+            raise CrpError(st, msg.decode() if msg else "")
+        return st
+
+    # -- inputs -------------------------------------------------------------
+    def set_field_grid(self, grid, spacing, origin=(0.0, 0.0, 0.0)):
+        """grid: [nx][ny][nz][3] float32/float64 numpy array (copied) or a
+        contiguous torch device tensor (used in place; kept alive here)."""
+        on_dev = hasattr(grid, "is_cuda") and grid.is_cuda
+        if on_dev:
+            import torch
+            assert grid.is_contiguous() and grid.dim() == 4 and grid.shape[3] == 3
+            dt = F32 if grid.dtype == torch.float32 else F64
+            self._keep = [grid]
+        else:
+            grid = np.ascontiguousarray(grid)
+            assert grid.ndim == 4 and grid.shape[3] == 3
+            dt = F32 if grid.dtype == np.float32 else F64
+        org = (C.c_double * 3)(*[float(v) for v in origin])
+        self._check(self.L.crp_set_field_grid(self.h, _ptr(grid), dt, int(on_dev),
+                                              grid.shape[0], grid.shape[1], grid.shape[2],
+                                              float(spacing), org))
+
+    def set_tables(self, tables):
+        arrs = [np.ascontiguousarray(a, np.float64) for a in
+                (tables.e_nodes, tables.t_pi, tables.t_n, tables.beta_p)]
+        self._check(self.L.crp_set_tables(self.h, len(arrs[0]), *[_ptr(a) for a in arrs]))
+
+    def inject(self, inj=None, *, id=None, A=None, Z=None, E=None, pos=None, dir=None,
+               lmax=None, on_device=False):
+        if inj is not None:
+            id, A, Z, E, pos, dir, lmax = inj.id, inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax
+        if on_device:
+            arrs = [id, A, Z, E, pos, dir, lmax]
+        else:
+            arrs = [np.ascontiguousarray(id, np.uint32), np.ascontiguousarray(A, np.int32),
+                    np.ascontiguousarray(Z, np.int32), np.ascontiguousarray(E, np.float64),
+                    np.ascontiguousarray(pos, np.float64), np.ascontiguousarray(dir, np.float64),
+                    np.ascontiguousarray(lmax, np.float64)]
+        n = int(arrs[0].shape[0])
+        self._check(self.L.crp_inject(self.h, n, *[_ptr(a) for a in arrs], int(on_device)))
+
+    # -- the hot path ---------------------------------------------------------
+    def propagate(self, max_cycles=0):
+        """Returns True when complete, False when candidates remain pending."""
+        st = self._check(self.L.crp_propagate(self.h, int(max_cycles)), ok=(OK, INCOMPLETE))
+        return st == OK
+
+    # -- outputs ------------------------------------------------------------
+    def counts(self):
+        c = Counters()
+        self._check(self.L.crp_counts(self.h, C.byref(c)))
+        return {k: getattr(c, k) for k in COUNT_FIELDS}
+
+    def reset_counters(self):
+        self._check(self.L.crp_reset_counters(self.h))
+
+    def read_finished(self, cap=None):
+        cap = self.counts()["finished_unread"] if cap is None else cap
+        arrs = _alloc(FIN_FIELDS, cap)
+        s = _fill(FinishedSoA, arrs)
+        n = C.c_int64(0)
+        self._check(self.L.crp_read_finished(self.h, cap, C.byref(s), C.byref(n)),
+                    ok=(OK, EOVERFLOW))
+        return {k: v[:n.value] for k, v in arrs.items()}
+
+    def discard_finished(self):
+        n = C.c_int64(0)
+        self._check(self.L.crp_read_finished(self.h, 1 << 62, None, C.byref(n)),
+                    ok=(OK, EOVERFLOW))
+        m = C.c_int64(0)
+        self._check(self.L.crp_read_neutral(self.h, 1 << 62, None, C.byref(m)),
+                    ok=(OK, EOVERFLOW))
+        return n.value, m.value
+
+    def read_neutral(self, cap=None):
+        cap = self.counts()["neutral_unread"] if cap is None else cap
+        arrs = _alloc(NEU_FIELDS, cap)
+        s = _fill(NeutralSoA, arrs)
+        n = C.c_int64(0)
+        self._check(self.L.crp_read_neutral(self.h, cap, C.byref(s), C.byref(n)),
+                    ok=(OK, EOVERFLOW))
+        return {k: v[:n.value] for k, v in arrs.items()}
+
+    def peek_pending(self, cap=None):
+        cap = self.counts()["pending"] if cap is None else cap
+        arrs = _alloc(FIN_FIELDS, cap)
+        s = _fill(FinishedSoA, arrs)
+        n = C.c_int64(0)
+        self._check(self.L.crp_peek_pending(self.h, cap, C.byref(s), C.byref(n)))
+        return {k: v[:n.value] for k, v in arrs.items()}
+
+    def eval_field(self, pos, mode=FP64):
+        on_dev = hasattr(pos, "is_cuda") and pos.is_cuda
+        if on_dev:
+            import torch
+            out = torch.empty_like(pos)
+        else:
+            pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+            out = np.empty_like(pos)
+        self._check(self.L.crp_eval_field(self.h, pos.shape[0], _ptr(pos), _ptr(out), mode,
+                                          int(on_dev)))
+        return out
+
+    # -- launch shape / tuning / timing ---------------------------------------
+    def set_launch(self, block=256, blocks_per_cu=4, quantum=4, layout=LAYOUT_LINEAR):
+        lch = Launch(block, blocks_per_cu, quantum, layout)
+        self._check(self.L.crp_set_launch(self.h, C.byref(lch)))
+
+    def get_launch(self):
+        lch = Launch()
+        self._check(self.L.crp_get_launch(self.h, C.byref(lch)))
+        return lch.as_dict()
+
+    def tune(self, max_cycles=64, cache_path=None):
+        best = Launch()
+        rate = C.c_double(0)
+        cp = cache_path.encode() if cache_path else None
+        self._check(self.L.crp_tune(self.h, int(max_cycles), cp, C.byref(best), C.byref(rate)))
+        return best.as_dict(), rate.value
+
+    def last_timing(self):
+        ms = C.c_double(0)
+        n = C.c_int64(0)
+        self._check(self.L.crp_last_timing(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    # -- checkpoint -----------------------------------------------------------
+    def snapshot(self) -> bytes:
+        p = C.c_void_p()
+        n = C.c_size_t(0)
+        self._check(self.L.crp_snapshot(self.h, C.byref(p), C.byref(n)))
+        try:
+            return C.string_at(p, n.value)
+        finally:
+            self.L.crp_free(p)
+
+    def restore(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._check(self.L.crp_restore(self.h, buf, len(blob)))
+
+    # -- neural field ---------------------------------------------------------
+    def nf_init(self, freq, params, b_scale):
+        f = np.ascontiguousarray(freq, np.int32)
+        p = np.ascontiguousarray(params, np.float32)
+        assert f.shape == (64, 3) and p.shape == (NF_NPARAM,)
+        self._check(self.L.crp_nf_init(self.h, _ptr(f), _ptr(p), float(b_scale)))
+
+    def nf_get_params(self):
+        p = np.empty(NF_NPARAM, np.float32)
+        self._check(self.L.crp_nf_get_params(self.h, _ptr(p)))
+        return p
+
+    def nf_loss_grad(self, pos, target):
+        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+        t = np.ascontiguousarray(target, np.float32).reshape(-1, 3)
+        out = np.empty(t.shape, np.float32)
+        g = np.empty(NF_NPARAM, np.float32)
+        loss = C.c_double(0)
+        self._check(self.L.crp_nf_loss_grad(self.h, pos.shape[0], _ptr(pos), _ptr(t), _ptr(out),
+                                            _ptr(g), C.byref(loss)))
+        return out, g, loss.value
+
+    def nf_train(self, steps, batch, lr0, lr1, seed):
+        losses = np.empty(max(int(steps), 1), np.float32)
+        self._check(self.L.crp_nf_train(self.h, int(steps), int(batch), float(lr0), float(lr1),
+                                        int(seed), _ptr(losses)))
+        return losses[:steps]
+
+
+def params_for(workload, precision=FP64, **kw):
+    """Params matching a workload description (see crp_inputs.Workload)."""
+    p = Params(precision=precision, tol=workload.tol, hmin=workload.hmin_m,
+               hmax=workload.hmax_m, obs_center=workload.observer,
+               obs_radius=workload.obs_radius_m, seed=workload.philox_seed)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def sort_finished(fin):
+    order = np.lexsort((fin["lineage"], fin["id"]))
+    return {k: v[order] for k, v in fin.items()}
+
+
+def sort_neutral(neu):
+    order = np.lexsort((neu["m"], neu["lineage"], neu["id"]))
+    return {k: v[order] for k, v in neu.items()}

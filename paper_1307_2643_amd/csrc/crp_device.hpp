@@ -1,0 +1,491 @@
+// Device-side building blocks of the propagation kernels (gfx950, wave64).
+//
+// Arithmetic contract (both precision forms): this file is compiled with
+// -ffp-contract=off and without fast-math, so each + - * / sqrt below is one
+// correctly rounded IEEE operation in the order written; sums are evaluated
+// left to right in index order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crp {
+
+constexpr double kC = 299792458.0;   // m/s
+
+// -------------------------------------------------------------------------
+// Cash-Karp embedded Runge-Kutta 4(5) tableau (Cash & Karp, ACM TOMS 16,
+// 1990).  Each rational coefficient is rounded once to FP64.
+// -------------------------------------------------------------------------
+struct CK {
+    static constexpr double a[6][5] = {
+        {0.0, 0.0, 0.0, 0.0, 0.0},
+        {1.0 / 5.0, 0.0, 0.0, 0.0, 0.0},
+        {3.0 / 40.0, 9.0 / 40.0, 0.0, 0.0, 0.0},
+        {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0.0, 0.0},
+        {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0.0},
+        {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+    // 5th-order weights of stages 1, 3, 4, 6 (stages 2 and 5 have weight 0)
+    static constexpr double b0 = 37.0 / 378.0, b2 = 250.0 / 621.0, b3 = 125.0 / 594.0,
+                            b5 = 512.0 / 1771.0;
+    // 5th minus embedded 4th order weights of stages 1, 3, 4, 5, 6
+    static constexpr double e0 = -277.0 / 64512.0, e2 = 6925.0 / 370944.0,
+                            e3 = -6925.0 / 202752.0, e4 = -277.0 / 14336.0, e5 = 277.0 / 7084.0;
+};
+
+// -------------------------------------------------------------------------
+// Philox4x64-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
+// -------------------------------------------------------------------------
+struct U64x4 {
+    uint64_t w[4];
+};
+
+__device__ inline U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                      uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+        const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0;
+        const uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    return U64x4{{c0, c1, c2, c3}};
+}
+
+// Draw for event number m of candidate (id, lineage): key (seed, id<<32|lineage).
+__device__ inline U64x4 event_draw(uint64_t seed, uint32_t id, uint32_t lineage, uint32_t m)
+{
+    return philox4x64_10((uint64_t)m, 0, 0, 0, seed, ((uint64_t)id << 32) | (uint64_t)lineage);
+}
+
+// Optical depth to the next interaction from one 64-bit word: -ln U with
+// U = ((w >> 11) + 1) 2^-53 in (0, 1], rounded to a multiple of 2^-24 (so a
+// last-ulp difference between log implementations almost never shows) and at
+// least 2^-24.
+__device__ inline double optical_depth(uint64_t w)
+{
+    const double U = (double)((w >> 11) + 1) * 0x1p-53;
+    const double t = -log(U);
+    const double q = floor(t * 16777216.0 + 0.5) * 0x1p-24;
+    return q < 0x1p-24 ? 0x1p-24 : q;
+}
+
+// Uniform [0, 1) from one word: (w >> 11) 2^-53.
+__device__ inline double unit_uniform(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
+
+// -------------------------------------------------------------------------
+// Step-size factor k / 1024 with k = floor(1024 * 0.95 * r^(-1/5)) defined
+// exactly as the largest integer with k^5 r <= (0.95 * 1024)^5 in FP64 (fixed
+// order); pow() only supplies the first guess.  k is capped at 5121.
+// -------------------------------------------------------------------------
+__device__ inline bool ctrl_ok(int k, double r)
+{
+    const double c1 = 0.95 * 1024.0;
+    const double c5 = (((c1 * c1) * c1) * c1) * c1;
+    const double kd = (double)k;
+    const double k5 = (((kd * kd) * kd) * kd) * kd;
+    return k5 * r <= c5;
+}
+
+__device__ inline int ctrl_k(double r)
+{
+    const int KMAX = 5121;
+    const double g = (0.95 * 1024.0) * pow(r, -0.2);
+    int k = 0;
+    if (g >= 1.0)   // also false for NaN
+        k = g > (double)KMAX ? KMAX : (int)floor(g);
+    while (k < KMAX && ctrl_ok(k + 1, r))
+        ++k;
+    while (k > 0 && !ctrl_ok(k, r))
+        --k;
+    return k;
+}
+
+// -------------------------------------------------------------------------
+// Interaction tables (per nucleon at eps = E/A), staged in LDS.
+// -------------------------------------------------------------------------
+struct TableView {
+    const double* e;     // LDS: nodes
+    const double* v[3];  // LDS: t_pi, t_n, beta_p
+    int n;
+    double lg0, scale;   // log10(e[0]), (n - 1) / (log10 e[n-1] - log10 e[0])
+};
+
+__device__ inline double table_value(const TableView& T, int which, double eps)
+{
+    const double* e = T.e;
+    const double* v = T.v[which];
+    const int n = T.n;
+    if (eps <= e[0])
+        return v[0];
+    if (eps >= e[n - 1])
+        return v[n - 1];
+    // first guess from the log-spaced layout, then exact correction against
+    // the node values: afterwards e[j] <= eps < e[j+1]
+    const double gs = (log10(eps) - T.lg0) * T.scale;
+    int j = 0;
+    if (gs > 0.0)   // also false for NaN
+        j = gs > (double)(n - 2) ? n - 2 : (int)gs;
+    while (j < n - 2 && e[j + 1] <= eps)
+        ++j;
+    while (j > 0 && e[j] > eps)
+        --j;
+    const double t = (eps - e[j]) / (e[j + 1] - e[j]);
+    return v[j] + t * (v[j + 1] - v[j]);
+}
+
+struct Rates {
+    double rpi, rn, r, beta;
+};
+
+// Species scaling: rates A t(E/A) (nucleon channel only for A >= 2),
+// continuous loss Z^2/A beta_p(E/A).
+__device__ inline Rates species_rates(const TableView& T, int A, int Z, double E)
+{
+    const double eps = E / (double)A;
+    Rates R;
+    R.rpi = (double)A * table_value(T, 0, eps);
+    R.rn = A >= 2 ? (double)A * table_value(T, 1, eps) : 0.0;
+    R.r = R.rpi + R.rn;
+    const double zz = (double)(Z * Z) / (double)A;
+    R.beta = zz * table_value(T, 2, eps);
+    return R;
+}
+
+// -------------------------------------------------------------------------
+// Field grid: periodic trilinear interpolation on a vertex grid.
+// -------------------------------------------------------------------------
+struct GridView {
+    const void* data;       // linear [nx][ny][nz][3] (float or double)
+    const float* corner;    // corner records [nx][ny][nz][32] (float) or null
+    int n[3];
+    int mask[3];            // n-1 if n is a power of two, else -1
+    int64_t stride[3];      // elements: ny*nz*3, nz*3, 3
+    double inv_spacing;     // 1 / spacing, rounded once
+    double origin[3];
+    int dtype;              // 0 float, 1 double
+};
+
+struct Cell {
+    int i0[3], i1[3];
+    double t[3];
+};
+
+__device__ inline int wrap_index(int i, int n, int mask)
+{
+    if (mask >= 0)
+        return i & mask;
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ inline Cell locate(const GridView& g, const double p[3])
+{
+    Cell c;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = (p[a] - g.origin[a]) * g.inv_spacing;
+        const double fl = floor(f);
+        const int i = (int)fl;
+        const int i0 = wrap_index(i, g.n[a], g.mask[a]);
+        c.i0[a] = i0;
+        c.i1[a] = (i0 + 1 == g.n[a]) ? 0 : i0 + 1;
+        c.t[a] = f - fl;
+    }
+    return c;
+}
+
+// The 8 corner vectors of a cell in the order c = dx + 2 dy + 4 dz.
+template <class GT>
+__device__ inline void gather_linear(const GridView& g, const Cell& c, GT v[8][3])
+{
+    const GT* G = (const GT*)g.data;
+    const int64_t ox[2] = {(int64_t)c.i0[0] * g.stride[0], (int64_t)c.i1[0] * g.stride[0]};
+    const int64_t oy[2] = {(int64_t)c.i0[1] * g.stride[1], (int64_t)c.i1[1] * g.stride[1]};
+    const int64_t oz[2] = {(int64_t)c.i0[2] * 3, (int64_t)c.i1[2] * 3};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const GT* p = G + ox[k & 1] + oy[(k >> 1) & 1] + oz[(k >> 2) & 1];
+        v[k][0] = p[0];
+        v[k][1] = p[1];
+        v[k][2] = p[2];
+    }
+}
+
+// Corner-replicated layout: one 128-byte record per cell holds the 8 corner
+// vectors (24 floats) followed by 8 pad floats.
+__device__ inline void gather_corner(const GridView& g, const Cell& c, float v[8][3])
+{
+    const int64_t cell = ((int64_t)c.i0[0] * g.n[1] + c.i0[1]) * g.n[2] + c.i0[2];
+    const float4* rec = (const float4*)(g.corner + cell * 32);
+    float f[24];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const float4 w = rec[q];
+        f[4 * q + 0] = w.x;
+        f[4 * q + 1] = w.y;
+        f[4 * q + 2] = w.z;
+        f[4 * q + 3] = w.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k][0] = f[3 * k + 0];
+        v[k][1] = f[3 * k + 1];
+        v[k][2] = f[3 * k + 2];
+    }
+}
+
+// FP64 weights and sums: w0 = 1 - t, w1 = t; weight (wx * wy) * wz.
+template <class GT>
+__device__ inline void interp_fp64(const double t[3], const GT v[8][3], double B[3])
+{
+    const double wx[2] = {1.0 - t[0], t[0]};
+    const double wy[2] = {1.0 - t[1], t[1]};
+    const double wz[2] = {1.0 - t[2], t[2]};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double w = (wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double term = w * (double)v[k][q];
+            B[q] = k == 0 ? term : B[q] + term;
+        }
+    }
+}
+
+// FP32 weights and sums (precision form); t is rounded to FP32 first.
+template <class GT>
+__device__ inline void interp_fp32(const double t[3], const GT v[8][3], float B[3])
+{
+    const float tx = (float)t[0], ty = (float)t[1], tz = (float)t[2];
+    const float wx[2] = {1.0f - tx, tx};
+    const float wy[2] = {1.0f - ty, ty};
+    const float wz[2] = {1.0f - tz, tz};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float w = (wx[k & 1] * wy[(k >> 1) & 1]) * wz[(k >> 2) & 1];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float term = w * (float)v[k][q];
+            B[q] = k == 0 ? term : B[q] + term;
+        }
+    }
+}
+
+// Field sources used by the stepper.  LAYOUT: 0 linear, 1 corner records.
+template <class GT, int LAYOUT>
+struct GridField {
+    GridView g;
+    __device__ inline void fp64(const double p[3], double B[3]) const
+    {
+        const Cell c = locate(g, p);
+        if constexpr (LAYOUT == 1) {
+            float v[8][3];
+            gather_corner(g, c, v);
+            interp_fp64(c.t, v, B);
+        } else {
+            GT v[8][3];
+            gather_linear<GT>(g, c, v);
+            interp_fp64(c.t, v, B);
+        }
+    }
+    __device__ inline void fp32(const double p[3], float B[3]) const
+    {
+        const Cell c = locate(g, p);
+        if constexpr (LAYOUT == 1) {
+            float v[8][3];
+            gather_corner(g, c, v);
+            interp_fp32(c.t, v, B);
+        } else {
+            GT v[8][3];
+            gather_linear<GT>(g, c, v);
+            float vf[8][3];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    vf[k][q] = (float)v[k][q];
+            interp_fp32(c.t, vf, B);
+        }
+    }
+};
+
+// -------------------------------------------------------------------------
+// One Cash-Karp attempt.  FP64 form: state y = (x, u), derivative
+// K = (u, kappa u x B(x)), kappa = Z c / E.  Returns the error estimate
+// h |sum e_i K_i^u| and the 5th-order state (local extrapolation).
+// -------------------------------------------------------------------------
+__device__ inline void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ inline double dot3(const double a[3], const double b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+__device__ inline void cross3f(const float a[3], const float b[3], float c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ inline float dot3f(const float a[3], const float b[3])
+{
+    return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+template <class F>
+__device__ inline void deriv_fp64(const F& field, double kappa, const double y[6], double k[6])
+{
+    double B[3], c[3];
+    field.fp64(y, B);
+    cross3(y + 3, B, c);
+    k[0] = y[3];
+    k[1] = y[4];
+    k[2] = y[5];
+    k[3] = kappa * c[0];
+    k[4] = kappa * c[1];
+    k[5] = kappa * c[2];
+}
+
+template <class F>
+__device__ inline double ck_attempt_fp64(const F& field, double kappa, const double y[6],
+                                         double h, double y5[6])
+{
+    double K[6][6];
+    deriv_fp64(field, kappa, y, K[0]);
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+        double ys[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            double s = CK::a[i][0] * K[0][q];
+#pragma unroll
+            for (int j = 1; j < i; ++j)
+                s = s + CK::a[i][j] * K[j][q];
+            ys[q] = y[q] + h * s;
+        }
+        deriv_fp64(field, kappa, ys, K[i]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        double s = CK::b0 * K[0][q];
+        s = s + CK::b2 * K[2][q];
+        s = s + CK::b3 * K[3][q];
+        s = s + CK::b5 * K[5][q];
+        y5[q] = y[q] + h * s;
+    }
+    double e[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double s = CK::e0 * K[0][3 + q];
+        s = s + CK::e2 * K[2][3 + q];
+        s = s + CK::e3 * K[3][3 + q];
+        s = s + CK::e4 * K[4][3 + q];
+        s = s + CK::e5 * K[5][3 + q];
+        e[q] = s;
+    }
+    return h * sqrt(dot3(e, e));
+}
+
+// Precision form: stage increments G_i = (h u_i, (h kappa) u_i x B(x_i)) in
+// FP32 with h and h*kappa formed in FP64 and rounded once; stage positions
+// are the FP64 position plus the FP32 offset; the error is |sum e_i G_i^u|.
+template <class F>
+__device__ inline void incr_fp32(const F& field, float hf, float hk, const double x[3],
+                                 const float u[3], float G[6])
+{
+    float B[3], c[3];
+    field.fp32(x, B);
+    cross3f(u, B, c);
+    G[0] = hf * u[0];
+    G[1] = hf * u[1];
+    G[2] = hf * u[2];
+    G[3] = hk * c[0];
+    G[4] = hk * c[1];
+    G[5] = hk * c[2];
+}
+
+template <class F>
+__device__ inline double ck_attempt_mix(const F& field, double kappa, const double x[3],
+                                        const double ud[3], double h, double x5[3],
+                                        double u5[3])
+{
+    const float hf = (float)h;
+    const float hk = (float)(h * kappa);
+    const float u[3] = {(float)ud[0], (float)ud[1], (float)ud[2]};
+    float G[6][6];
+    incr_fp32(field, hf, hk, x, u, G[0]);
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+        float s[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float acc = (float)CK::a[i][0] * G[0][q];
+#pragma unroll
+            for (int j = 1; j < i; ++j)
+                acc = acc + (float)CK::a[i][j] * G[j][q];
+            s[q] = acc;
+        }
+        double xs[3];
+        float us[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            xs[q] = x[q] + (double)s[q];
+            us[q] = u[q] + s[3 + q];
+        }
+        incr_fp32(field, hf, hk, xs, us, G[i]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        float s = (float)CK::b0 * G[0][q];
+        s = s + (float)CK::b2 * G[2][q];
+        s = s + (float)CK::b3 * G[3][q];
+        s = s + (float)CK::b5 * G[5][q];
+        if (q < 3)
+            x5[q] = x[q] + (double)s;
+        else
+            u5[q - 3] = (double)(u[q - 3] + s);
+    }
+    float e[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        float s = (float)CK::e0 * G[0][3 + q];
+        s = s + (float)CK::e2 * G[2][3 + q];
+        s = s + (float)CK::e3 * G[3][3 + q];
+        s = s + (float)CK::e4 * G[4][3 + q];
+        s = s + (float)CK::e5 * G[5][3 + q];
+        e[q] = s;
+    }
+    return (double)sqrtf(dot3f(e, e));
+}
+
+// -------------------------------------------------------------------------
+// Wave64 helpers.
+// -------------------------------------------------------------------------
+__device__ inline uint64_t wave_ballot(bool p) { return __ballot(p); }
+
+// number of set bits of mask in lanes below this one
+__device__ inline int lanes_below(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & 63u); }
+
+}  // namespace crp

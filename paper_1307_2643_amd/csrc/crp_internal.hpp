@@ -1,0 +1,81 @@
+// Internal layout of the device buffers and kernel parameter blocks shared by
+// the host runtime and the kernels of libcrp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crp_device.hpp"
+
+namespace crp {
+
+// Candidate queue, structure of arrays (one entry per candidate slot).
+// Vectors are planar: x + q * cap holds component q.
+struct QueueSoA {
+    double *x, *u, *u0;
+    double *E, *L, *Lmax, *hctrl, *tau, *E0;
+    uint32_t *id, *lineage, *m, *nsteps, *nrej;
+    int32_t *A, *Z;
+    uint32_t* ready;     // publication flag of slots written during a run
+    int64_t cap;
+};
+
+struct FinishedSoA {
+    double *x, *u, *u0;  // planar [3][cap]
+    double *E, *L, *E0;
+    uint32_t *id, *lineage, *m, *nsteps, *nrej;
+    int32_t *status, *A, *Z;
+    int64_t cap;
+};
+
+struct NeutralSoA {
+    double *x, *u;       // planar [3][cap]
+    double* E;
+    uint32_t *id, *lineage, *m;
+    int32_t* chan;
+    int64_t cap;
+};
+
+// Device counter block (all 64-bit, updated with device-scope atomics).
+struct DevCounters {
+    unsigned long long head, tail;          // queue claim / append cursors
+    unsigned long long fin_n, neu_n, park_n;
+    unsigned long long steps, attempts, rejects, forced;
+    unsigned long long events, null_events, inter_pi, inter_n;
+    unsigned long long charged_sec, neutral_sec;
+    unsigned long long finished, observed, max_traj, energy_floor;
+    unsigned long long queue_dropped, neutral_dropped;
+    unsigned long long error;               // nonzero: a wait timed out
+};
+
+struct TableParams {
+    const double* e;
+    const double* v[3];
+    int n;
+    double lg0, scale;
+};
+
+struct StepParams {
+    double tol, hmin, hmax, eps_loss, kappa_pi, e_floor;
+    double obs[3], obs_r;
+    uint64_t seed;
+    int renorm;
+};
+
+struct PropParams {
+    QueueSoA q;
+    QueueSoA park;
+    FinishedSoA fin;
+    NeutralSoA neu;
+    DevCounters* cnt;
+    GridView grid;
+    TableParams tab;
+    StepParams sp;
+    int64_t max_cycles;          // <= 0: no limit
+    unsigned long long tail0;    // slots below were written before the launch
+    int quantum;
+};
+
+enum { MODE_FP64 = 0, MODE_MIX = 1 };
+
+}  // namespace crp

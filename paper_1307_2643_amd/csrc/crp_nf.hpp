@@ -1,0 +1,36 @@
+// Neural-field (Fourier-feature MLP) part of libcrp: interface between the
+// host runtime and the neural-field kernels.
+#pragma once
+
+#include <string>
+
+#include "../../include/crp.h"
+#include "crp_internal.hpp"
+
+struct crp_ctx;
+
+namespace crp {
+
+struct NeuralField;
+
+NeuralField* nf_create(hipStream_t s);
+void nf_destroy(NeuralField* nf);
+crp_status nf_load(NeuralField* nf, const int32_t* freq, const float* params, double b_scale,
+                   std::string& err);
+crp_status nf_get(NeuralField* nf, float* params, std::string& err);
+crp_status nf_eval(NeuralField* nf, const GridView& g, int64_t n, const double* dpos, double* dB,
+                   hipStream_t s);
+crp_status nf_loss_grad(NeuralField* nf, const GridView& g, int64_t n, const double* pos,
+                        const float* target, float* out, float* grad, double* loss,
+                        std::string& err);
+crp_status nf_train(NeuralField* nf, const GridView& g, int64_t steps, int64_t batch, double lr0,
+                    double lr1, uint64_t seed, float* loss_out, std::string& err);
+crp_status nf_propagate(NeuralField* nf, crp_ctx* ctx, int64_t max_cycles, DevCounters* dc);
+
+// run bookkeeping shared with the grid path (defined in crp_runtime.hip)
+crp_status ctx_run_params(crp_ctx* ctx, int64_t max_cycles, PropParams* P, int* nb, int* bs,
+                          size_t* lds);
+hipStream_t ctx_stream(crp_ctx* ctx);
+void ctx_set_timing(crp_ctx* ctx, double ms, int64_t launches);
+
+}  // namespace crp

@@ -1,0 +1,1280 @@
+// Host runtime of libcrp: the C-ABI declared in include/crp.h.
+//
+// Owns every device buffer of a context (queue, parked queue, finished and
+// neutral record buffers, counters, tables, optional corner-layout grid),
+// launches the kernels on the context's stream and converts errors into
+// crp_status codes (no exception crosses the ABI).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/crp.h"
+#include "crp_internal.hpp"
+#include "crp_nf.hpp"
+
+namespace crp {
+template <int MODE, class GT, int LAYOUT>
+__global__ void k_propagate(PropParams P);
+template <class GT, int LAYOUT>
+__global__ void k_eval_field(GridView g, int64_t n, const double* pos, double* B, int mode);
+__global__ void k_validate(int64_t n, const uint32_t* id, const int32_t* A, const int32_t* Z,
+                           const double* E, const double* pos, const double* dir,
+                           const double* lmax, double max_extent, unsigned long long* first_bad);
+__global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id,
+                         const int32_t* A, const int32_t* Z, const double* E,
+                         const double* pos, const double* dir, const double* lmax,
+                         uint64_t seed, double hmin, int mix);
+__global__ void k_corner_relayout(GridView g, float* out);
+}  // namespace crp
+
+using namespace crp;
+
+struct crp_ctx {
+    crp_config cfg;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cus = 256;
+    std::string device_name;
+
+    // field grid
+    bool has_grid = false;
+    const void* grid = nullptr;
+    void* grid_owned = nullptr;
+    int grid_dtype = CRP_F64;
+    int64_t gn[3] = {0, 0, 0};
+    double spacing = 0.0;
+    double origin[3] = {0, 0, 0};
+    float* corner = nullptr;
+
+    // tables (device: e, tpi, tn, bp consecutive)
+    bool has_tables = false;
+    double* tab = nullptr;
+    int tab_n = 0;
+    double lg0 = 0.0, lgscale = 0.0;
+
+    // buffers
+    void* qmem[2] = {nullptr, nullptr};
+    QueueSoA q, park;
+    void* fmem = nullptr;
+    FinishedSoA fin;
+    void* nmem = nullptr;
+    NeutralSoA neu;
+    DevCounters* cnt = nullptr;
+    unsigned long long* scratch = nullptr;   // small device scratch (validation)
+
+    int64_t pending = 0;
+    int64_t fin_unread = 0, neu_unread = 0;
+    crp_counters totals;
+
+    crp_launch launch;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double last_ms = 0.0;
+    int64_t last_launches = 0;
+
+    NeuralField* nf = nullptr;
+};
+
+namespace {
+
+crp_status fail(crp_ctx* ctx, crp_status st, const std::string& msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? CRP_ENOMEM : CRP_EDEVICE,           \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+    } while (0)
+
+// Carves a structure of arrays out of one allocation (256-byte aligned pieces).
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+size_t queue_layout(char* base, int64_t cap, QueueSoA* q)
+{
+    Carver c{base};
+    QueueSoA t;
+    t.x = c.take<double>(3 * cap);
+    t.u = c.take<double>(3 * cap);
+    t.u0 = c.take<double>(3 * cap);
+    t.E = c.take<double>(cap);
+    t.L = c.take<double>(cap);
+    t.Lmax = c.take<double>(cap);
+    t.hctrl = c.take<double>(cap);
+    t.tau = c.take<double>(cap);
+    t.E0 = c.take<double>(cap);
+    t.id = c.take<uint32_t>(cap);
+    t.lineage = c.take<uint32_t>(cap);
+    t.m = c.take<uint32_t>(cap);
+    t.nsteps = c.take<uint32_t>(cap);
+    t.nrej = c.take<uint32_t>(cap);
+    t.A = c.take<int32_t>(cap);
+    t.Z = c.take<int32_t>(cap);
+    t.ready = c.take<uint32_t>(cap);
+    t.cap = cap;
+    if (q)
+        *q = t;
+    return c.off;
+}
+
+size_t finished_layout(char* base, int64_t cap, FinishedSoA* f)
+{
+    Carver c{base};
+    FinishedSoA t;
+    t.x = c.take<double>(3 * cap);
+    t.u = c.take<double>(3 * cap);
+    t.u0 = c.take<double>(3 * cap);
+    t.E = c.take<double>(cap);
+    t.L = c.take<double>(cap);
+    t.E0 = c.take<double>(cap);
+    t.id = c.take<uint32_t>(cap);
+    t.lineage = c.take<uint32_t>(cap);
+    t.m = c.take<uint32_t>(cap);
+    t.nsteps = c.take<uint32_t>(cap);
+    t.nrej = c.take<uint32_t>(cap);
+    t.status = c.take<int32_t>(cap);
+    t.A = c.take<int32_t>(cap);
+    t.Z = c.take<int32_t>(cap);
+    t.cap = cap;
+    if (f)
+        *f = t;
+    return c.off;
+}
+
+size_t neutral_layout(char* base, int64_t cap, NeutralSoA* n)
+{
+    Carver c{base};
+    NeutralSoA t;
+    t.x = c.take<double>(3 * cap);
+    t.u = c.take<double>(3 * cap);
+    t.E = c.take<double>(cap);
+    t.id = c.take<uint32_t>(cap);
+    t.lineage = c.take<uint32_t>(cap);
+    t.m = c.take<uint32_t>(cap);
+    t.chan = c.take<int32_t>(cap);
+    t.cap = cap;
+    if (n)
+        *n = t;
+    return c.off;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+GridView make_view(const crp_ctx* ctx)
+{
+    GridView g;
+    g.data = ctx->grid;
+    g.corner = ctx->corner;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = (int)ctx->gn[a];
+        g.mask[a] = is_pow2(ctx->gn[a]) ? (int)(ctx->gn[a] - 1) : -1;
+        g.origin[a] = ctx->origin[a];
+    }
+    g.stride[0] = ctx->gn[1] * ctx->gn[2] * 3;
+    g.stride[1] = ctx->gn[2] * 3;
+    g.stride[2] = 3;
+    g.inv_spacing = 1.0 / ctx->spacing;
+    g.dtype = ctx->grid_dtype == CRP_F32 ? 0 : 1;
+    return g;
+}
+
+int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Copies [start, start+k) of a planar [3][cap] device array into host [k][3].
+hipError_t copy_planar(double* host, const double* dev, int64_t cap, int64_t start, int64_t k,
+                       hipStream_t s)
+{
+    std::vector<double> tmp((size_t)k);
+    for (int a = 0; a < 3; ++a) {
+        hipError_t e = hipMemcpyAsync(tmp.data(), dev + a * cap + start, k * sizeof(double),
+                                      hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess)
+            return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return e;
+        for (int64_t i = 0; i < k; ++i)
+            host[3 * i + a] = tmp[(size_t)i];
+    }
+    return hipSuccess;
+}
+
+template <class T>
+hipError_t copy_d2h(T* host, const T* dev, int64_t k, hipStream_t s)
+{
+    if (k == 0 || host == nullptr)
+        return hipSuccess;
+    return hipMemcpyAsync(host, dev, k * sizeof(T), hipMemcpyDeviceToHost, s);
+}
+
+crp_status ensure_corner(crp_ctx* ctx)
+{
+    if (ctx->corner)
+        return CRP_OK;
+    if (ctx->grid_dtype != CRP_F32)
+        return fail(ctx, CRP_EINVAL, "corner layout needs an FP32 grid");
+    const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
+    HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
+    GridView g = make_view(ctx);
+    k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return CRP_OK;
+}
+
+void free_corner(crp_ctx* ctx)
+{
+    if (ctx->corner) {
+        (void)hipFree(ctx->corner);
+        ctx->corner = nullptr;
+    }
+}
+
+// Launches one propagation run over the pending queue (no host bookkeeping
+// of totals).  On return the device counter block is in *dc.
+crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
+{
+    DevCounters init;
+    std::memset(&init, 0, sizeof init);
+    init.head = 0;
+    init.tail = (unsigned long long)ctx->pending;
+    init.fin_n = (unsigned long long)ctx->fin_unread;
+    init.neu_n = (unsigned long long)ctx->neu_unread;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
+
+    PropParams P;
+    P.q = ctx->q;
+    P.park = ctx->park;
+    P.fin = ctx->fin;
+    P.neu = ctx->neu;
+    P.cnt = ctx->cnt;
+    P.grid = make_view(ctx);
+    P.tab.e = ctx->tab;
+    P.tab.v[0] = ctx->tab + ctx->tab_n;
+    P.tab.v[1] = ctx->tab + 2 * ctx->tab_n;
+    P.tab.v[2] = ctx->tab + 3 * ctx->tab_n;
+    P.tab.n = ctx->tab_n;
+    P.tab.lg0 = ctx->lg0;
+    P.tab.scale = ctx->lgscale;
+    const crp_config& c = ctx->cfg;
+    P.sp.tol = c.tol;
+    P.sp.hmin = c.hmin;
+    P.sp.hmax = c.hmax;
+    P.sp.eps_loss = c.eps_loss;
+    P.sp.kappa_pi = c.kappa_pi;
+    P.sp.e_floor = c.e_floor;
+    for (int a = 0; a < 3; ++a)
+        P.sp.obs[a] = c.obs_center[a];
+    P.sp.obs_r = c.obs_radius;
+    P.sp.seed = c.seed;
+    P.sp.renorm = c.renormalize;
+    P.max_cycles = max_cycles;
+    P.tail0 = (unsigned long long)ctx->pending;
+    P.quantum = ctx->launch.quantum;
+
+    const int layout = ctx->launch.layout;
+    if (layout == CRP_LAYOUT_CORNER) {
+        crp_status st = ensure_corner(ctx);
+        if (st != CRP_OK)
+            return st;
+        P.grid.corner = ctx->corner;
+    }
+    const int bs = ctx->launch.block;
+    const int nb = ctx->num_cus * ctx->launch.blocks_per_cu;
+    const size_t lds = (size_t)4 * ctx->tab_n * sizeof(double);
+    const bool mix = c.precision == CRP_MIX;
+    const bool f32 = ctx->grid_dtype == CRP_F32;
+
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (!mix && !f32)
+        k_propagate<MODE_FP64, double, 0><<<nb, bs, lds, ctx->stream>>>(P);
+    else if (!mix && layout == CRP_LAYOUT_CORNER)
+        k_propagate<MODE_FP64, float, 1><<<nb, bs, lds, ctx->stream>>>(P);
+    else if (!mix)
+        k_propagate<MODE_FP64, float, 0><<<nb, bs, lds, ctx->stream>>>(P);
+    else if (!f32)
+        k_propagate<MODE_MIX, double, 0><<<nb, bs, lds, ctx->stream>>>(P);
+    else if (layout == CRP_LAYOUT_CORNER)
+        k_propagate<MODE_MIX, float, 1><<<nb, bs, lds, ctx->stream>>>(P);
+    else
+        k_propagate<MODE_MIX, float, 0><<<nb, bs, lds, ctx->stream>>>(P);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(dc, ctx->cnt, sizeof *dc, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    ctx->last_ms = ms;
+    ctx->last_launches = 1;
+    if (dc->error)
+        return fail(ctx, CRP_EDEVICE, "propagation kernel: a queue publication wait timed out");
+    return CRP_OK;
+}
+
+// Host bookkeeping after a run: record counts, parked candidates become the
+// pending queue.
+void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
+{
+    ctx->fin_unread = (int64_t)std::min<unsigned long long>(dc.fin_n, ctx->fin.cap);
+    ctx->neu_unread = (int64_t)std::min<unsigned long long>(dc.neu_n, ctx->neu.cap);
+    if (add_totals) {
+        crp_counters& t = ctx->totals;
+        t.finished += dc.finished;
+        t.observed += dc.observed;
+        t.max_traj += dc.max_traj;
+        t.energy_floor += dc.energy_floor;
+        t.steps += dc.steps;
+        t.attempts += dc.attempts;
+        t.rejects += dc.rejects;
+        t.forced += dc.forced;
+        t.events += dc.events;
+        t.null_events += dc.null_events;
+        t.inter_pi += dc.inter_pi;
+        t.inter_n += dc.inter_n;
+        t.charged_sec += dc.charged_sec;
+        t.neutral_sec += dc.neutral_sec;
+        t.queue_dropped += dc.queue_dropped;
+        t.neutral_dropped += dc.neutral_dropped;
+    }
+    ctx->pending = (int64_t)dc.park_n;
+    if (dc.park_n > 0) {
+        std::swap(ctx->q, ctx->park);
+        std::swap(ctx->qmem[0], ctx->qmem[1]);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* crp_last_error(const crp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
+{
+    if (!cfg || !out)
+        return CRP_EINVAL;
+    *out = nullptr;
+    const crp_config& c = *cfg;
+    if (!(c.precision == CRP_FP64 || c.precision == CRP_MIX) ||
+        !(c.field_mode == CRP_FIELD_GRID || c.field_mode == CRP_FIELD_NEURAL) ||
+        !(c.tol > 0) || !(c.hmin > 0) || !(c.hmax >= c.hmin) || !(c.eps_loss > 0) ||
+        !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !(c.obs_radius >= 0) ||
+        c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40))
+        return CRP_EINVAL;
+    crp_ctx* ctx = new (std::nothrow) crp_ctx();
+    if (!ctx)
+        return CRP_ENOMEM;
+    ctx->cfg = c;
+    ctx->stream = (hipStream_t)stream;
+    std::memset(&ctx->totals, 0, sizeof ctx->totals);
+    ctx->launch.block = 256;
+    ctx->launch.blocks_per_cu = 4;
+    ctx->launch.quantum = 4;
+    ctx->launch.layout = CRP_LAYOUT_LINEAR;
+    auto bail = [&](crp_status st, const char* what, hipError_t e) {
+        fprintf(stderr, "crp_create: %s: %s\n", what, hipGetErrorString(e));
+        crp_destroy(ctx);
+        return st;
+    };
+    hipError_t e = hipSetDevice(c.device);
+    if (e != hipSuccess)
+        return bail(CRP_EDEVICE, "hipSetDevice", e);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, c.device);
+    if (e != hipSuccess)
+        return bail(CRP_EDEVICE, "hipGetDeviceProperties", e);
+    ctx->num_cus = prop.multiProcessorCount;
+    ctx->device_name = prop.gcnArchName;
+    const int64_t qc = c.queue_capacity;
+    for (int b = 0; b < 2; ++b) {
+        size_t bytes = queue_layout(nullptr, qc, nullptr);
+        e = hipMalloc(&ctx->qmem[b], bytes);
+        if (e != hipSuccess)
+            return bail(CRP_ENOMEM, "queue allocation", e);
+        queue_layout((char*)ctx->qmem[b], qc, b == 0 ? &ctx->q : &ctx->park);
+        QueueSoA& qq = b == 0 ? ctx->q : ctx->park;
+        e = hipMemset(qq.ready, 0, qc * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return bail(CRP_EDEVICE, "hipMemset", e);
+    }
+    {
+        size_t bytes = finished_layout(nullptr, 2 * qc, nullptr);
+        e = hipMalloc(&ctx->fmem, bytes);
+        if (e != hipSuccess)
+            return bail(CRP_ENOMEM, "finished-record allocation", e);
+        finished_layout((char*)ctx->fmem, 2 * qc, &ctx->fin);
+    }
+    {
+        size_t bytes = neutral_layout(nullptr, c.neutral_capacity, nullptr);
+        e = hipMalloc(&ctx->nmem, bytes);
+        if (e != hipSuccess)
+            return bail(CRP_ENOMEM, "neutral-record allocation", e);
+        neutral_layout((char*)ctx->nmem, c.neutral_capacity, &ctx->neu);
+    }
+    e = hipMalloc((void**)&ctx->cnt, sizeof(DevCounters));
+    if (e != hipSuccess)
+        return bail(CRP_ENOMEM, "counter allocation", e);
+    e = hipMalloc((void**)&ctx->scratch, 64);
+    if (e != hipSuccess)
+        return bail(CRP_ENOMEM, "scratch allocation", e);
+    e = hipEventCreate(&ctx->ev0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&ctx->ev1);
+    if (e != hipSuccess)
+        return bail(CRP_EDEVICE, "hipEventCreate", e);
+    *out = ctx;
+    return CRP_OK;
+}
+
+void crp_destroy(crp_ctx* ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipSetDevice(ctx->cfg.device);
+    if (ctx->stream)
+        (void)hipStreamSynchronize(ctx->stream);
+    else
+        (void)hipDeviceSynchronize();
+    nf_destroy(ctx->nf);
+    for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, (void*)ctx->cnt,
+                    (void*)ctx->scratch, ctx->grid_owned, (void*)ctx->tab, (void*)ctx->corner})
+        if (p)
+            (void)hipFree(p);
+    if (ctx->ev0)
+        (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1)
+        (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int32_t on_device,
+                              int64_t nx, int64_t ny, int64_t nz, double spacing_m,
+                              const double origin_m[3])
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!data || !(dtype == CRP_F32 || dtype == CRP_F64))
+        return fail(ctx, CRP_EINVAL, "grid: null data or bad dtype");
+    const int64_t lim = 1ll << 20;
+    if (nx < 2 || ny < 2 || nz < 2 || nx > lim || ny > lim || nz > lim)
+        return fail(ctx, CRP_EINVAL, "grid: each dimension must be in [2, 2^20]");
+    if (!(spacing_m > 0) || !std::isfinite(spacing_m))
+        return fail(ctx, CRP_EINVAL, "grid: spacing must be positive and finite");
+    double org[3] = {0, 0, 0};
+    if (origin_m)
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(origin_m[a]))
+                return fail(ctx, CRP_EINVAL, "grid: origin must be finite");
+            org[a] = origin_m[a];
+        }
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const size_t bytes = (size_t)nx * ny * nz * 3 * (dtype == CRP_F32 ? 4 : 8);
+    void* owned = nullptr;
+    const void* ptr = data;
+    if (!on_device) {
+        HIPCHK(ctx, hipMalloc(&owned, bytes));
+        hipError_t e = hipMemcpy(owned, data, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(owned);
+            return fail(ctx, CRP_EDEVICE, std::string("grid upload: ") + hipGetErrorString(e));
+        }
+        ptr = owned;
+    }
+    if (ctx->grid_owned)
+        (void)hipFree(ctx->grid_owned);
+    free_corner(ctx);
+    ctx->grid_owned = owned;
+    ctx->grid = ptr;
+    ctx->grid_dtype = dtype;
+    ctx->gn[0] = nx;
+    ctx->gn[1] = ny;
+    ctx->gn[2] = nz;
+    ctx->spacing = spacing_m;
+    for (int a = 0; a < 3; ++a)
+        ctx->origin[a] = org[a];
+    ctx->has_grid = true;
+    if (ctx->launch.layout == CRP_LAYOUT_CORNER && dtype != CRP_F32)
+        ctx->launch.layout = CRP_LAYOUT_LINEAR;
+    return CRP_OK;
+}
+
+crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e, const double* tpi,
+                          const double* tn, const double* bp)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (n < 2 || n > 1024 || !e || !tpi || !tn || !bp)
+        return fail(ctx, CRP_EINVAL, "tables: need 2 <= n <= 1024 and non-null arrays");
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(e[i]) || !(e[i] > 0))
+            return fail(ctx, CRP_EINVAL, "tables: nodes must be positive and finite");
+        if (i > 0 && !(e[i] > e[i - 1]))
+            return fail(ctx, CRP_EINVAL, "tables: nodes must be strictly increasing");
+        for (const double* v : {tpi, tn, bp})
+            if (!std::isfinite(v[i]) || v[i] < 0)
+                return fail(ctx, CRP_EINVAL, "tables: values must be finite and >= 0");
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<double> h((size_t)4 * n);
+    std::memcpy(h.data(), e, n * sizeof(double));
+    std::memcpy(h.data() + n, tpi, n * sizeof(double));
+    std::memcpy(h.data() + 2 * n, tn, n * sizeof(double));
+    std::memcpy(h.data() + 3 * n, bp, n * sizeof(double));
+    if (ctx->tab)
+        (void)hipFree(ctx->tab);
+    ctx->tab = nullptr;
+    ctx->has_tables = false;
+    HIPCHK(ctx, hipMalloc((void**)&ctx->tab, h.size() * sizeof(double)));
+    HIPCHK(ctx, hipMemcpy(ctx->tab, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    ctx->tab_n = n;
+    ctx->lg0 = std::log10(e[0]);
+    ctx->lgscale = (double)(n - 1) / (std::log10(e[n - 1]) - std::log10(e[0]));
+    ctx->has_tables = true;
+    return CRP_OK;
+}
+
+static std::string bad_candidate(int64_t i, const int32_t* A, const int32_t* Z, const double* E,
+                                 const double* pos, const double* dir, const double* lmax,
+                                 double max_extent)
+{
+    char buf[256];
+    if (!(A[i] >= 1 && A[i] <= 255 && Z[i] >= 1 && Z[i] <= A[i]))
+        snprintf(buf, sizeof buf, "inject: candidate %lld: need 1 <= Z <= A <= 255 (A=%d Z=%d)",
+                 (long long)i, A[i], Z[i]);
+    else if (!(std::isfinite(E[i]) && E[i] > 0))
+        snprintf(buf, sizeof buf, "inject: candidate %lld: energy must be finite and > 0",
+                 (long long)i);
+    else if (!(std::isfinite(lmax[i]) && lmax[i] > 0))
+        snprintf(buf, sizeof buf, "inject: candidate %lld: lmax must be finite and > 0",
+                 (long long)i);
+    else {
+        double d2 = 0, p2 = 0;
+        bool fin = true;
+        for (int a = 0; a < 3; ++a) {
+            fin = fin && std::isfinite(pos[3 * i + a]) && std::isfinite(dir[3 * i + a]);
+            d2 += dir[3 * i + a] * dir[3 * i + a];
+            p2 += pos[3 * i + a] * pos[3 * i + a];
+        }
+        if (!fin)
+            snprintf(buf, sizeof buf, "inject: candidate %lld: non-finite position/direction",
+                     (long long)i);
+        else if (std::fabs(std::sqrt(d2) - 1.0) > 1e-12)
+            snprintf(buf, sizeof buf, "inject: candidate %lld: |dir| must be 1 within 1e-12",
+                     (long long)i);
+        else if (!(std::sqrt(p2) + lmax[i] < max_extent))
+            snprintf(buf, sizeof buf,
+                     "inject: candidate %lld: |pos| + lmax must stay below 2^30 grid cells",
+                     (long long)i);
+        else
+            snprintf(buf, sizeof buf, "inject: candidate %lld is invalid", (long long)i);
+    }
+    return buf;
+}
+
+crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t* A,
+                      const int32_t* Z, const double* E, const double* pos, const double* dir,
+                      const double* lmax, int32_t on_device)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (n < 0)
+        return fail(ctx, CRP_EINVAL, "inject: n must be >= 0");
+    if (n == 0)
+        return CRP_OK;
+    if (!id || !A || !Z || !E || !pos || !dir || !lmax)
+        return fail(ctx, CRP_EINVAL, "inject: null array");
+    if (!ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "inject: set the field grid first");
+    if (ctx->pending + n > ctx->q.cap)
+        return fail(ctx, CRP_EQUEUE, "inject: queue capacity exceeded");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    const double max_extent = std::ldexp(1.0, 30) * ctx->spacing;
+    const uint32_t* d_id = id;
+    const int32_t *d_A = A, *d_Z = Z;
+    const double *d_E = E, *d_pos = pos, *d_dir = dir, *d_lmax = lmax;
+    void* stage = nullptr;
+    if (!on_device) {
+        for (int64_t i = 0; i < n; ++i) {
+            bool ok = A[i] >= 1 && A[i] <= 255 && Z[i] >= 1 && Z[i] <= A[i] &&
+                      std::isfinite(E[i]) && E[i] > 0 && std::isfinite(lmax[i]) && lmax[i] > 0;
+            double d2 = 0, p2 = 0;
+            for (int a = 0; a < 3 && ok; ++a) {
+                ok = std::isfinite(pos[3 * i + a]) && std::isfinite(dir[3 * i + a]);
+                d2 += dir[3 * i + a] * dir[3 * i + a];
+                p2 += pos[3 * i + a] * pos[3 * i + a];
+            }
+            ok = ok && std::fabs(std::sqrt(d2) - 1.0) <= 1e-12 &&
+                 std::sqrt(p2) + lmax[i] < max_extent;
+            if (!ok)
+                return fail(ctx, CRP_EINVAL, bad_candidate(i, A, Z, E, pos, dir, lmax, max_extent));
+        }
+        const size_t bytes = (size_t)n * (4 + 4 + 4 + 8 + 24 + 24 + 8) + 7 * 256;
+        HIPCHK(ctx, hipMalloc(&stage, bytes));
+        Carver cv{(char*)stage};
+        uint32_t* s_id = cv.take<uint32_t>(n);
+        int32_t* s_A = cv.take<int32_t>(n);
+        int32_t* s_Z = cv.take<int32_t>(n);
+        double* s_E = cv.take<double>(n);
+        double* s_pos = cv.take<double>(3 * n);
+        double* s_dir = cv.take<double>(3 * n);
+        double* s_lmax = cv.take<double>(n);
+        hipError_t e = hipSuccess;
+        auto up = [&](void* d, const void* h, size_t b) {
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d, h, b, hipMemcpyHostToDevice, ctx->stream);
+        };
+        up(s_id, id, n * 4);
+        up(s_A, A, n * 4);
+        up(s_Z, Z, n * 4);
+        up(s_E, E, n * 8);
+        up(s_pos, pos, n * 24);
+        up(s_dir, dir, n * 24);
+        up(s_lmax, lmax, n * 8);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(ctx, CRP_EDEVICE, std::string("inject upload: ") + hipGetErrorString(e));
+        }
+        d_id = s_id;
+        d_A = s_A;
+        d_Z = s_Z;
+        d_E = s_E;
+        d_pos = s_pos;
+        d_dir = s_dir;
+        d_lmax = s_lmax;
+    } else {
+        const unsigned long long none = ~0ull;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->scratch, &none, 8, hipMemcpyHostToDevice, ctx->stream));
+        k_validate<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, id, A, Z, E, pos, dir, lmax,
+                                                                 max_extent, ctx->scratch);
+        HIPCHK(ctx, hipGetLastError());
+        unsigned long long bad = 0;
+        HIPCHK(ctx, hipMemcpyAsync(&bad, ctx->scratch, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (bad != ~0ull)
+            return fail(ctx, CRP_EINVAL,
+                        "inject: candidate " + std::to_string(bad) + " is invalid (device input)");
+    }
+    k_inject<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
+        ctx->q, ctx->pending, n, d_id, d_A, d_Z, d_E, d_pos, d_dir, d_lmax, ctx->cfg.seed,
+        ctx->cfg.hmin, ctx->cfg.precision == CRP_MIX ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (stage)
+        (void)hipFree(stage);
+    if (e != hipSuccess)
+        return fail(ctx, CRP_EDEVICE, std::string("inject: ") + hipGetErrorString(e));
+    ctx->pending += n;
+    return CRP_OK;
+}
+
+crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!ctx->has_grid && ctx->cfg.field_mode == CRP_FIELD_GRID)
+        return fail(ctx, CRP_ESTATE, "propagate: no field grid");
+    if (!ctx->has_tables)
+        return fail(ctx, CRP_ESTATE, "propagate: no tables");
+    if (ctx->cfg.field_mode == CRP_FIELD_NEURAL && !ctx->nf)
+        return fail(ctx, CRP_ESTATE, "propagate: neural field not initialised");
+    ctx->last_ms = 0.0;
+    ctx->last_launches = 0;
+    if (ctx->pending == 0)
+        return CRP_OK;
+    if (ctx->fin_unread > ctx->q.cap)
+        return fail(ctx, CRP_ESTATE, "propagate: read finished records first");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    DevCounters dc;
+    crp_status st;
+    if (ctx->cfg.field_mode == CRP_FIELD_NEURAL)
+        st = nf_propagate(ctx->nf, ctx, max_cycles, &dc);
+    else
+        st = run_kernel(ctx, max_cycles, &dc);
+    if (st != CRP_OK)
+        return st;
+    after_run(ctx, dc, true);
+    if (dc.queue_dropped > 0)
+        return fail(ctx, CRP_EQUEUE,
+                    "propagate: " + std::to_string(dc.queue_dropped) +
+                        " spawned secondaries dropped (queue capacity)");
+    return ctx->pending > 0 ? CRP_INCOMPLETE : CRP_OK;
+}
+
+crp_status crp_read_finished(crp_ctx* ctx, int64_t cap, const crp_finished_soa* out,
+                             int64_t* n_out)
+{
+    if (!ctx || cap < 0 || !n_out)
+        return CRP_EINVAL;
+    const int64_t k = std::min(cap, ctx->fin_unread);
+    const int64_t s = ctx->fin_unread - k;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    if (out && k > 0) {
+        const FinishedSoA& f = ctx->fin;
+        HIPCHK(ctx, copy_d2h(out->id, f.id + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->lineage, f.lineage + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->m, f.m + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->nsteps, f.nsteps + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->nrej, f.nrej + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->status, f.status + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->A, f.A + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->Z, f.Z + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E, f.E + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->L, f.L + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E0, f.E0 + s, k, ctx->stream));
+        if (out->x)
+            HIPCHK(ctx, copy_planar(out->x, f.x, f.cap, s, k, ctx->stream));
+        if (out->u)
+            HIPCHK(ctx, copy_planar(out->u, f.u, f.cap, s, k, ctx->stream));
+        if (out->u0)
+            HIPCHK(ctx, copy_planar(out->u0, f.u0, f.cap, s, k, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->fin_unread -= k;
+    *n_out = k;
+    return ctx->fin_unread > 0 ? CRP_EOVERFLOW : CRP_OK;
+}
+
+crp_status crp_read_neutral(crp_ctx* ctx, int64_t cap, const crp_neutral_soa* out,
+                            int64_t* n_out)
+{
+    if (!ctx || cap < 0 || !n_out)
+        return CRP_EINVAL;
+    const int64_t k = std::min(cap, ctx->neu_unread);
+    const int64_t s = ctx->neu_unread - k;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    if (out && k > 0) {
+        const NeutralSoA& f = ctx->neu;
+        HIPCHK(ctx, copy_d2h(out->id, f.id + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->lineage, f.lineage + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->m, f.m + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->chan, f.chan + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E, f.E + s, k, ctx->stream));
+        if (out->x)
+            HIPCHK(ctx, copy_planar(out->x, f.x, f.cap, s, k, ctx->stream));
+        if (out->u)
+            HIPCHK(ctx, copy_planar(out->u, f.u, f.cap, s, k, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->neu_unread -= k;
+    *n_out = k;
+    return ctx->neu_unread > 0 ? CRP_EOVERFLOW : CRP_OK;
+}
+
+crp_status crp_peek_pending(crp_ctx* ctx, int64_t cap, const crp_finished_soa* out,
+                            int64_t* n_out)
+{
+    if (!ctx || cap < 0 || !n_out)
+        return CRP_EINVAL;
+    const int64_t k = std::min(cap, ctx->pending);
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    if (out && k > 0) {
+        const QueueSoA& q = ctx->q;
+        HIPCHK(ctx, copy_d2h(out->id, q.id, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->lineage, q.lineage, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->m, q.m, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->nsteps, q.nsteps, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->nrej, q.nrej, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->A, q.A, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->Z, q.Z, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E, q.E, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->L, q.L, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E0, q.E0, k, ctx->stream));
+        if (out->x)
+            HIPCHK(ctx, copy_planar(out->x, q.x, q.cap, 0, k, ctx->stream));
+        if (out->u)
+            HIPCHK(ctx, copy_planar(out->u, q.u, q.cap, 0, k, ctx->stream));
+        if (out->u0)
+            HIPCHK(ctx, copy_planar(out->u0, q.u0, q.cap, 0, k, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (out->status)
+            for (int64_t i = 0; i < k; ++i)
+                out->status[i] = CRP_ACTIVE;
+    }
+    *n_out = k;
+    return CRP_OK;
+}
+
+crp_status crp_counts(crp_ctx* ctx, crp_counters* out)
+{
+    if (!ctx || !out)
+        return CRP_EINVAL;
+    *out = ctx->totals;
+    out->pending = ctx->pending;
+    out->finished_unread = ctx->fin_unread;
+    out->neutral_unread = ctx->neu_unread;
+    return CRP_OK;
+}
+
+crp_status crp_reset_counters(crp_ctx* ctx)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    std::memset(&ctx->totals, 0, sizeof ctx->totals);
+    return CRP_OK;
+}
+
+crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B, int32_t mode,
+                          int32_t on_device)
+{
+    if (!ctx || n < 0 || (n > 0 && (!pos || !B)))
+        return CRP_EINVAL;
+    if (n == 0)
+        return CRP_OK;
+    const bool neural = mode == 16 + CRP_FIELD_NEURAL;
+    if (!(mode == CRP_FP64 || mode == CRP_MIX || neural))
+        return fail(ctx, CRP_EINVAL, "eval_field: bad mode");
+    if (!ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "eval_field: no field grid");
+    if (neural && !ctx->nf)
+        return fail(ctx, CRP_ESTATE, "eval_field: neural field not initialised");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    const double* dpos = pos;
+    double* dB = B;
+    void* stage = nullptr;
+    if (!on_device) {
+        HIPCHK(ctx, hipMalloc(&stage, (size_t)n * 48));
+        dpos = (const double*)stage;
+        dB = (double*)stage + 3 * n;
+        HIPCHK(ctx, hipMemcpyAsync((void*)dpos, pos, n * 24, hipMemcpyHostToDevice, ctx->stream));
+    }
+    hipError_t e = hipSuccess;
+    if (neural) {
+        crp_status st = nf_eval(ctx->nf, make_view(ctx), n, dpos, dB, ctx->stream);
+        if (st != CRP_OK) {
+            if (stage)
+                (void)hipFree(stage);
+            return fail(ctx, st, "eval_field: neural evaluation failed");
+        }
+    } else {
+        GridView g = make_view(ctx);
+        const int md = mode == CRP_MIX ? MODE_MIX : MODE_FP64;
+        if (ctx->grid_dtype == CRP_F64)
+            k_eval_field<double, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+        else if (ctx->launch.layout == CRP_LAYOUT_CORNER && ctx->corner)
+            k_eval_field<float, 1><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+        else
+            k_eval_field<float, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(B, dB, n * 24, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (stage)
+        (void)hipFree(stage);
+    if (e != hipSuccess)
+        return fail(ctx, CRP_EDEVICE, std::string("eval_field: ") + hipGetErrorString(e));
+    return CRP_OK;
+}
+
+crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* l)
+{
+    if (!ctx || !l)
+        return CRP_EINVAL;
+    if (!(l->block == 64 || l->block == 128 || l->block == 256 || l->block == 512) ||
+        l->blocks_per_cu < 1 || l->blocks_per_cu > 64 || l->quantum < 1 || l->quantum > 4096 ||
+        !(l->layout == CRP_LAYOUT_LINEAR || l->layout == CRP_LAYOUT_CORNER))
+        return fail(ctx, CRP_EINVAL, "set_launch: invalid launch shape");
+    if (l->layout == CRP_LAYOUT_CORNER && ctx->has_grid && ctx->grid_dtype != CRP_F32)
+        return fail(ctx, CRP_EINVAL, "set_launch: corner layout needs an FP32 grid");
+    ctx->launch = *l;
+    return CRP_OK;
+}
+
+crp_status crp_get_launch(crp_ctx* ctx, crp_launch* l)
+{
+    if (!ctx || !l)
+        return CRP_EINVAL;
+    *l = ctx->launch;
+    return CRP_OK;
+}
+
+crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (kernel_ms)
+        *kernel_ms = ctx->last_ms;
+    if (launches)
+        *launches = ctx->last_launches;
+    return CRP_OK;
+}
+
+// ---- autotuner ----------------------------------------------------------
+crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, crp_launch* best,
+                    double* best_rate)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!ctx->has_grid || !ctx->has_tables)
+        return fail(ctx, CRP_ESTATE, "tune: set grid and tables first");
+    if (ctx->pending == 0)
+        return fail(ctx, CRP_ESTATE, "tune: inject a calibration batch first");
+    if (ctx->cfg.field_mode != CRP_FIELD_GRID)
+        return fail(ctx, CRP_ESTATE, "tune: grid field mode only");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    // back up the pending queue: slots [0, pending) of every array
+    const int64_t np = ctx->pending;
+    const size_t qbytes = queue_layout(nullptr, ctx->q.cap, nullptr);
+    void* backup = nullptr;
+    HIPCHK(ctx, hipMalloc(&backup, qbytes));
+    HIPCHK(ctx, hipMemcpyAsync(backup, ctx->qmem[0], qbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    const crp_launch orig = ctx->launch;
+    const int64_t fin0 = ctx->fin_unread, neu0 = ctx->neu_unread;
+    std::vector<crp_launch> cands;
+    const bool corner_ok = ctx->grid_dtype == CRP_F32;
+    for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
+        for (int bs : {64, 128, 256, 512})
+            for (int bpc : {2, 4, 8})
+                for (int qn : {1, 8})
+                    if (bs * bpc <= 2048)
+                        cands.push_back(crp_launch{bs, bpc, qn, layout});
+    crp_launch bestl = orig;
+    double bestr = -1.0;
+    crp_status st = CRP_OK;
+    for (const crp_launch& l : cands) {
+        // restore the queue (the park buffer swap may have moved it)
+        ctx->q = QueueSoA();
+        queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->qmem[0], backup, qbytes, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        queue_layout((char*)ctx->qmem[1], ctx->park.cap, &ctx->park);
+        ctx->pending = np;
+        ctx->fin_unread = fin0;
+        ctx->neu_unread = neu0;
+        ctx->launch = l;
+        DevCounters dc;
+        st = run_kernel(ctx, max_cycles, &dc);
+        if (st != CRP_OK)
+            break;
+        const double rate = ctx->last_ms > 0 ? (double)dc.steps / (ctx->last_ms * 1e-3) : 0.0;
+        if (rate > bestr) {
+            bestr = rate;
+            bestl = l;
+        }
+    }
+    // restore the pending work exactly as it was
+    queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
+    queue_layout((char*)ctx->qmem[1], ctx->park.cap, &ctx->park);
+    (void)hipMemcpyAsync(ctx->qmem[0], backup, qbytes, hipMemcpyDeviceToDevice, ctx->stream);
+    (void)hipMemsetAsync(ctx->q.ready, 0, ctx->q.cap * sizeof(uint32_t), ctx->stream);
+    (void)hipMemsetAsync(ctx->park.ready, 0, ctx->park.cap * sizeof(uint32_t), ctx->stream);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(backup);
+    ctx->pending = np;
+    ctx->fin_unread = fin0;
+    ctx->neu_unread = neu0;
+    if (st != CRP_OK) {
+        ctx->launch = orig;
+        return st;
+    }
+    ctx->launch = bestl;
+    if (best)
+        *best = bestl;
+    if (best_rate)
+        *best_rate = bestr;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s grid=%lldx%lldx%lld dtype=%d precision=%d field=%d : block=%d "
+                       "blocks_per_cu=%d quantum=%d layout=%d steps_per_s=%.6e\n",
+                    ctx->device_name.c_str(), (long long)ctx->gn[0], (long long)ctx->gn[1],
+                    (long long)ctx->gn[2], ctx->grid_dtype, ctx->cfg.precision,
+                    ctx->cfg.field_mode, bestl.block, bestl.blocks_per_cu, bestl.quantum,
+                    bestl.layout, bestr);
+            fclose(f);
+        }
+    }
+    return CRP_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoint -----------------------------------------------------------
+namespace {
+const uint64_t kMagic = 0x31504b43505243ull;  // "CRPCKP1"
+struct SnapHeader {
+    uint64_t magic;
+    int64_t pending, fin_unread, neu_unread;
+    int32_t precision, pad;
+    crp_counters totals;
+};
+
+template <class T>
+void put(std::vector<char>& b, const T* d, int64_t n, hipStream_t s)
+{
+    const size_t off = b.size();
+    b.resize(off + n * sizeof(T));
+    if (n)
+        (void)hipMemcpyAsync(b.data() + off, d, n * sizeof(T), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+}
+
+template <class T>
+bool get(const char*& p, const char* end, T* d, int64_t n, hipStream_t s)
+{
+    const size_t b = n * sizeof(T);
+    if ((size_t)(end - p) < b)
+        return false;
+    if (n)
+        (void)hipMemcpyAsync(d, p, b, hipMemcpyHostToDevice, s);
+    (void)hipStreamSynchronize(s);
+    p += b;
+    return true;
+}
+}  // namespace
+
+extern "C" {
+
+crp_status crp_snapshot(crp_ctx* ctx, void** blob, size_t* bytes)
+{
+    if (!ctx || !blob || !bytes)
+        return CRP_EINVAL;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    std::vector<char> b(sizeof(SnapHeader));
+    SnapHeader h;
+    std::memset(&h, 0, sizeof h);
+    h.magic = kMagic;
+    h.pending = ctx->pending;
+    h.fin_unread = ctx->fin_unread;
+    h.neu_unread = ctx->neu_unread;
+    h.precision = ctx->cfg.precision;
+    h.totals = ctx->totals;
+    std::memcpy(b.data(), &h, sizeof h);
+    hipStream_t s = ctx->stream;
+    const QueueSoA& q = ctx->q;
+    const int64_t np = ctx->pending;
+    for (int a = 0; a < 3; ++a) {
+        put(b, q.x + a * q.cap, np, s);
+        put(b, q.u + a * q.cap, np, s);
+        put(b, q.u0 + a * q.cap, np, s);
+    }
+    for (double* p : {q.E, q.L, q.Lmax, q.hctrl, q.tau, q.E0})
+        put(b, p, np, s);
+    for (uint32_t* p : {q.id, q.lineage, q.m, q.nsteps, q.nrej})
+        put(b, p, np, s);
+    for (int32_t* p : {q.A, q.Z})
+        put(b, p, np, s);
+    const FinishedSoA& f = ctx->fin;
+    const int64_t nf = ctx->fin_unread;
+    for (int a = 0; a < 3; ++a) {
+        put(b, f.x + a * f.cap, nf, s);
+        put(b, f.u + a * f.cap, nf, s);
+        put(b, f.u0 + a * f.cap, nf, s);
+    }
+    for (double* p : {f.E, f.L, f.E0})
+        put(b, p, nf, s);
+    for (uint32_t* p : {f.id, f.lineage, f.m, f.nsteps, f.nrej})
+        put(b, p, nf, s);
+    for (int32_t* p : {f.status, f.A, f.Z})
+        put(b, p, nf, s);
+    const NeutralSoA& n = ctx->neu;
+    const int64_t nn = ctx->neu_unread;
+    for (int a = 0; a < 3; ++a) {
+        put(b, n.x + a * n.cap, nn, s);
+        put(b, n.u + a * n.cap, nn, s);
+    }
+    put(b, n.E, nn, s);
+    for (uint32_t* p : {n.id, n.lineage, n.m})
+        put(b, p, nn, s);
+    put(b, n.chan, nn, s);
+    void* mem = std::malloc(b.size());
+    if (!mem)
+        return fail(ctx, CRP_ENOMEM, "snapshot: host allocation failed");
+    std::memcpy(mem, b.data(), b.size());
+    *blob = mem;
+    *bytes = b.size();
+    return CRP_OK;
+}
+
+crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes)
+{
+    if (!ctx || !blob || bytes < sizeof(SnapHeader))
+        return CRP_EINVAL;
+    SnapHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    if (h.magic != kMagic || h.precision != ctx->cfg.precision)
+        return fail(ctx, CRP_EINVAL, "restore: not a snapshot of this version / precision");
+    if (h.pending > ctx->q.cap || h.fin_unread > ctx->fin.cap || h.neu_unread > ctx->neu.cap)
+        return fail(ctx, CRP_EINVAL, "restore: snapshot exceeds this context's capacity");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    hipStream_t s = ctx->stream;
+    const char* p = (const char*)blob + sizeof h;
+    const char* end = (const char*)blob + bytes;
+    bool ok = true;
+    const QueueSoA& q = ctx->q;
+    const int64_t np = h.pending;
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && get(p, end, q.x + a * q.cap, np, s);
+        ok = ok && get(p, end, q.u + a * q.cap, np, s);
+        ok = ok && get(p, end, q.u0 + a * q.cap, np, s);
+    }
+    for (double* d : {q.E, q.L, q.Lmax, q.hctrl, q.tau, q.E0})
+        ok = ok && get(p, end, d, np, s);
+    for (uint32_t* d : {q.id, q.lineage, q.m, q.nsteps, q.nrej})
+        ok = ok && get(p, end, d, np, s);
+    for (int32_t* d : {q.A, q.Z})
+        ok = ok && get(p, end, d, np, s);
+    const FinishedSoA& f = ctx->fin;
+    const int64_t nf = h.fin_unread;
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && get(p, end, f.x + a * f.cap, nf, s);
+        ok = ok && get(p, end, f.u + a * f.cap, nf, s);
+        ok = ok && get(p, end, f.u0 + a * f.cap, nf, s);
+    }
+    for (double* d : {f.E, f.L, f.E0})
+        ok = ok && get(p, end, d, nf, s);
+    for (uint32_t* d : {f.id, f.lineage, f.m, f.nsteps, f.nrej})
+        ok = ok && get(p, end, d, nf, s);
+    for (int32_t* d : {f.status, f.A, f.Z})
+        ok = ok && get(p, end, d, nf, s);
+    const NeutralSoA& n = ctx->neu;
+    const int64_t nn = h.neu_unread;
+    for (int a = 0; a < 3; ++a) {
+        ok = ok && get(p, end, n.x + a * n.cap, nn, s);
+        ok = ok && get(p, end, n.u + a * n.cap, nn, s);
+    }
+    ok = ok && get(p, end, n.E, nn, s);
+    for (uint32_t* d : {n.id, n.lineage, n.m})
+        ok = ok && get(p, end, d, nn, s);
+    ok = ok && get(p, end, n.chan, nn, s);
+    if (!ok || p != end)
+        return fail(ctx, CRP_EINVAL, "restore: truncated or oversized snapshot");
+    ctx->pending = h.pending;
+    ctx->fin_unread = h.fin_unread;
+    ctx->neu_unread = h.neu_unread;
+    ctx->totals = h.totals;
+    return CRP_OK;
+}
+
+void crp_free(void* p) { std::free(p); }
+
+// ---- neural field entry points (implemented in crp_nf.hip) ---------------
+crp_status crp_nf_init(crp_ctx* ctx, const int32_t* freq, const float* params, double b_scale)
+{
+    if (!ctx || !freq || !params || !(b_scale > 0))
+        return CRP_EINVAL;
+    if (!ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "nf_init: set the field grid first (period and origin)");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    if (!ctx->nf) {
+        ctx->nf = nf_create(ctx->stream);
+        if (!ctx->nf)
+            return fail(ctx, CRP_ENOMEM, "nf_init: allocation failed");
+    }
+    return nf_load(ctx->nf, freq, params, b_scale, ctx->err);
+}
+
+crp_status crp_nf_get_params(crp_ctx* ctx, float* params)
+{
+    if (!ctx || !params)
+        return CRP_EINVAL;
+    if (!ctx->nf)
+        return fail(ctx, CRP_ESTATE, "nf: not initialised");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    return nf_get(ctx->nf, params, ctx->err);
+}
+
+crp_status crp_nf_loss_grad(crp_ctx* ctx, int64_t n, const double* pos, const float* target,
+                            float* out, float* grad, double* loss)
+{
+    if (!ctx || n <= 0 || !pos || !target)
+        return CRP_EINVAL;
+    if (!ctx->nf)
+        return fail(ctx, CRP_ESTATE, "nf: not initialised");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    return nf_loss_grad(ctx->nf, make_view(ctx), n, pos, target, out, grad, loss, ctx->err);
+}
+
+crp_status crp_nf_train(crp_ctx* ctx, int64_t steps, int64_t batch, double lr0, double lr1,
+                        uint64_t seed, float* loss_out)
+{
+    if (!ctx || steps < 0 || batch <= 0 || !(lr0 > 0) || !(lr1 > 0))
+        return CRP_EINVAL;
+    if (!ctx->nf)
+        return fail(ctx, CRP_ESTATE, "nf: not initialised");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    return nf_train(ctx->nf, make_view(ctx), steps, batch, lr0, lr1, seed, loss_out, ctx->err);
+}
+
+}  // extern "C"
+
+// Used by the neural-field propagation path to reuse the run bookkeeping.
+namespace crp {
+crp_status ctx_run_params(crp_ctx* ctx, int64_t max_cycles, PropParams* P, int* nb, int* bs,
+                          size_t* lds)
+{
+    P->q = ctx->q;
+    P->park = ctx->park;
+    P->fin = ctx->fin;
+    P->neu = ctx->neu;
+    P->cnt = ctx->cnt;
+    P->grid = make_view(ctx);
+    P->tab.e = ctx->tab;
+    P->tab.v[0] = ctx->tab + ctx->tab_n;
+    P->tab.v[1] = ctx->tab + 2 * ctx->tab_n;
+    P->tab.v[2] = ctx->tab + 3 * ctx->tab_n;
+    P->tab.n = ctx->tab_n;
+    P->tab.lg0 = ctx->lg0;
+    P->tab.scale = ctx->lgscale;
+    const crp_config& c = ctx->cfg;
+    P->sp.tol = c.tol;
+    P->sp.hmin = c.hmin;
+    P->sp.hmax = c.hmax;
+    P->sp.eps_loss = c.eps_loss;
+    P->sp.kappa_pi = c.kappa_pi;
+    P->sp.e_floor = c.e_floor;
+    for (int a = 0; a < 3; ++a)
+        P->sp.obs[a] = c.obs_center[a];
+    P->sp.obs_r = c.obs_radius;
+    P->sp.seed = c.seed;
+    P->sp.renorm = c.renormalize;
+    P->max_cycles = max_cycles;
+    P->tail0 = (unsigned long long)ctx->pending;
+    P->quantum = ctx->launch.quantum;
+    *nb = ctx->num_cus * ctx->launch.blocks_per_cu;
+    *bs = ctx->launch.block;
+    *lds = (size_t)4 * ctx->tab_n * sizeof(double);
+    DevCounters init;
+    std::memset(&init, 0, sizeof init);
+    init.tail = (unsigned long long)ctx->pending;
+    init.fin_n = (unsigned long long)ctx->fin_unread;
+    init.neu_n = (unsigned long long)ctx->neu_unread;
+    hipError_t e = hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream);
+    return e == hipSuccess ? CRP_OK : CRP_EDEVICE;
+}
+
+hipStream_t ctx_stream(crp_ctx* ctx) { return ctx->stream; }
+void ctx_set_timing(crp_ctx* ctx, double ms, int64_t launches)
+{
+    ctx->last_ms = ms;
+    ctx->last_launches = launches;
+}
+}  // namespace crp

@@ -1,0 +1,374 @@
+"""GPU (HIP, through the C-ABI) versus the CPU oracle on the same seeded inputs.
+
+Bar: integer bookkeeping exact (counts, channels, event numbers, statuses,
+species); FP64 positions within 1e-9 * max(L, |x|) and energies within 1e-6
+relative; the precision form is compared with the oracle's precision form
+under the same bar, and its error against the FP64 oracle is reported.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import crp_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+INT_FIELDS = ("id", "lineage", "m", "nsteps", "nrej", "status", "A", "Z")
+CNT_KEYS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts", "rejects",
+            "forced", "events", "null_events", "inter_pi", "inter_n", "charged_sec",
+            "neutral_sec")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1307_2643_amd import crp
+    crp.load()
+    return crp
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def small_grid():
+    return I.W_SMALL.make_grid()
+
+
+@pytest.fixture(scope="module")
+def mixed_grid():
+    return I.W_MIXED256.make_grid()
+
+
+def make_ctx(P, w, grid, tables, precision, qcap=1 << 16, ncap=1 << 16, **kw):
+    prm = P.params_for(w, precision, queue_capacity=qcap, neutral_capacity=ncap, **kw)
+    ctx = P.Context(prm)
+    ctx.set_field_grid(grid, w.spacing_m)
+    ctx.set_tables(tables)
+    return ctx
+
+
+def run_gpu(ctx, inj, max_cycles=0):
+    ctx.inject(inj)
+    done = ctx.propagate(max_cycles)
+    return done, ctx.read_finished(), ctx.read_neutral(), ctx.counts()
+
+
+def compare_records(fg, fo, what, x_tol=1e-9, e_tol=1e-6):
+    from paper_1307_2643_amd import crp
+    fg = crp.sort_finished(fg)
+    fo = crp.sort_finished(fo)
+    assert len(fg["id"]) == len(fo["id"]), what
+    for k in INT_FIELDS:
+        bad = np.nonzero(fg[k] != fo[k])[0]
+        assert bad.size == 0, f"{what}: field {k} differs at {bad[:5]}"
+    scale = np.maximum(fo["L"], np.linalg.norm(fo["x"], axis=1))
+    dx = np.linalg.norm(fg["x"] - fo["x"], axis=1)
+    assert np.all(dx <= x_tol * np.maximum(scale, 1.0)), f"{what}: max dx/scale {np.max(dx / scale)}"
+    assert np.all(np.abs(fg["E"] / fo["E"] - 1) <= e_tol), what
+    assert np.all(np.abs(fg["L"] - fo["L"]) <= x_tol * np.maximum(fo["L"], 1.0)), what
+    assert np.all(np.linalg.norm(fg["u"] - fo["u"], axis=1) <= 1e-7), what
+    same = np.all(fg["x"] == fo["x"], axis=1) & np.all(fg["u"] == fo["u"], axis=1) & \
+        (fg["E"] == fo["E"]) & (fg["L"] == fo["L"])
+    say(f"{what}: {len(fg['id'])} records, bitwise identical {same.sum()} "
+        f"({100.0 * same.mean():.3f}%)")
+    return same
+
+
+def compare_neutral(ng, no, what):
+    from paper_1307_2643_amd import crp
+    ng = crp.sort_neutral(ng)
+    no = crp.sort_neutral(no)
+    assert len(ng["id"]) == len(no["id"]), what
+    for k in ("id", "lineage", "m", "chan"):
+        assert np.array_equal(ng[k], no[k]), f"{what}: {k}"
+    assert np.allclose(ng["E"], no["E"], rtol=1e-6, atol=0), what
+    assert np.allclose(ng["x"], no["x"], rtol=0, atol=1e-9 * 1e26), what
+
+
+def compare_counts(cg, co, what):
+    for k in CNT_KEYS:
+        assert cg[k] == co[k], f"{what}: count {k}: gpu {cg[k]} oracle {co[k]}"
+
+
+# ---------------------------------------------------------------------------
+# Field gather: the stepper's interpolation is bitwise the oracle's.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("gdtype,mode", [(np.float64, 0), (np.float32, 0), (np.float32, 1),
+                                         (np.float64, 1)])
+def test_eval_field_bitwise(P, O, small_grid, gdtype, mode):
+    w = I.W_SMALL
+    g = small_grid.astype(gdtype)
+    ctx = make_ctx(P, w, g, w.make_tables(), P.FP64)
+    rng = np.random.default_rng(1)
+    box = 32 * w.spacing_m
+    pos = (rng.random((100_000, 3)) * 7.0 - 3.0) * box       # several periods, both signs
+    pos[:100] = np.round(pos[:100] / w.spacing_m) * w.spacing_m  # exact vertices
+    say(f"eval_field dtype={np.dtype(gdtype).name} mode={mode}")
+    got = ctx.eval_field(pos, mode)
+    ref = O.eval_field(O.GridRef(g, w.spacing_m), pos, O.MIX if mode == 1 else O.FP64)
+    assert np.array_equal(got, ref)
+    if gdtype == np.float32:
+        ctx.set_launch(layout=P.LAYOUT_CORNER)
+        ctx.propagate()  # nothing pending: no-op
+        say("eval_field corner layout")
+        ctx.inject(w.make_injection(64))
+        ctx.propagate()            # builds the corner records on first use
+        got2 = ctx.eval_field(pos, mode)
+        assert np.array_equal(got2, ref)
+    ctx.close()
+
+
+def test_eval_field_non_power_of_two_grid(P, O):
+    rng = np.random.default_rng(2)
+    g = rng.standard_normal((6, 5, 7, 3)) * 1e-13
+    w = I.W_SMALL
+    ctx = make_ctx(P, w, g, w.make_tables(), P.FP64)
+    pos = (rng.random((20000, 3)) * 40 - 20) * w.spacing_m
+    say("eval_field 6x5x7")
+    got = ctx.eval_field(pos, 0)
+    ref = O.eval_field(O.GridRef(g, w.spacing_m), pos, O.FP64)
+    assert np.array_equal(got, ref)
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Whole path: small workload (1000 protons, 32^3 FP64 grid, loss table).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_workload_parity(P, O, small_grid, precision):
+    w = I.W_SMALL
+    grid = small_grid if precision == 0 else small_grid.astype(np.float32)
+    tables = w.make_tables()
+    inj = w.make_injection()
+    say(f"small workload precision={precision}")
+    ctx = make_ctx(P, w, grid, tables, precision)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done
+    fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
+                                O.GridRef(grid, w.spacing_m), O.TablesRef(tables), inj)
+    compare_counts(cg, co, "small")
+    same = compare_records(fg, fo, f"small p{precision}")
+    assert same.mean() > 0.99
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Mixed nuclei with interactions, secondaries and the observer (256^3 grid).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mixed_workload_subset_parity(P, O, mixed_grid, precision):
+    w = I.W_MIXED256
+    grid = mixed_grid if precision == 0 else mixed_grid.astype(np.float32)
+    tables = w.make_tables()
+    inj = w.make_injection(3000)
+    say(f"mixed 256^3 subset precision={precision}")
+    ctx = make_ctx(P, w, grid, tables, precision)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done
+    fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
+                                O.GridRef(grid, w.spacing_m), O.TablesRef(tables), inj,
+                                nthreads=0)
+    compare_counts(cg, co, "mixed")
+    assert co["charged_sec"] > 0 and co["neutral_sec"] > 0
+    same = compare_records(fg, fo, f"mixed p{precision}")
+    assert same.mean() > 0.99
+    compare_neutral(ng, no, "mixed neutral")
+    ctx.close()
+
+
+def test_observer_detections_match(P, O, mixed_grid):
+    """Protons and nuclei aimed near the observer sphere: detection statuses exact."""
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    n = 2000
+    rng = np.random.default_rng(5)
+    inj = w.make_injection(n)
+    tgt = np.array(w.observer) + rng.standard_normal((n, 3)) * 2 * I.MPC_M
+    d = tgt / np.linalg.norm(tgt, axis=1)[:, None]
+    inj.dir = d / np.linalg.norm(d, axis=1)[:, None]
+    inj.E = np.full(n, 3e20)
+    ctx = make_ctx(P, w, mixed_grid, tables, 0)
+    say("observer detections")
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    fo, no, co, _ = O.propagate(O.config_for(w), O.GridRef(mixed_grid, w.spacing_m),
+                                O.TablesRef(tables), inj)
+    assert co["observed"] > 100
+    compare_counts(cg, co, "observer")
+    compare_records(fg, fo, "observer")
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Invariance: launch shape, batch split, cycle budget, checkpoint/restore.
+# ---------------------------------------------------------------------------
+def _gpu_run(P, w, grid, tables, inj, precision=0, launch=None, batches=1, max_cycles=0,
+             qcap=1 << 16):
+    ctx = make_ctx(P, w, grid, tables, precision, qcap=qcap)
+    if launch:
+        ctx.set_launch(**launch)
+    n = len(inj)
+    cuts = np.linspace(0, n, batches + 1).astype(int)
+    fins, neus = [], []
+    for b in range(batches):
+        ctx.inject(inj.subset(slice(cuts[b], cuts[b + 1])))
+        while not ctx.propagate(max_cycles):
+            pass
+        fins.append(ctx.read_finished())
+        neus.append(ctx.read_neutral())
+    cnt = ctx.counts()
+    ctx.close()
+    fin = {k: np.concatenate([f[k] for f in fins]) for k in fins[0]}
+    neu = {k: np.concatenate([f[k] for f in neus]) for k in neus[0]}
+    return fin, neu, cnt
+
+
+def _assert_identical(a, b):
+    from paper_1307_2643_amd import crp
+    a = crp.sort_finished(a)
+    b = crp.sort_finished(b)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("launch", [dict(block=64, blocks_per_cu=1, quantum=1),
+                                    dict(block=512, blocks_per_cu=2, quantum=16),
+                                    dict(block=128, blocks_per_cu=8, quantum=3, layout=1)])
+def test_launch_shape_invariance(P, mixed_grid, launch):
+    w = I.W_MIXED256
+    grid = mixed_grid.astype(np.float32)
+    tables = w.make_tables()
+    inj = w.make_injection(3000)
+    say(f"invariance launch={launch}")
+    ref, rn, rc = _gpu_run(P, w, grid, tables, inj, precision=1)
+    got, gn, gc = _gpu_run(P, w, grid, tables, inj, precision=1, launch=launch)
+    _assert_identical(ref, got)
+    for k in CNT_KEYS:
+        assert rc[k] == gc[k]
+
+
+def test_batch_split_and_budget_invariance(P, mixed_grid):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    inj = w.make_injection(3000)
+    say("batch split + budget")
+    ref, _, rc = _gpu_run(P, w, mixed_grid, tables, inj)
+    got, _, gc = _gpu_run(P, w, mixed_grid, tables, inj, batches=3, max_cycles=37)
+    _assert_identical(ref, got)
+    for k in CNT_KEYS:
+        assert rc[k] == gc[k]
+
+
+def test_budget_state_matches_oracle_cycle_cap(P, O, mixed_grid):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    inj = w.make_injection(1500)
+    say("cycle cap vs oracle")
+    ctx = make_ctx(P, w, mixed_grid, tables, 0)
+    ctx.inject(inj)
+    done = ctx.propagate(25)
+    assert not done
+    pend = ctx.peek_pending()
+    fin = ctx.read_finished()
+    fo, _, co, _ = O.propagate(O.config_for(w, max_cycles=25), O.GridRef(mixed_grid, w.spacing_m),
+                               O.TablesRef(tables), inj)
+    allg = {k: np.concatenate([fin[k], pend[k]]) for k in fin}
+    compare_records(allg, fo, "cycle cap 25")
+    ctx.close()
+
+
+def test_snapshot_restore_resume(P, mixed_grid):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    inj = w.make_injection(2000)
+    say("snapshot/restore")
+    ref, _, rc = _gpu_run(P, w, mixed_grid, tables, inj)
+    ctx = make_ctx(P, w, mixed_grid, tables, 0)
+    ctx.inject(inj)
+    assert not ctx.propagate(40)
+    blob = ctx.snapshot()
+    ctx.close()
+    ctx2 = make_ctx(P, w, mixed_grid, tables, 0)
+    ctx2.restore(blob)
+    while not ctx2.propagate(0):
+        pass
+    got = ctx2.read_finished()
+    _assert_identical(ref, got)
+    c2 = ctx2.counts()
+    for k in CNT_KEYS:
+        assert c2[k] == rc[k]
+    ctx2.close()
+
+
+# ---------------------------------------------------------------------------
+# Error paths and edge cases.
+# ---------------------------------------------------------------------------
+def test_inject_validation_all_or_nothing(P, small_grid):
+    w = I.W_SMALL
+    ctx = make_ctx(P, w, small_grid, w.make_tables(), 0)
+    inj = w.make_injection(10)
+    inj.Z = inj.Z.copy()
+    inj.Z[7] = 3          # Z > A
+    say("inject validation")
+    with pytest.raises(P.CrpError) as ei:
+        ctx.inject(inj)
+    assert ei.value.status == -1 and "candidate 7" in str(ei.value)
+    assert ctx.counts()["pending"] == 0
+    inj2 = w.make_injection(10)
+    inj2.dir = inj2.dir * 1.001
+    with pytest.raises(P.CrpError):
+        ctx.inject(inj2)
+    ctx.inject(w.make_injection(10))
+    assert ctx.counts()["pending"] == 10
+    assert ctx.propagate()
+    assert len(ctx.read_finished()["id"]) == 10
+    ctx.close()
+
+
+def test_empty_and_capacity(P, mixed_grid):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    ctx = make_ctx(P, w, mixed_grid, tables, 0, qcap=256)
+    say("empty / capacity")
+    assert ctx.propagate()                  # nothing pending
+    with pytest.raises(P.CrpError) as ei:
+        ctx.inject(w.make_injection(300))
+    assert ei.value.status == -5
+    # a full queue of heavy nuclei that spawn: secondaries beyond capacity are
+    # dropped and reported
+    inj = w.make_injection(256)
+    inj.A[:] = 56
+    inj.Z[:] = 26
+    inj.E[:] = 5e20
+    ctx.inject(inj)
+    with pytest.raises(P.CrpError) as ei:
+        ctx.propagate()
+    assert ei.value.status == -5
+    assert ctx.counts()["queue_dropped"] > 0
+    ctx.close()
+
+
+def test_single_candidate_and_ragged_batch(P, O, mixed_grid):
+    """Batches of 1 and 65 candidates (one full wave plus one lane)."""
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    for n in (1, 65):
+        inj = w.make_injection(n)
+        ctx = make_ctx(P, w, mixed_grid, tables, 0)
+        say(f"ragged n={n}")
+        done, fg, ng, cg = run_gpu(ctx, inj)
+        fo, no, co, _ = O.propagate(O.config_for(w), O.GridRef(mixed_grid, w.spacing_m),
+                                    O.TablesRef(tables), inj)
+        compare_counts(cg, co, f"n={n}")
+        compare_records(fg, fo, f"n={n}")
+        ctx.close()
