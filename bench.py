@@ -1,0 +1,353 @@
+"""Benchmark of the propagation hot path on one MI355X.
+
+One bench step = inject one batch of synthetic candidates (already resident in
+HBM) and propagate every candidate and spawned secondary to completion.  The
+workload is the 1024^3 FP32 turbulent grid (10 kpc cells, 1 nG RMS) with 1e7
+mixed H/He/N/Fe candidates on an E^-2 spectrum from the origin, interaction
+and loss tables, a 1 Mpc observer at (50,0,0) Mpc and a 100 Mpc trajectory
+limit.  The headline value is accepted candidate-steps per second of the
+precision form; the FP64 method on the same grid is timed beside it, and the
+precision form's error against the FP64 oracle is reported on a sample.
+
+    python bench.py [--steps K] [--warmup W] [--n CANDIDATES] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+GATHERS_PER_ATTEMPT = 6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sources_sha():
+    h = hashlib.sha256()
+    for f in ("crp_device.hpp", "crp_kernels.hip", "crp_internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1307_2643_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=None, help="candidates per batch (default 1e7)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-method variant")
+    ap.add_argument("--launch", type=str, default=None,
+                    help="force the launch shape BLOCK,BLOCKS_PER_CU,REFILL,LAYOUT (no tuner)")
+    ap.add_argument("--no-sample", action="store_true",
+                    help="skip the error sample against the oracle")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--summarize-pmc", type=str, default=None, metavar="DIR",
+                    help="offline: per-launch HBM traffic from rocprofv3 --pmc CSV output")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the propagation "
+              "shards by candidate id across GPUs without communication, but this build "
+              "measures one GPU's share.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import crp_inputs as I
+    from paper_1307_2643_amd import crp
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)                       # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+
+    w = I.W_MIXED1024
+    n = args.n or w.n_candidates
+    log(f"[bench] workload {w.name}: n={n}, grid {w.grid_n}^3 fp32")
+    t0 = time.time()
+    grid = w.make_grid(device=dev)                     # [1024]^3 x 3 float32, 12.9 GB
+    torch.cuda.synchronize()
+    log(f"[bench] grid generated in {time.time() - t0:.1f}s")
+    tables = w.make_tables()
+    inj = w.make_injection(n)
+    d_inj = [torch.as_tensor(a, device=dev) for a in
+             (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+
+    def context(precision):
+        prm = crp.params_for(w, precision, device=0, queue_capacity=2 * n,
+                             neutral_capacity=max(n, 1 << 20))
+        ctx = crp.Context(prm, stream)
+        ctx.set_field_grid(grid, w.spacing_m)
+        ctx.set_tables(tables)
+        return ctx
+
+    def inject(ctx, count=None):
+        if count is None:
+            ctx.inject(id=d_inj[0], A=d_inj[1], Z=d_inj[2], E=d_inj[3], pos=d_inj[4],
+                       dir=d_inj[5], lmax=d_inj[6], on_device=True)
+        else:
+            ctx.inject(id=d_inj[0][:count], A=d_inj[1][:count], Z=d_inj[2][:count],
+                       E=d_inj[3][:count], pos=d_inj[4][:count], dir=d_inj[5][:count],
+                       lmax=d_inj[6][:count], on_device=True)
+
+    # ---- precision form: tune (untimed), warm up, time K steps ---------------
+    ctx = context(crp.MIX)
+    tuned = None
+    if args.launch:
+        b, bpc, rf, lay = [int(v) for v in args.launch.split(",")]
+        ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
+    elif not args.no_tune:
+        t0 = time.time()
+        inject(ctx, min(n, 1 << 20))
+        tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
+        ctx.discard_finished()
+        while not ctx.propagate(0):
+            pass
+        ctx.discard_finished()
+        log(f"[bench] autotuner picked {tuned} ({rate:.3e} steps/s on the calibration "
+            f"batch) in {time.time() - t0:.1f}s")
+    if args.layout is not None:
+        lch = ctx.get_launch()
+        lch["layout"] = args.layout
+        ctx.set_launch(**lch)
+    launch = ctx.get_launch()
+
+    def one_step(c):
+        inject(c)
+        c.propagate(0)
+        ms, nl = c.last_timing()
+        cnt = c.counts()
+        c.discard_finished()
+        return ms, cnt
+
+    for i in range(args.warmup):
+        ctx.reset_counters()
+        ms, cnt = one_step(ctx)
+        log(f"[bench] warmup {i}: kernel {ms:.1f} ms, {cnt['steps']} steps")
+    ctx.reset_counters()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ms, cnt = one_step(ctx)
+        kms.append(ms)
+        log(f"[bench] step {i}: kernel {ms:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cnt = ctx.counts()
+    steps_total = cnt["steps"]
+    attempts_total = cnt["attempts"]
+    value = steps_total / wall
+    ms_per_step = 1000.0 * wall / args.steps
+    kernel_ms = sum(kms) / len(kms)
+    attempts_per_launch = attempts_total / args.steps
+    alg_bytes = attempts_per_launch * GATHERS_PER_ATTEMPT * 8 * 3 * 4
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    log(f"[bench] precision form: {value:.4e} steps/s, {ms_per_step:.1f} ms/step, "
+        f"kernel {kernel_ms:.1f} ms, {achieved:.1f} GB/s algorithmic")
+
+    # ---- sample for the stated error: MIX (GPU) vs FP64 oracle --------------
+    nsample = 0 if args.no_sample else min(n, 2000)
+    horizon = 16
+    if nsample:
+        ctx.reset_counters()
+        inject(ctx, nsample)
+        ctx.propagate(0)
+        mix_fin = crp.sort_finished(ctx.read_finished())
+        ctx.discard_finished()
+        # the same candidates after their first `horizon` cycles
+        inject(ctx, nsample)
+        ctx.propagate(horizon)
+        part = ctx.read_finished()
+        pend = ctx.peek_pending()
+        mix_short = crp.sort_finished({k: np.concatenate([part[k], pend[k]]) for k in part})
+        while not ctx.propagate(0):
+            pass
+        ctx.discard_finished()
+    ctx.close()
+
+    variants = {"mix": {"steps_per_s": value, "kernel_ms": kernel_ms, "launch": launch}}
+
+    # ---- FP64 method on the same FP32 grid ("plain grid") ----------------------
+    fp64_fin = None
+    if not args.no_fp64:
+        c64 = context(crp.FP64)
+        c64.set_launch(**launch)
+        one_step(c64)                    # untimed: builds this context's grid records
+        c64.reset_counters()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms64, cnt64 = one_step(c64)
+        torch.cuda.synchronize()
+        wall64 = time.perf_counter() - t1
+        variants["fp64"] = {"steps_per_s": cnt64["steps"] / wall64, "kernel_ms": ms64}
+        log(f"[bench] FP64 method: {cnt64['steps'] / wall64:.4e} steps/s")
+        if nsample:
+            c64.reset_counters()
+            inject(c64, nsample)
+            c64.propagate(0)
+            fp64_fin = crp.sort_finished(c64.read_finished())
+        c64.close()
+
+    # ---- CPU oracle baseline and error of the precision form ----------------
+    cpu = None
+    err = None
+    if not args.no_cpu and nsample:
+        from oracle import oracle as O
+        host_grid = grid.cpu().numpy()
+        G = O.GridRef(host_grid, w.spacing_m)
+        T = O.TablesRef(tables)
+        threads = len(os.sched_getaffinity(0))
+        fo, _, co, used = O.propagate(O.config_for(w), G, T, inj.subset(slice(0, nsample)),
+                                      nthreads=threads)
+        fo = O.sort_finished(fo)
+        err = {"full_run": error_report(mix_fin, fo)}
+        fs, _, _, _ = O.propagate(O.config_for(w, max_cycles=horizon), G, T,
+                                  inj.subset(slice(0, nsample)), nthreads=threads)
+        err[f"after_{horizon}_cycles"] = error_report(mix_short, O.sort_finished(fs))
+        if fp64_fin is not None:
+            if len(fp64_fin["id"]) == len(fo["id"]):
+                same = int(np.sum(np.all(fp64_fin["x"] == fo["x"], axis=1) &
+                                  (fp64_fin["E"] == fo["E"])))
+                err["fp64_gpu_vs_fp64_oracle_bitwise"] = f"{same}/{len(fo['id'])}"
+            else:
+                err["fp64_gpu_vs_fp64_oracle_bitwise"] = "record counts differ"
+        # time the oracle's precision form on a bounded sample of the workload
+        probe = 256
+        t1 = time.perf_counter()
+        _, _, cp, used = O.propagate(O.config_for(w, precision=O.MIX), G, T,
+                                     inj.subset(slice(0, probe)), nthreads=threads)
+        tp = time.perf_counter() - t1
+        m = int(min(n, max(probe, probe * args.cpu_seconds / max(tp, 1e-3))))
+        t1 = time.perf_counter()
+        _, _, cp, used = O.propagate(O.config_for(w, precision=O.MIX), G, T,
+                                     inj.subset(slice(0, m)), nthreads=threads)
+        tc = time.perf_counter() - t1
+        cpu = {"value": cp["steps"] / tc, "unit": "candidate-steps/s", "cores": used,
+               "kind": "oracle",
+               "sample": f"first {m} candidates of the same batch (precision form), "
+                         f"{cp['steps']} steps in {tc:.1f}s"}
+        log(f"[bench] CPU oracle: {cpu['value']:.3e} steps/s on {used} threads")
+        del host_grid
+
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "propagate_mix_grid1024_traffic.json")
+    if os.path.exists(tpath):
+        t = json.load(open(tpath))
+        if t.get("kernel_sources_sha") == kernel_sources_sha() and t.get("launch") == launch:
+            traffic = t.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": "candidate-steps/sec at 1024^3 grid: plain grid vs FP32/neural-field form "
+                  "at stated error",
+        "value": value,
+        "unit": "candidate-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "candidates_per_step": n, "grid": "1024^3x3 fp32",
+                   "cell_kpc": 10, "precision": "mix", "launch": launch},
+        "variants": variants,
+        "error_vs_fp64_oracle": err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_propagate<MIX,float,%s>" % ("corner-coop" if launch["layout"] else "linear"),
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "attempts_per_launch": attempts_per_launch},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def summarize_pmc(d):
+    """Per-launch HBM read/write bytes of the propagation kernel from two
+    rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each
+    scaled by what the same counter reads for the 1 GiB copy (--calib-copy)."""
+    import csv
+    import glob
+    vals = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            c, k = r["Counter_Name"], r["Kernel_Name"]
+            if c not in ("FETCH_SIZE", "WRITE_SIZE"):
+                continue
+            kind = "prop" if "k_propagate" in k else ("copy" if "copyBuffer" in k else None)
+            if kind:
+                vals.setdefault((kind, c), []).append(float(r["Counter_Value"]))
+    gib = float(1 << 30)
+    out = {"kernel_sources_sha": kernel_sources_sha()}
+    for c, key in (("FETCH_SIZE", "read"), ("WRITE_SIZE", "write")):
+        copy = max(vals[("copy", c)]) * 1024.0          # the 1 GiB copy, bytes as counted
+        prop = max(vals[("prop", c)]) * 1024.0          # the largest (timed) propagation launch
+        factor = gib / copy
+        out[f"{key}_scale_factor"] = factor
+        out[f"{key}_bytes_per_launch"] = prop * factor
+    out["hbm_bytes_per_launch"] = out["read_bytes_per_launch"] + out["write_bytes_per_launch"]
+    print(json.dumps(out, indent=1))
+
+
+def error_report(gpu, ref):
+    """Per-output error of the precision form against the FP64 oracle, over
+    the records present in both (keyed by (id, lineage))."""
+    kg = gpu["id"].astype(np.uint64) << np.uint64(32) | gpu["lineage"].astype(np.uint64)
+    kr = ref["id"].astype(np.uint64) << np.uint64(32) | ref["lineage"].astype(np.uint64)
+    common, ig, ir = np.intersect1d(kg, kr, return_indices=True)
+    only = int(len(kg) + len(kr) - 2 * len(common))
+    gpu = {k: v[ig] for k, v in gpu.items()}
+    ref = {k: v[ir] for k, v in ref.items()}
+    scale = np.maximum(ref["L"], 1.0)
+    dx = np.linalg.norm(gpu["x"] - ref["x"], axis=1) / scale
+    cosang = np.clip((gpu["u"] * ref["u"]).sum(1), -1.0, 1.0)
+    dang = np.degrees(np.arccos(cosang))
+    dE = np.abs(gpu["E"] / ref["E"] - 1.0)
+    dL = np.abs(gpu["L"] / ref["L"] - 1.0)
+
+    def q(v):
+        return {"median": float(np.median(v)), "p99": float(np.quantile(v, 0.99)),
+                "max": float(np.max(v))}
+
+    ints = {k: int(np.sum(gpu[k] != ref[k])) for k in ("status", "A", "Z", "m", "nsteps")}
+    th_g = np.degrees(np.arccos(np.clip((gpu["u"] * gpu["u0"]).sum(1), -1, 1)))
+    th_r = np.degrees(np.arccos(np.clip((ref["u"] * ref["u0"]).sum(1), -1, 1)))
+    hg = np.histogram(th_g, bins=36, range=(0, 180))[0] / len(th_g)
+    hr = np.histogram(th_r, bins=36, range=(0, 180))[0] / len(th_r)
+    return {"records_compared": int(len(ref["id"])), "records_in_one_only": only,
+            "position_rel": q(dx), "direction_deg": q(dang),
+            "energy_rel": q(dE), "length_rel": q(dL), "integer_mismatches": ints,
+            "deflection_hist_distance": float(0.5 * np.abs(hg - hr).sum())}
+
+
+if __name__ == "__main__":
+    main()

@@ -75,9 +75,10 @@ typedef struct {
 
 /* Kernel launch shape of the persistent propagation kernel. */
 typedef struct {
-    int32_t block;            /* threads per block: 64, 128, 256 or 512 */
-    int32_t blocks_per_cu;    /* persistent blocks per compute unit (>= 1) */
-    int32_t quantum;          /* attempts between refills of idle lanes (>= 1) */
+    int32_t block;            /* threads per block: 128 or 256 */
+    int32_t blocks_per_cu;    /* persistent blocks per compute unit (1..64) */
+    int32_t refill;           /* a wave claims new candidates once this many of its
+                                 64 lanes are idle (1..64) */
     int32_t layout;           /* CRP_LAYOUT_LINEAR or CRP_LAYOUT_CORNER */
 } crp_launch;
 

@@ -51,7 +51,7 @@ class Config(C.Structure):
 
 
 class Launch(C.Structure):
-    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("quantum", C.c_int32),
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill", C.c_int32),
                 ("layout", C.c_int32)]
 
     def as_dict(self):
@@ -325,8 +325,8 @@ class Context:
         return out
 
     # -- launch shape / tuning / timing ---------------------------------------
-    def set_launch(self, block=256, blocks_per_cu=4, quantum=4, layout=LAYOUT_LINEAR):
-        lch = Launch(block, blocks_per_cu, quantum, layout)
+    def set_launch(self, block=256, blocks_per_cu=4, refill=16, layout=LAYOUT_LINEAR):
+        lch = Launch(block, blocks_per_cu, refill, layout)
         self._check(self.L.crp_set_launch(self.h, C.byref(lch)))
 
     def get_launch(self):

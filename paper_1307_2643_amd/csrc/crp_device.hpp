@@ -244,6 +244,59 @@ __device__ inline void gather_corner(const GridView& g, const Cell& c, float v[8
     }
 }
 
+// Wave-cooperative gather of the 64 lanes' corner records (all 64 lanes of
+// the wave must call it together).  The records are fetched in two rounds of
+// 32: in each round the 32 records x 6 sixteen-byte chunks are spread over
+// the 64 lanes, so one load instruction touches about 11 records (cache lines
+// and address translations) instead of 64 and each line is read by 6
+// neighbouring lanes; the chunks reach their owner lane through `stage`, a
+// 32 x 24-float LDS area private to the wave.
+__device__ inline void gather_corner_coop(const float* corner, int64_t cell, float* stage,
+                                          float v[8][3])
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    float f[24];
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int idx = 64 * j + lane;            // 0..191
+            const int r = idx / 6, c = idx - 6 * r;   // record of the round, chunk
+            const int64_t rc = __shfl(cell, 32 * round + r);
+            const float4 w = ((const float4*)(corner + rc * 32))[c];
+            ((float4*)stage)[idx] = w;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((lane >> 5) == round) {
+            const float4* my = (const float4*)(stage + (lane & 31) * 24);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float4 w = my[q];
+                f[4 * q + 0] = w.x;
+                f[4 * q + 1] = w.y;
+                f[4 * q + 2] = w.z;
+                f[4 * q + 3] = w.w;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k][0] = f[3 * k + 0];
+        v[k][1] = f[3 * k + 1];
+        v[k][2] = f[3 * k + 2];
+    }
+}
+
+__device__ inline int64_t cell_index(const GridView& g, const Cell& c)
+{
+    return ((int64_t)c.i0[0] * g.n[1] + c.i0[1]) * g.n[2] + c.i0[2];
+}
+
 // FP64 weights and sums: w0 = 1 - t, w1 = t; weight (wx * wy) * wz.
 template <class GT>
 __device__ inline void interp_fp64(const double t[3], const GT v[8][3], double B[3])
@@ -281,41 +334,40 @@ __device__ inline void interp_fp32(const double t[3], const GT v[8][3], float B[
     }
 }
 
-// Field sources used by the stepper.  LAYOUT: 0 linear, 1 corner records.
+// Field sources used by the stepper.  LAYOUT: 0 linear, 1 corner records
+// (per lane), 2 corner records gathered cooperatively by the whole wave.
 template <class GT, int LAYOUT>
 struct GridField {
     GridView g;
+    float* stage = nullptr;   // LAYOUT 2: the wave's LDS staging area
+    __device__ inline void corners(const Cell& c, GT v[8][3]) const
+    {
+        if constexpr (LAYOUT == 2)
+            gather_corner_coop(g.corner, cell_index(g, c), stage, v);
+        else if constexpr (LAYOUT == 1)
+            gather_corner(g, c, v);
+        else
+            gather_linear<GT>(g, c, v);
+    }
     __device__ inline void fp64(const double p[3], double B[3]) const
     {
         const Cell c = locate(g, p);
-        if constexpr (LAYOUT == 1) {
-            float v[8][3];
-            gather_corner(g, c, v);
-            interp_fp64(c.t, v, B);
-        } else {
-            GT v[8][3];
-            gather_linear<GT>(g, c, v);
-            interp_fp64(c.t, v, B);
-        }
+        GT v[8][3];
+        corners(c, v);
+        interp_fp64(c.t, v, B);
     }
     __device__ inline void fp32(const double p[3], float B[3]) const
     {
         const Cell c = locate(g, p);
-        if constexpr (LAYOUT == 1) {
-            float v[8][3];
-            gather_corner(g, c, v);
-            interp_fp32(c.t, v, B);
-        } else {
-            GT v[8][3];
-            gather_linear<GT>(g, c, v);
-            float vf[8][3];
+        GT v[8][3];
+        corners(c, v);
+        float vf[8][3];
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < 8; ++k)
 #pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    vf[k][q] = (float)v[k][q];
-            interp_fp32(c.t, vf, B);
-        }
+            for (int q = 0; q < 3; ++q)
+                vf[k][q] = (float)v[k][q];
+        interp_fp32(c.t, vf, B);
     }
 };
 
@@ -460,6 +512,61 @@ __device__ inline double ck_attempt_mix(const F& field, double kappa, const doub
             x5[q] = x[q] + (double)s;
         else
             u5[q - 3] = (double)(u[q - 3] + s);
+    }
+    float e[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        float s = (float)CK::e0 * G[0][3 + q];
+        s = s + (float)CK::e2 * G[2][3 + q];
+        s = s + (float)CK::e3 * G[3][3 + q];
+        s = s + (float)CK::e4 * G[4][3 + q];
+        s = s + (float)CK::e5 * G[5][3 + q];
+        e[q] = s;
+    }
+    return (double)sqrtf(dot3f(e, e));
+}
+
+// Same attempt with the direction held in FP32 (the precision form stores u
+// in FP32, so this is the same arithmetic without the FP64 round trip).
+template <class F>
+__device__ inline double ck_attempt_mix_f(const F& field, double kappa, const double x[3],
+                                          const float u[3], double h, double x5[3],
+                                          float u5[3])
+{
+    const float hf = (float)h;
+    const float hk = (float)(h * kappa);
+    float G[6][6];
+    incr_fp32(field, hf, hk, x, u, G[0]);
+#pragma unroll
+    for (int i = 1; i < 6; ++i) {
+        float s[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            float acc = (float)CK::a[i][0] * G[0][q];
+#pragma unroll
+            for (int j = 1; j < i; ++j)
+                acc = acc + (float)CK::a[i][j] * G[j][q];
+            s[q] = acc;
+        }
+        double xs[3];
+        float us[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            xs[q] = x[q] + (double)s[q];
+            us[q] = u[q] + s[3 + q];
+        }
+        incr_fp32(field, hf, hk, xs, us, G[i]);
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        float s = (float)CK::b0 * G[0][q];
+        s = s + (float)CK::b2 * G[2][q];
+        s = s + (float)CK::b3 * G[3][q];
+        s = s + (float)CK::b5 * G[5][q];
+        if (q < 3)
+            x5[q] = x[q] + (double)s;
+        else
+            u5[q - 3] = u[q - 3] + s;
     }
     float e[3];
 #pragma unroll

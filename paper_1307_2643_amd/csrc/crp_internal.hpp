@@ -38,7 +38,9 @@ struct NeutralSoA {
 
 // Device counter block (all 64-bit, updated with device-scope atomics).
 struct DevCounters {
-    unsigned long long head, tail;          // queue claim / append cursors
+    unsigned long long head;                // claim cursor of slots written before the run
+    unsigned long long tail;                // append cursor (end of written slots)
+    unsigned long long head1;               // claim cursor of slots appended during the run
     unsigned long long fin_n, neu_n, park_n;
     unsigned long long steps, attempts, rejects, forced;
     unsigned long long events, null_events, inter_pi, inter_n;
@@ -73,7 +75,7 @@ struct PropParams {
     StepParams sp;
     int64_t max_cycles;          // <= 0: no limit
     unsigned long long tail0;    // slots below were written before the launch
-    int quantum;
+    int refill;                  // idle lanes that trigger a claim (1..64)
 };
 
 enum { MODE_FP64 = 0, MODE_MIX = 1 };

@@ -24,29 +24,6 @@ struct Cand {
     int A, Z;
 };
 
-__device__ inline void load_cand(const QueueSoA& q, int64_t i, Cand& c)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        c.x[a] = q.x[a * q.cap + i];
-        c.u[a] = q.u[a * q.cap + i];
-        c.u0[a] = q.u0[a * q.cap + i];
-    }
-    c.E = q.E[i];
-    c.L = q.L[i];
-    c.Lmax = q.Lmax[i];
-    c.hctrl = q.hctrl[i];
-    c.tau = q.tau[i];
-    c.E0 = q.E0[i];
-    c.id = q.id[i];
-    c.lineage = q.lineage[i];
-    c.m = q.m[i];
-    c.nsteps = q.nsteps[i];
-    c.nrej = q.nrej[i];
-    c.A = q.A[i];
-    c.Z = q.Z[i];
-}
-
 __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
 {
 #pragma unroll
@@ -70,100 +47,95 @@ __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
     q.Z[i] = c.Z;
 }
 
-__device__ inline void store_finished(const FinishedSoA& f, int64_t i, const Cand& c,
-                                      int status)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        f.x[a * f.cap + i] = c.x[a];
-        f.u[a * f.cap + i] = c.u[a];
-        f.u0[a * f.cap + i] = c.u0[a];
-    }
-    f.E[i] = c.E;
-    f.L[i] = c.L;
-    f.E0[i] = c.E0;
-    f.id[i] = c.id;
-    f.lineage[i] = c.lineage;
-    f.m[i] = c.m;
-    f.nsteps[i] = c.nsteps;
-    f.nrej[i] = c.nrej;
-    f.status[i] = status;
-    f.A[i] = c.A;
-    f.Z[i] = c.Z;
-}
-
-struct LaneCount {
-    uint32_t steps, attempts, rejects, forced;
-    uint32_t events, null_events, inter_pi, inter_n;
-    uint32_t charged_sec, neutral_sec;
-    uint32_t finished, observed, max_traj, energy_floor;
-    uint32_t queue_dropped, neutral_dropped;
+// Wave-uniform bookkeeping: each per-lane event of an iteration is counted
+// with a ballot, so the counters live in scalar registers.
+enum {
+    WC_STEPS = 0, WC_ATTEMPTS, WC_REJECTS, WC_FORCED, WC_EVENTS, WC_NULL, WC_PI, WC_N,
+    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_COUNT
+};
+enum : uint32_t {
+    EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_EVENT = 1u << 3,
+    EV_NULL = 1u << 4, EV_PI = 1u << 5, EV_N = 1u << 6, EV_FIN = 1u << 7, EV_OBS = 1u << 8,
+    EV_TRAJ = 1u << 9, EV_EFLOOR = 1u << 10, EV_QDROP = 1u << 11, EV_NDROP = 1u << 12
 };
 
-__device__ inline unsigned long long wave_sum(uint32_t v)
+__device__ inline unsigned long long count_bit(uint32_t ev, uint32_t bit)
 {
-    unsigned long long s = v;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        s += __shfl_xor(s, off);
-    return s;
+    return (unsigned long long)__popcll(__ballot((ev & bit) != 0u));
 }
 
-__device__ inline void flush_counts(DevCounters* cnt, const LaneCount& lc)
+// Adds a wave-uniform count to the block's LDS counter.
+__device__ inline void add_count(unsigned long long* bc, int i, unsigned long long v)
 {
-    const uint32_t* v = (const uint32_t*)&lc;
-    unsigned long long* d = &cnt->steps;
-    const int nf = (int)(sizeof(LaneCount) / sizeof(uint32_t));
-    // steps .. neutral_sec map to consecutive device fields; the rest below
-    unsigned long long sums[sizeof(LaneCount) / sizeof(uint32_t)];
-#pragma unroll
-    for (int i = 0; i < nf; ++i)
-        sums[i] = wave_sum(v[i]);
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int i = 0; i < 10; ++i)
-            if (sums[i])
-                atomicAdd(d + i, sums[i]);
-        if (sums[10])
-            atomicAdd(&cnt->finished, sums[10]);
-        if (sums[11])
-            atomicAdd(&cnt->observed, sums[11]);
-        if (sums[12])
-            atomicAdd(&cnt->max_traj, sums[12]);
-        if (sums[13])
-            atomicAdd(&cnt->energy_floor, sums[13]);
-        if (sums[14])
-            atomicAdd(&cnt->queue_dropped, sums[14]);
-        if (sums[15])
-            atomicAdd(&cnt->neutral_dropped, sums[15]);
+    if (v != 0ull && lane_id() == 0)
+        atomicAdd(bc + i, v);
+}
+
+__device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* bc)
+{
+    unsigned long long* dst[WC_COUNT] = {
+        &cnt->steps, &cnt->attempts, &cnt->rejects, &cnt->forced, &cnt->events,
+        &cnt->null_events, &cnt->inter_pi, &cnt->inter_n, &cnt->finished, &cnt->observed,
+        &cnt->max_traj, &cnt->energy_floor, &cnt->queue_dropped, &cnt->neutral_dropped};
+    const int i = (int)threadIdx.x;
+    if (i < WC_COUNT && bc[i] != 0ull) {
+        atomicAdd(dst[i], bc[i]);
+        // every pion-like event emits one neutral secondary, every nucleon-loss
+        // event one charged secondary
+        if (i == WC_PI)
+            atomicAdd(&cnt->neutral_sec, bc[i]);
+        if (i == WC_N)
+            atomicAdd(&cnt->charged_sec, bc[i]);
     }
 }
 
-// Claims up to `want` queue slots in [head, min(tail, cap)).
-__device__ inline void claim_slots(DevCounters* cnt, unsigned long long cap, int want,
-                                   unsigned long long& base, unsigned long long& take)
+// Claims up to `want` slots: first from the region written before the launch
+// with one atomicAdd (overshoot past tail0 is harmless there), then from the
+// region appended during the run with a compare-and-swap on its own cursor.
+__device__ inline void claim_slots(DevCounters* cnt, unsigned long long tail0,
+                                   unsigned long long cap, int want, bool try_initial,
+                                   unsigned long long& base, unsigned long long& take,
+                                   bool& initial_left)
 {
-    unsigned long long h = __hip_atomic_load(&cnt->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    take = 0;
+    base = 0;
+    initial_left = false;
+    if (try_initial) {
+        const unsigned long long b = atomicAdd(&cnt->head, (unsigned long long)want);
+        if (b < tail0) {
+            base = b;
+            take = tail0 - b < (unsigned long long)want ? tail0 - b : (unsigned long long)want;
+            initial_left = b + take < tail0;
+            return;
+        }
+    }
+    unsigned long long h = __hip_atomic_load(&cnt->head1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         unsigned long long t =
             __hip_atomic_load(&cnt->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (t > cap)
             t = cap;
-        if (h >= t) {
-            base = h;
-            take = 0;
+        if (h >= t)
             return;
-        }
         unsigned long long n = t - h;
         if (n > (unsigned long long)want)
             n = (unsigned long long)want;
-        if (__hip_atomic_compare_exchange_strong(&cnt->head, &h, h + n, __ATOMIC_RELAXED,
+        if (__hip_atomic_compare_exchange_strong(&cnt->head1, &h, h + n, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
             base = h;
             take = n;
             return;
         }
     }
+}
+
+__device__ inline bool appended_available(DevCounters* cnt, unsigned long long cap)
+{
+    unsigned long long h = __hip_atomic_load(&cnt->head1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long t = __hip_atomic_load(&cnt->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (t > cap)
+        t = cap;
+    return h < t;
 }
 
 // Waits until a slot appended during this run is published.  The producer
@@ -182,65 +154,154 @@ __device__ inline bool wait_published(uint32_t* flag, DevCounters* cnt)
     return false;
 }
 
-template <int MODE, class GT, int LAYOUT>
-__global__ void __launch_bounds__(512) k_propagate(PropParams P)
+// Per-lane candidate state that is not needed inside a Cash-Karp attempt,
+// kept in LDS (structure of arrays over the block's lanes) so that only the
+// position, direction, step and curvature occupy registers in the attempt.
+template <int BS>
+struct LaneShared {
+    double E[BS], L[BS], Lmax[BS], hctrl[BS], tau[BS], R[BS], beta[BS];
+    uint32_t id[BS], lineage[BS], m[BS], nsteps[BS], nrej[BS], cycles[BS];
+    uint32_t azf[BS];   // A | Z << 8 | step-limit flag << 16
+};
+
+__device__ inline int unpack_A(uint32_t v) { return (int)(v & 0xffu); }
+__device__ inline int unpack_Z(uint32_t v) { return (int)((v >> 8) & 0xffu); }
+__device__ inline int unpack_flag(uint32_t v) { return (int)((v >> 16) & 0xffu); }
+__device__ inline uint32_t pack_azf(int A, int Z, int flag)
 {
-    extern __shared__ double lds_tab[];
-    const int ntab = P.tab.n;
-    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
-        lds_tab[i] = P.tab.e[i];
-        lds_tab[ntab + i] = P.tab.v[0][i];
-        lds_tab[2 * ntab + i] = P.tab.v[1][i];
-        lds_tab[3 * ntab + i] = P.tab.v[2][i];
+    return (uint32_t)A | ((uint32_t)Z << 8) | ((uint32_t)flag << 16);
+}
+
+// Hides a pointer's value from the optimiser so that loads through it stay
+// inside the (rarely taken) branch that needs them instead of being hoisted
+// out of the persistent loop into scalar registers.
+template <class T>
+__device__ inline const T* opaque(const T* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+template <int MODE>
+struct DirType {
+    using T = double;
+};
+template <>
+struct DirType<MODE_MIX> {
+    using T = float;
+};
+
+// Minimum waves per SIMD the register allocation targets (occupancy vs
+// spills), per precision form.
+#ifndef CRP_WAVES_MIX
+#define CRP_WAVES_MIX 2
+#endif
+#ifndef CRP_WAVES_FP64
+#define CRP_WAVES_FP64 2
+#endif
+
+template <int MODE, class GT, int LAYOUT, int BS>
+__global__ void __launch_bounds__(BS, MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64)
+    k_propagate(const PropParams* __restrict__ PP)
+{
+    using UT = typename DirType<MODE>::T;   // direction storage: FP64 or FP32
+    extern __shared__ double lds[];           // interaction tables
+    __shared__ LaneShared<BS> S;              // per-lane cold state
+    __shared__ unsigned long long bc[WC_COUNT];   // block bookkeeping counters
+    // LDS staging of the wave-cooperative corner gather (LAYOUT 2 only)
+    __shared__ float4 stage_mem[LAYOUT == 2 ? BS / 64 * 192 : 1];
+    const int t = (int)threadIdx.x;
+    const int ntab = PP->tab.n;
+    {
+        const TableParams tp = PP->tab;
+        for (int i = t; i < ntab; i += BS) {
+            lds[i] = tp.e[i];
+            lds[ntab + i] = tp.v[0][i];
+            lds[2 * ntab + i] = tp.v[1][i];
+            lds[3 * ntab + i] = tp.v[2][i];
+        }
     }
+    if (t < WC_COUNT)
+        bc[t] = 0ull;
     __syncthreads();
     TableView T;
-    T.e = lds_tab;
-    T.v[0] = lds_tab + ntab;
-    T.v[1] = lds_tab + 2 * ntab;
-    T.v[2] = lds_tab + 3 * ntab;
+    T.e = lds;
+    T.v[0] = lds + ntab;
+    T.v[1] = lds + 2 * ntab;
+    T.v[2] = lds + 3 * ntab;
     T.n = ntab;
-    T.lg0 = P.tab.lg0;
-    T.scale = P.tab.scale;
+    T.lg0 = PP->tab.lg0;
+    T.scale = PP->tab.scale;
 
-    const GridField<GT, LAYOUT> F{P.grid};
-    const StepParams S = P.sp;
+    GridField<GT, LAYOUT> F;
+    F.g = PP->grid;
+    F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * 192 : 0));
+    const StepParams sp = PP->sp;
     const int lane = lane_id();
-    const unsigned long long qcap = (unsigned long long)P.q.cap;
+    const unsigned long long qcap = (unsigned long long)PP->q.cap;
+    const unsigned long long tail0 = PP->tail0;
+    const int refill = PP->refill;
+    const int64_t max_cycles = PP->max_cycles;
+    DevCounters* const cnt = PP->cnt;
 
-    bool active = false;
-    bool fresh = true;
-    Cand c;
-    int64_t cycles = 0;
-    double h = 0.0, kappa = 0.0, R = 0.0, beta = 0.0;
-    int flag = LIM_CTRL;
-    LaneCount lc = {};
-    int iter = 0;
-    bool dry = false;
+    // registers through the attempt: position, direction, step, curvature
+    double x[3] = {0.0, 0.0, 0.0};
+    UT u[3] = {0, 0, 0};
+    double h = 0.0, kappa = 0.0;
+    int64_t slot = 0;
+    bool active = false, fresh = true;
+    bool dry = false, initial_left = true;
+    uint32_t iter = 0;
 
     for (;;) {
         // ---- refill idle lanes from the queue -------------------------------
         const uint64_t idle = __ballot(!active);
-        if (idle != 0ull && (idle == ~0ull || (!dry && iter % P.quantum == 0))) {
-            const int want = __popcll(idle);
-            unsigned long long base = 0, take = 0;
+        const int nidle = __popcll(idle);
+        if (dry && nidle >= refill && (iter & 63u) == 0u && idle != ~0ull) {
+            bool avail = false;
             if (lane == 0)
-                claim_slots(P.cnt, qcap, want, base, take);
+                avail = appended_available(cnt, qcap);
+            if (__shfl((int)avail, 0))
+                dry = false;
+        }
+        if (idle == ~0ull || (!dry && nidle >= refill)) {
+            unsigned long long base = 0, take = 0;
+            bool left = false;
+            if (lane == 0)
+                claim_slots(cnt, tail0, qcap, nidle, initial_left, base, take, left);
             base = __shfl(base, 0);
             take = __shfl(take, 0);
-            dry = take < (unsigned long long)want;
+            initial_left = __shfl((int)left, 0) != 0;
+            dry = take < (unsigned long long)nidle;
             if (!active) {
                 const int rank = lanes_below(idle);
                 if ((unsigned long long)rank < take) {
-                    const unsigned long long slot = base + (unsigned long long)rank;
+                    const unsigned long long sl = base + (unsigned long long)rank;
                     bool ok = true;
-                    if (slot >= P.tail0)
-                        ok = wait_published(P.q.ready + slot, P.cnt);
+                    if (sl >= tail0)
+                        ok = wait_published(opaque(PP)->q.ready + sl, cnt);
                     if (ok) {
-                        load_cand(P.q, (int64_t)slot, c);
+                        const QueueSoA& q = opaque(PP)->q;
+                        slot = (int64_t)sl;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            x[a] = q.x[a * q.cap + slot];
+                            u[a] = (UT)q.u[a * q.cap + slot];
+                        }
+                        S.E[t] = q.E[slot];
+                        S.L[t] = q.L[slot];
+                        S.Lmax[t] = q.Lmax[slot];
+                        S.hctrl[t] = q.hctrl[slot];
+                        S.tau[t] = q.tau[slot];
+                        S.id[t] = q.id[slot];
+                        S.lineage[t] = q.lineage[slot];
+                        S.m[t] = q.m[slot];
+                        S.nsteps[t] = q.nsteps[slot];
+                        S.nrej[t] = q.nrej[slot];
+                        S.cycles[t] = 0u;
+                        S.azf[t] = pack_azf(q.A[slot], q.Z[slot], LIM_CTRL);
                         active = true;
                         fresh = true;
-                        cycles = 0;
                     }
                 }
             }
@@ -251,27 +312,30 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
 
         // ---- start of a cycle: rates and step proposal -----------------------
         if (active && fresh) {
-            const Rates rt = species_rates(T, c.A, c.Z, c.E);
-            R = rt.r;
-            beta = rt.beta;
-            h = c.hctrl;
-            flag = LIM_CTRL;
-            if (c.Lmax - c.L < h) {
-                h = c.Lmax - c.L;
+            const uint32_t azf = S.azf[t];
+            const int A = unpack_A(azf), Z = unpack_Z(azf);
+            const double E = S.E[t];
+            const Rates rt = species_rates(T, A, Z, E);
+            const double R = rt.r, beta = rt.beta;
+            const double L = S.L[t], Lmax = S.Lmax[t], tau = S.tau[t];
+            int flag = LIM_CTRL;
+            h = S.hctrl[t];
+            if (Lmax - L < h) {
+                h = Lmax - L;
                 flag = LIM_TRAJ;
             }
-            if (R > 0.0 && c.tau / R < h) {
-                h = c.tau / R;
+            if (R > 0.0 && tau / R < h) {
+                h = tau / R;
                 flag = LIM_INTER;
             }
-            if (beta > 0.0 && S.eps_loss / beta < h) {
-                h = S.eps_loss / beta;
+            if (beta > 0.0 && sp.eps_loss / beta < h) {
+                h = sp.eps_loss / beta;
                 flag = LIM_LOSS;
             }
-            if (S.obs_r > 0.0) {
-                const double d[3] = {c.x[0] - S.obs[0], c.x[1] - S.obs[1], c.x[2] - S.obs[2]};
+            if (sp.obs_r > 0.0) {
+                const double d[3] = {x[0] - sp.obs[0], x[1] - sp.obs[1], x[2] - sp.obs[2]};
                 const double dist = sqrt(dot3(d, d));
-                const double half = 0.5 * S.obs_r;
+                const double half = 0.5 * sp.obs_r;
                 double hob = dist - half;
                 if (hob < half)
                     hob = half;
@@ -280,18 +344,27 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
                     flag = LIM_OBS;
                 }
             }
-            kappa = ((double)c.Z * kC) / c.E;
+            kappa = ((double)Z * kC) / E;
+            S.R[t] = R;
+            S.beta[t] = beta;
+            S.azf[t] = pack_azf(A, Z, flag);
             fresh = false;
         }
 
-        // ---- one Cash-Karp attempt and, if accepted, the rest of the cycle ---
-        bool fin = false, neutral = false, spawn = false, park = false;
+        // ---- one Cash-Karp attempt -------------------------------------------
+        uint32_t ev = 0u;
         int status = ST_ACTIVE;
         double dE = 0.0, Esec = 0.0;
-        if (active) {
-            double x5[3], u5[3], err;
+        bool neutral = false, spawn = false, park = false;
+        // with the cooperative gather every lane of the wave takes part in the
+        // attempt (idle lanes on a harmless cell); results are used only by
+        // busy lanes
+        double x5[3];
+        UT u5[3];
+        double err = 0.0;
+        if (active || LAYOUT == 2) {
             if constexpr (MODE == MODE_FP64) {
-                const double y[6] = {c.x[0], c.x[1], c.x[2], c.u[0], c.u[1], c.u[2]};
+                const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
                 err = ck_attempt_fp64(F, kappa, y, h, y5);
 #pragma unroll
@@ -300,13 +373,16 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
                     u5[q] = y5[3 + q];
                 }
             } else {
-                err = ck_attempt_mix(F, kappa, c.x, c.u, h, x5, u5);
+                err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5);
             }
-            lc.attempts++;
-            const double r = err / S.tol;
-            if (r <= 1.0 || h <= S.hmin) {
+        }
+        if (active) {
+            ev |= EV_ATTEMPT;
+            const double r = err / sp.tol;
+            if (r <= 1.0 || h <= sp.hmin) {
+                ev |= EV_ACCEPT;
                 if (r > 1.0)
-                    lc.forced++;
+                    ev |= EV_FORCED;
                 double fac = 5.0;
                 if (r > 0.0) {
                     fac = (double)ctrl_k(r) / 1024.0;
@@ -314,115 +390,114 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
                         fac = 5.0;
                 }
                 double hn = h * fac;
-                if (hn < S.hmin)
-                    hn = S.hmin;
-                if (hn > S.hmax)
-                    hn = S.hmax;
-                c.hctrl = hn;
+                if (hn < sp.hmin)
+                    hn = sp.hmin;
+                if (hn > sp.hmax)
+                    hn = sp.hmax;
+                S.hctrl[t] = hn;
                 // integration module: position, direction, trajectory length
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
-                    c.x[q] = x5[q];
-                if (S.renorm) {
+                    x[q] = x5[q];
+                if (sp.renorm) {
                     if constexpr (MODE == MODE_FP64) {
                         const double nrm = sqrt(dot3(u5, u5));
 #pragma unroll
                         for (int q = 0; q < 3; ++q)
-                            c.u[q] = u5[q] / nrm;
+                            u[q] = u5[q] / nrm;
                     } else {
-                        const float uf[3] = {(float)u5[0], (float)u5[1], (float)u5[2]};
-                        const float nrm = sqrtf(dot3f(uf, uf));
+                        const float nrm = sqrtf(dot3f(u5, u5));
 #pragma unroll
                         for (int q = 0; q < 3; ++q)
-                            c.u[q] = (double)(uf[q] / nrm);
+                            u[q] = u5[q] / nrm;
                     }
                 } else {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
-                        c.u[q] = u5[q];
+                        u[q] = u5[q];
                 }
-                c.L = c.L + h;
-                c.nsteps++;
-                lc.steps++;
+                const double L = S.L[t] + h;
+                S.L[t] = L;
+                S.nsteps[t] += 1u;
                 // continuous loss: (2,2) Pade form of exp(-beta h)
+                double E = S.E[t];
                 {
-                    const double z = beta * h;
+                    const double z = S.beta[t] * h;
                     const double z2 = z * z;
                     const double num = (12.0 - 6.0 * z) + z2;
                     const double den = (12.0 + 6.0 * z) + z2;
-                    c.E = c.E * (num / den);
+                    E = E * (num / den);
                 }
                 // stochastic interactions: optical-depth clock
-                c.tau = c.tau - R * h;
-                if (flag == LIM_INTER || c.tau <= 0.0) {
-                    c.m++;
-                    const U64x4 w = event_draw(S.seed, c.id, c.lineage, c.m);
-                    const double Eint = c.E;
-                    const Rates ri = species_rates(T, c.A, c.Z, Eint);
+                const uint32_t azf = S.azf[t];
+                const int flag = unpack_flag(azf);
+                double tau = S.tau[t] - S.R[t] * h;
+                if (flag == LIM_INTER || tau <= 0.0) {
+                    const uint32_t m = S.m[t] + 1u;
+                    S.m[t] = m;
+                    const U64x4 w = event_draw(sp.seed, S.id[t], S.lineage[t], m);
+                    int A = unpack_A(azf), Z = unpack_Z(azf);
+                    const double Eint = E;
+                    const Rates ri = species_rates(T, A, Z, Eint);
                     const double Ptot = ri.rpi + ri.rn;
-                    lc.events++;
+                    ev |= EV_EVENT;
                     if (Ptot > 0.0) {
                         const double Uc = unit_uniform(w.w[0]);
                         if (Uc * Ptot < ri.rpi) {
-                            dE = (S.kappa_pi * Eint) / (double)c.A;
-                            c.E = Eint - dE;
-                            lc.inter_pi++;
-                            lc.neutral_sec++;
+                            dE = (sp.kappa_pi * Eint) / (double)A;
+                            E = Eint - dE;
+                            ev |= EV_PI;
                             neutral = true;
                         } else {
-                            const int pout = (2 * c.Z > c.A) ? 1 : 0;
-                            const int Aold = c.A;
-                            Esec = Eint / (double)Aold;
-                            c.Z -= pout;
-                            c.A -= 1;
-                            c.E = Eint - Esec;
-                            lc.inter_n++;
-                            lc.charged_sec++;
+                            const int pout = (2 * Z > A) ? 1 : 0;
+                            Esec = Eint / (double)A;
+                            Z -= pout;
+                            A -= 1;
+                            E = Eint - Esec;
+                            S.azf[t] = pack_azf(A, Z, flag);
+                            ev |= EV_N;
                             spawn = true;
                         }
                     } else {
-                        lc.null_events++;
+                        ev |= EV_NULL;
                     }
                     // all interaction state is reset after an interaction
-                    c.tau = optical_depth(w.w[1]);
+                    tau = optical_depth(w.w[1]);
                 }
+                S.E[t] = E;
+                S.tau[t] = tau;
                 // boundary and observer modules, checked after the cycle
-                ++cycles;
-                if (S.obs_r > 0.0) {
-                    const double d[3] = {c.x[0] - S.obs[0], c.x[1] - S.obs[1],
-                                         c.x[2] - S.obs[2]};
-                    if (sqrt(dot3(d, d)) <= S.obs_r)
+                const uint32_t cyc = S.cycles[t] + 1u;
+                S.cycles[t] = cyc;
+                if (sp.obs_r > 0.0) {
+                    const double d[3] = {x[0] - sp.obs[0], x[1] - sp.obs[1], x[2] - sp.obs[2]};
+                    if (sqrt(dot3(d, d)) <= sp.obs_r)
                         status = ST_OBSERVED;
                 }
-                if (status == ST_ACTIVE && (flag == LIM_TRAJ || c.L >= c.Lmax))
+                if (status == ST_ACTIVE && (flag == LIM_TRAJ || L >= S.Lmax[t]))
                     status = ST_MAX_TRAJ;
-                if (status == ST_ACTIVE && c.E < S.e_floor)
+                if (status == ST_ACTIVE && E < sp.e_floor)
                     status = ST_ENERGY_FLOOR;
                 if (status != ST_ACTIVE) {
-                    fin = true;
-                    lc.finished++;
-                    if (status == ST_OBSERVED)
-                        lc.observed++;
-                    else if (status == ST_MAX_TRAJ)
-                        lc.max_traj++;
-                    else
-                        lc.energy_floor++;
-                } else if (P.max_cycles > 0 && cycles >= P.max_cycles) {
+                    ev |= EV_FIN;
+                    ev |= status == ST_OBSERVED ? EV_OBS
+                                                : (status == ST_MAX_TRAJ ? EV_TRAJ : EV_EFLOOR);
+                } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
                     park = true;
                 }
                 fresh = true;
             } else {
-                lc.rejects++;
-                c.nrej++;
+                S.nrej[t] += 1u;
                 double fac = (double)ctrl_k(r) / 1024.0;
                 if (fac < 0.1)
                     fac = 0.1;
                 h = h * fac;
-                if (h < S.hmin)
-                    h = S.hmin;
-                flag = LIM_CTRL;
+                if (h < sp.hmin)
+                    h = sp.hmin;
+                S.azf[t] = (S.azf[t] & 0xffffu) | ((uint32_t)LIM_CTRL << 16);
             }
         }
+        const bool fin = (ev & EV_FIN) != 0u;
 
         // ---- appends: one atomic per wave for each kind ----------------------
         {
@@ -430,24 +505,25 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
             if (mk) {
                 unsigned long long base = 0;
                 if (lane == 0)
-                    base = atomicAdd(&P.cnt->neu_n, (unsigned long long)__popcll(mk));
+                    base = atomicAdd(&cnt->neu_n, (unsigned long long)__popcll(mk));
                 base = __shfl(base, 0);
                 if (neutral) {
+                    const NeutralSoA& nq = opaque(PP)->neu;
                     const unsigned long long i = base + (unsigned long long)lanes_below(mk);
-                    if (i < (unsigned long long)P.neu.cap) {
+                    if (i < (unsigned long long)nq.cap) {
                         const int64_t k = (int64_t)i;
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
-                            P.neu.x[a * P.neu.cap + k] = c.x[a];
-                            P.neu.u[a * P.neu.cap + k] = c.u[a];
+                            nq.x[a * nq.cap + k] = x[a];
+                            nq.u[a * nq.cap + k] = (double)u[a];
                         }
-                        P.neu.E[k] = dE;
-                        P.neu.id[k] = c.id;
-                        P.neu.lineage[k] = c.lineage;
-                        P.neu.m[k] = c.m;
-                        P.neu.chan[k] = 0;
+                        nq.E[k] = dE;
+                        nq.id[k] = S.id[t];
+                        nq.lineage[k] = S.lineage[t];
+                        nq.m[k] = S.m[t];
+                        nq.chan[k] = 0;
                     } else {
-                        lc.neutral_dropped++;
+                        ev |= EV_NDROP;
                     }
                 }
             }
@@ -457,36 +533,37 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
             if (mk) {
                 unsigned long long base = 0;
                 if (lane == 0)
-                    base = atomicAdd(&P.cnt->tail, (unsigned long long)__popcll(mk));
+                    base = atomicAdd(&cnt->tail, (unsigned long long)__popcll(mk));
                 base = __shfl(base, 0);
                 if (spawn) {
                     const unsigned long long i = base + (unsigned long long)lanes_below(mk);
                     if (i < qcap) {
-                        Cand s;
+                        const QueueSoA& q = opaque(PP)->q;
+                        const int64_t k = (int64_t)i;
+                        const uint32_t id = S.id[t], lin = S.m[t];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
-                            s.x[a] = c.x[a];
-                            s.u[a] = c.u[a];
-                            s.u0[a] = c.u0[a];
+                            q.x[a * q.cap + k] = x[a];
+                            q.u[a * q.cap + k] = (double)u[a];
+                            q.u0[a * q.cap + k] = q.u0[a * q.cap + slot];
                         }
-                        s.E = Esec;
-                        s.L = c.L;
-                        s.Lmax = c.Lmax;
-                        s.hctrl = S.hmin;
-                        s.E0 = c.E0;
-                        s.id = c.id;
-                        s.lineage = c.m;
-                        s.m = 0;
-                        s.nsteps = 0;
-                        s.nrej = 0;
-                        s.A = 1;
-                        s.Z = 1;
-                        s.tau = optical_depth(event_draw(S.seed, s.id, s.lineage, 0).w[1]);
-                        store_cand(P.q, (int64_t)i, s);
-                        __hip_atomic_store(P.q.ready + i, 1u, __ATOMIC_RELEASE,
+                        q.E[k] = Esec;
+                        q.L[k] = S.L[t];
+                        q.Lmax[k] = S.Lmax[t];
+                        q.hctrl[k] = sp.hmin;
+                        q.E0[k] = q.E0[slot];
+                        q.id[k] = id;
+                        q.lineage[k] = lin;
+                        q.m[k] = 0u;
+                        q.nsteps[k] = 0u;
+                        q.nrej[k] = 0u;
+                        q.A[k] = 1;
+                        q.Z[k] = 1;
+                        q.tau[k] = optical_depth(event_draw(sp.seed, id, lin, 0u).w[1]);
+                        __hip_atomic_store(q.ready + i, 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     } else {
-                        lc.queue_dropped++;
+                        ev |= EV_QDROP;
                     }
                 }
             }
@@ -496,12 +573,32 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
             if (mk) {
                 unsigned long long base = 0;
                 if (lane == 0)
-                    base = atomicAdd(&P.cnt->fin_n, (unsigned long long)__popcll(mk));
+                    base = atomicAdd(&cnt->fin_n, (unsigned long long)__popcll(mk));
                 base = __shfl(base, 0);
                 if (fin) {
                     const unsigned long long i = base + (unsigned long long)lanes_below(mk);
-                    if (i < (unsigned long long)P.fin.cap)
-                        store_finished(P.fin, (int64_t)i, c, status);
+                    const PropParams* Q = opaque(PP);
+                    if (i < (unsigned long long)Q->fin.cap) {
+                        const FinishedSoA& f = Q->fin;
+                        const int64_t k = (int64_t)i;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            f.x[a * f.cap + k] = x[a];
+                            f.u[a * f.cap + k] = (double)u[a];
+                            f.u0[a * f.cap + k] = Q->q.u0[a * Q->q.cap + slot];
+                        }
+                        f.E[k] = S.E[t];
+                        f.L[k] = S.L[t];
+                        f.E0[k] = Q->q.E0[slot];
+                        f.id[k] = S.id[t];
+                        f.lineage[k] = S.lineage[t];
+                        f.m[k] = S.m[t];
+                        f.nsteps[k] = S.nsteps[t];
+                        f.nrej[k] = S.nrej[t];
+                        f.status[k] = status;
+                        f.A[k] = unpack_A(S.azf[t]);
+                        f.Z[k] = unpack_Z(S.azf[t]);
+                    }
                     active = false;
                 }
             }
@@ -511,28 +608,77 @@ __global__ void __launch_bounds__(512) k_propagate(PropParams P)
             if (mk) {
                 unsigned long long base = 0;
                 if (lane == 0)
-                    base = atomicAdd(&P.cnt->park_n, (unsigned long long)__popcll(mk));
+                    base = atomicAdd(&cnt->park_n, (unsigned long long)__popcll(mk));
                 base = __shfl(base, 0);
                 if (park) {
                     const unsigned long long i = base + (unsigned long long)lanes_below(mk);
-                    if (i < (unsigned long long)P.park.cap)
-                        store_cand(P.park, (int64_t)i, c);
+                    const PropParams* Q = opaque(PP);
+                    if (i < (unsigned long long)Q->park.cap) {
+                        const QueueSoA& pq = Q->park;
+                        const int64_t k = (int64_t)i;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            pq.x[a * pq.cap + k] = x[a];
+                            pq.u[a * pq.cap + k] = (double)u[a];
+                            pq.u0[a * pq.cap + k] = Q->q.u0[a * Q->q.cap + slot];
+                        }
+                        pq.E[k] = S.E[t];
+                        pq.L[k] = S.L[t];
+                        pq.Lmax[k] = S.Lmax[t];
+                        pq.hctrl[k] = S.hctrl[t];
+                        pq.tau[k] = S.tau[t];
+                        pq.E0[k] = Q->q.E0[slot];
+                        pq.id[k] = S.id[t];
+                        pq.lineage[k] = S.lineage[t];
+                        pq.m[k] = S.m[t];
+                        pq.nsteps[k] = S.nsteps[t];
+                        pq.nrej[k] = S.nrej[t];
+                        pq.A[k] = unpack_A(S.azf[t]);
+                        pq.Z[k] = unpack_Z(S.azf[t]);
+                    }
                     active = false;
                 }
             }
         }
+
+        // ---- bookkeeping: wave ballots into the block's LDS counters --------
+        {
+            const unsigned long long att = count_bit(ev, EV_ATTEMPT);
+            const unsigned long long acc = count_bit(ev, EV_ACCEPT);
+            add_count(bc, WC_ATTEMPTS, att);
+            add_count(bc, WC_STEPS, acc);
+            add_count(bc, WC_REJECTS, att - acc);
+            if (__ballot((ev & ~(EV_ATTEMPT | EV_ACCEPT)) != 0u)) {
+                add_count(bc, WC_FORCED, count_bit(ev, EV_FORCED));
+                add_count(bc, WC_EVENTS, count_bit(ev, EV_EVENT));
+                add_count(bc, WC_NULL, count_bit(ev, EV_NULL));
+                add_count(bc, WC_PI, count_bit(ev, EV_PI));
+                add_count(bc, WC_N, count_bit(ev, EV_N));
+                add_count(bc, WC_FINISHED, count_bit(ev, EV_FIN));
+                add_count(bc, WC_OBSERVED, count_bit(ev, EV_OBS));
+                add_count(bc, WC_MAXTRAJ, count_bit(ev, EV_TRAJ));
+                add_count(bc, WC_EFLOOR, count_bit(ev, EV_EFLOOR));
+                add_count(bc, WC_QDROP, count_bit(ev, EV_QDROP));
+                add_count(bc, WC_NDROP, count_bit(ev, EV_NDROP));
+            }
+        }
     }
-    flush_counts(P.cnt, lc);
+    __syncthreads();   // every wave of the block has left the loop
+    flush_counts(cnt, bc);
 }
 
 // Explicit instantiations: FP64 / mixed stage arithmetic x grid element type x
 // grid layout (corner records exist for FP32 grids only).
-template __global__ void k_propagate<MODE_FP64, double, 0>(PropParams);
-template __global__ void k_propagate<MODE_FP64, float, 0>(PropParams);
-template __global__ void k_propagate<MODE_FP64, float, 1>(PropParams);
-template __global__ void k_propagate<MODE_MIX, double, 0>(PropParams);
-template __global__ void k_propagate<MODE_MIX, float, 0>(PropParams);
-template __global__ void k_propagate<MODE_MIX, float, 1>(PropParams);
+#define CRP_INST(MODE, GT, LAYOUT)                                                   \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 128>(const PropParams*); \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 256>(const PropParams*);
+CRP_INST(MODE_FP64, double, 0)
+CRP_INST(MODE_FP64, float, 0)
+CRP_INST(MODE_FP64, float, 2)
+CRP_INST(MODE_MIX, double, 0)
+CRP_INST(MODE_MIX, float, 0)
+CRP_INST(MODE_MIX, float, 2)
+#undef CRP_INST
 
 // -------------------------------------------------------------------------
 // Injection: validation (first bad index) and slot initialisation.

@@ -21,8 +21,8 @@
 #include "crp_nf.hpp"
 
 namespace crp {
-template <int MODE, class GT, int LAYOUT>
-__global__ void k_propagate(PropParams P);
+template <int MODE, class GT, int LAYOUT, int BS>
+__global__ void k_propagate(const PropParams* PP);
 template <class GT, int LAYOUT>
 __global__ void k_eval_field(GridView g, int64_t n, const double* pos, double* B, int mode);
 __global__ void k_validate(int64_t n, const uint32_t* id, const int32_t* A, const int32_t* Z,
@@ -68,6 +68,7 @@ struct crp_ctx {
     void* nmem = nullptr;
     NeutralSoA neu;
     DevCounters* cnt = nullptr;
+    PropParams* d_params = nullptr;          // kernel parameter block (device)
     unsigned long long* scratch = nullptr;   // small device scratch (validation)
 
     int64_t pending = 0;
@@ -203,6 +204,23 @@ GridView make_view(const crp_ctx* ctx)
 
 int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
+// Dynamic LDS of the propagation kernel: the four tables (the per-lane state
+// kept out of registers is static LDS of the kernel).
+size_t lds_bytes(int ntab, int block)
+{
+    (void)block;
+    return (size_t)4 * ntab * sizeof(double);
+}
+
+template <int MODE, class GT, int LAYOUT>
+void launch_propagate(int nb, int bs, size_t lds, hipStream_t s, const PropParams* dp)
+{
+    if (bs == 128)
+        k_propagate<MODE, GT, LAYOUT, 128><<<nb, 128, lds, s>>>(dp);
+    else
+        k_propagate<MODE, GT, LAYOUT, 256><<<nb, 256, lds, s>>>(dp);
+}
+
 // Copies [start, start+k) of a planar [3][cap] device array into host [k][3].
 hipError_t copy_planar(double* host, const double* dev, int64_t cap, int64_t start, int64_t k,
                        hipStream_t s)
@@ -261,6 +279,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     std::memset(&init, 0, sizeof init);
     init.head = 0;
     init.tail = (unsigned long long)ctx->pending;
+    init.head1 = (unsigned long long)ctx->pending;
     init.fin_n = (unsigned long long)ctx->fin_unread;
     init.neu_n = (unsigned long long)ctx->neu_unread;
     HIPCHK(ctx, hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
@@ -293,7 +312,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.sp.renorm = c.renormalize;
     P.max_cycles = max_cycles;
     P.tail0 = (unsigned long long)ctx->pending;
-    P.quantum = ctx->launch.quantum;
+    P.refill = ctx->launch.refill;
 
     const int layout = ctx->launch.layout;
     if (layout == CRP_LAYOUT_CORNER) {
@@ -304,23 +323,26 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     }
     const int bs = ctx->launch.block;
     const int nb = ctx->num_cus * ctx->launch.blocks_per_cu;
-    const size_t lds = (size_t)4 * ctx->tab_n * sizeof(double);
+    const size_t lds = lds_bytes(ctx->tab_n, bs);
     const bool mix = c.precision == CRP_MIX;
     const bool f32 = ctx->grid_dtype == CRP_F32;
 
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_params, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
+    const PropParams* dp = ctx->d_params;
+    hipStream_t s = ctx->stream;
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     if (!mix && !f32)
-        k_propagate<MODE_FP64, double, 0><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp);
     else if (!mix && layout == CRP_LAYOUT_CORNER)
-        k_propagate<MODE_FP64, float, 1><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_FP64, float, 2>(nb, bs, lds, s, dp);
     else if (!mix)
-        k_propagate<MODE_FP64, float, 0><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_FP64, float, 0>(nb, bs, lds, s, dp);
     else if (!f32)
-        k_propagate<MODE_MIX, double, 0><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_MIX, double, 0>(nb, bs, lds, s, dp);
     else if (layout == CRP_LAYOUT_CORNER)
-        k_propagate<MODE_MIX, float, 1><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_MIX, float, 2>(nb, bs, lds, s, dp);
     else
-        k_propagate<MODE_MIX, float, 0><<<nb, bs, lds, ctx->stream>>>(P);
+        launch_propagate<MODE_MIX, float, 0>(nb, bs, lds, s, dp);
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(dc, ctx->cnt, sizeof *dc, hipMemcpyDeviceToHost, ctx->stream));
@@ -392,7 +414,7 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     std::memset(&ctx->totals, 0, sizeof ctx->totals);
     ctx->launch.block = 256;
     ctx->launch.blocks_per_cu = 4;
-    ctx->launch.quantum = 4;
+    ctx->launch.refill = 16;
     ctx->launch.layout = CRP_LAYOUT_LINEAR;
     auto bail = [&](crp_status st, const char* what, hipError_t e) {
         fprintf(stderr, "crp_create: %s: %s\n", what, hipGetErrorString(e));
@@ -437,6 +459,9 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     e = hipMalloc((void**)&ctx->cnt, sizeof(DevCounters));
     if (e != hipSuccess)
         return bail(CRP_ENOMEM, "counter allocation", e);
+    e = hipMalloc((void**)&ctx->d_params, sizeof(PropParams));
+    if (e != hipSuccess)
+        return bail(CRP_ENOMEM, "parameter block allocation", e);
     e = hipMalloc((void**)&ctx->scratch, 64);
     if (e != hipSuccess)
         return bail(CRP_ENOMEM, "scratch allocation", e);
@@ -460,6 +485,7 @@ void crp_destroy(crp_ctx* ctx)
         (void)hipDeviceSynchronize();
     nf_destroy(ctx->nf);
     for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, (void*)ctx->cnt,
+                    (void*)ctx->d_params,
                     (void*)ctx->scratch, ctx->grid_owned, (void*)ctx->tab, (void*)ctx->corner})
         if (p)
             (void)hipFree(p);
@@ -897,8 +923,8 @@ crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* l)
 {
     if (!ctx || !l)
         return CRP_EINVAL;
-    if (!(l->block == 64 || l->block == 128 || l->block == 256 || l->block == 512) ||
-        l->blocks_per_cu < 1 || l->blocks_per_cu > 64 || l->quantum < 1 || l->quantum > 4096 ||
+    if (!(l->block == 128 || l->block == 256) || l->blocks_per_cu < 1 ||
+        l->blocks_per_cu > 64 || l->refill < 1 || l->refill > 64 ||
         !(l->layout == CRP_LAYOUT_LINEAR || l->layout == CRP_LAYOUT_CORNER))
         return fail(ctx, CRP_EINVAL, "set_launch: invalid launch shape");
     if (l->layout == CRP_LAYOUT_CORNER && ctx->has_grid && ctx->grid_dtype != CRP_F32)
@@ -951,11 +977,11 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     std::vector<crp_launch> cands;
     const bool corner_ok = ctx->grid_dtype == CRP_F32;
     for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
-        for (int bs : {64, 128, 256, 512})
-            for (int bpc : {2, 4, 8})
-                for (int qn : {1, 8})
-                    if (bs * bpc <= 2048)
-                        cands.push_back(crp_launch{bs, bpc, qn, layout});
+        for (int bs : {128, 256})
+            for (int bpc : {4, 8, 16})
+                for (int rf : {8, 32})
+                    if (bs * bpc <= 2048 && bs * bpc >= 512)
+                        cands.push_back(crp_launch{bs, bpc, rf, layout});
     crp_launch bestl = orig;
     double bestr = -1.0;
     crp_status st = CRP_OK;
@@ -1004,10 +1030,10 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
         FILE* f = fopen(cache_path, "a");
         if (f) {
             fprintf(f, "%s grid=%lldx%lldx%lld dtype=%d precision=%d field=%d : block=%d "
-                       "blocks_per_cu=%d quantum=%d layout=%d steps_per_s=%.6e\n",
+                       "blocks_per_cu=%d refill=%d layout=%d steps_per_s=%.6e\n",
                     ctx->device_name.c_str(), (long long)ctx->gn[0], (long long)ctx->gn[1],
                     (long long)ctx->gn[2], ctx->grid_dtype, ctx->cfg.precision,
-                    ctx->cfg.field_mode, bestl.block, bestl.blocks_per_cu, bestl.quantum,
+                    ctx->cfg.field_mode, bestl.block, bestl.blocks_per_cu, bestl.refill,
                     bestl.layout, bestr);
             fclose(f);
         }
@@ -1258,13 +1284,14 @@ crp_status ctx_run_params(crp_ctx* ctx, int64_t max_cycles, PropParams* P, int* 
     P->sp.renorm = c.renormalize;
     P->max_cycles = max_cycles;
     P->tail0 = (unsigned long long)ctx->pending;
-    P->quantum = ctx->launch.quantum;
+    P->refill = ctx->launch.refill;
     *nb = ctx->num_cus * ctx->launch.blocks_per_cu;
     *bs = ctx->launch.block;
-    *lds = (size_t)4 * ctx->tab_n * sizeof(double);
+    *lds = lds_bytes(ctx->tab_n, *bs);
     DevCounters init;
     std::memset(&init, 0, sizeof init);
     init.tail = (unsigned long long)ctx->pending;
+    init.head1 = (unsigned long long)ctx->pending;
     init.fin_n = (unsigned long long)ctx->fin_unread;
     init.neu_n = (unsigned long long)ctx->neu_unread;
     hipError_t e = hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream);

@@ -241,9 +241,9 @@ def _assert_identical(a, b):
         assert np.array_equal(a[k], b[k]), k
 
 
-@pytest.mark.parametrize("launch", [dict(block=64, blocks_per_cu=1, quantum=1),
-                                    dict(block=512, blocks_per_cu=2, quantum=16),
-                                    dict(block=128, blocks_per_cu=8, quantum=3, layout=1)])
+@pytest.mark.parametrize("launch", [dict(block=128, blocks_per_cu=1, refill=1),
+                                    dict(block=256, blocks_per_cu=2, refill=64),
+                                    dict(block=128, blocks_per_cu=8, refill=3, layout=1)])
 def test_launch_shape_invariance(P, mixed_grid, launch):
     w = I.W_MIXED256
     grid = mixed_grid.astype(np.float32)
