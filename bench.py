@@ -132,10 +132,6 @@ def main():
         ctx.discard_finished()
         log(f"[bench] autotuner picked {tuned} ({rate:.3e} steps/s on the calibration "
             f"batch) in {time.time() - t0:.1f}s")
-    if args.layout is not None:
-        lch = ctx.get_launch()
-        lch["layout"] = args.layout
-        ctx.set_launch(**lch)
     launch = ctx.get_launch()
 
     def one_step(c):
