@@ -58,7 +58,8 @@ typedef struct {
                                  increments, field interpolation and direction in
                                  FP32; position, length, step control, energy and
                                  interactions in FP64. */
-    int32_t field_mode;       /* CRP_FIELD_GRID or CRP_FIELD_NEURAL (needs crp_nf_*) */
+    int32_t field_mode;       /* CRP_FIELD_GRID or CRP_FIELD_NEURAL (needs crp_nf_init and
+                                 precision CRP_MIX) */
     int32_t renormalize;      /* 1: |u| renormalised after every accepted step */
     int32_t device;           /* HIP device ordinal */
     double tol;               /* direction error tolerance per step */

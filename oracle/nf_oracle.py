@@ -101,3 +101,33 @@ def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[i] / (1.0 - b2 ** t)
         params[i] = params[i] - lr * mh / (np.sqrt(vh) + eps)
     return params, m, v
+
+
+NF_WIDTH = 128
+NF_NPARAM = 4 * (NF_WIDTH * NF_WIDTH + NF_WIDTH) + 3 * NF_WIDTH + 3
+
+
+def flatten(weights, biases):
+    """Flat parameter vector in the order W1, b1, ..., W4, b4, W5, b5."""
+    parts = []
+    for W, b in zip(weights, biases):
+        parts.append(np.asarray(W, np.float64).ravel())
+        parts.append(np.asarray(b, np.float64).ravel())
+    return np.concatenate(parts)
+
+
+def unflatten(params, width=NF_WIDTH, depth=4, nout=3):
+    """Inverse of flatten: lists of W [out][in] and b [out]."""
+    p = np.asarray(params, np.float64)
+    ws, bs = [], []
+    off = 0
+    fan = width
+    for _ in range(depth):
+        ws.append(p[off:off + width * fan].reshape(width, fan))
+        off += width * fan
+        bs.append(p[off:off + width])
+        off += width
+    ws.append(p[off:off + nout * width].reshape(nout, width))
+    off += nout * width
+    bs.append(p[off:off + nout])
+    return ws, bs

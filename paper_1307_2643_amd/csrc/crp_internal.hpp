@@ -64,6 +64,15 @@ struct StepParams {
     int renorm;
 };
 
+// Neural-field source of the propagation kernel: the network image in global
+// memory (staged into LDS by every block) and the grid period it was fit on.
+struct NFProp {
+    const char* img;
+    double origin[3];
+    double inv_box[3];
+    float b_scale;
+};
+
 struct PropParams {
     QueueSoA q;
     QueueSoA park;
@@ -76,6 +85,7 @@ struct PropParams {
     int64_t max_cycles;          // <= 0: no limit
     unsigned long long tail0;    // slots below were written before the launch
     int refill;                  // idle lanes that trigger a claim (1..64)
+    NFProp nf;                   // used by the neural-field instantiation only
 };
 
 enum { MODE_FP64 = 0, MODE_MIX = 1 };

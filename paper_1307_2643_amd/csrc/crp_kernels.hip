@@ -11,6 +11,7 @@
 // Finished records, neutral records, spawned secondaries and budget-parked
 // candidates are appended with one atomic per wave (ballot + prefix count).
 #include "crp_internal.hpp"
+#include "crp_nf_device.hpp"
 
 namespace crp {
 
@@ -182,6 +183,17 @@ __device__ inline const T* opaque(const T* p)
     return p;
 }
 
+// Field source of a layout: 0 linear grid, 1 corner records (per lane),
+// 2 corner records gathered by the whole wave, 3 the neural field.
+template <class GT, int LAYOUT>
+struct FieldOf {
+    using T = GridField<GT, LAYOUT>;
+};
+template <class GT>
+struct FieldOf<GT, 3> {
+    using T = NeuralFieldSrc;
+};
+
 template <int MODE>
 struct DirType {
     using T = double;
@@ -201,7 +213,7 @@ struct DirType<MODE_MIX> {
 #endif
 
 template <int MODE, class GT, int LAYOUT, int BS>
-__global__ void __launch_bounds__(BS, MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64)
+__global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64))
     k_propagate(const PropParams* __restrict__ PP)
 {
     using UT = typename DirType<MODE>::T;   // direction storage: FP64 or FP32
@@ -233,9 +245,17 @@ __global__ void __launch_bounds__(BS, MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAV
     T.lg0 = PP->tab.lg0;
     T.scale = PP->tab.scale;
 
-    GridField<GT, LAYOUT> F;
-    F.g = PP->grid;
-    F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * 192 : 0));
+    typename FieldOf<GT, LAYOUT>::T F;
+    if constexpr (LAYOUT == 3) {
+        // the network image follows the tables in dynamic LDS
+        char* img = (char*)(lds + 4 * ntab);
+        nf_stage_lds(img, PP->nf.img);
+        __syncthreads();
+        F.v = nf_view_lds(img, PP->nf.origin, PP->nf.inv_box, PP->nf.b_scale);
+    } else {
+        F.g = PP->grid;
+        F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * 192 : 0));
+    }
     const StepParams sp = PP->sp;
     const int lane = lane_id();
     const unsigned long long qcap = (unsigned long long)PP->q.cap;
@@ -362,7 +382,7 @@ __global__ void __launch_bounds__(BS, MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAV
         double x5[3];
         UT u5[3];
         double err = 0.0;
-        if (active || LAYOUT == 2) {
+        if (active || LAYOUT >= 2) {
             if constexpr (MODE == MODE_FP64) {
                 const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
@@ -679,6 +699,8 @@ CRP_INST(MODE_MIX, double, 0)
 CRP_INST(MODE_MIX, float, 0)
 CRP_INST(MODE_MIX, float, 2)
 #undef CRP_INST
+// neural field (precision form, one block of 256 per CU: the network fills LDS)
+template __global__ void k_propagate<MODE_MIX, float, 3, 256>(const PropParams*);
 
 // -------------------------------------------------------------------------
 // Injection: validation (first bad index) and slot initialisation.

@@ -25,12 +25,6 @@ crp_status nf_loss_grad(NeuralField* nf, const GridView& g, int64_t n, const dou
                         std::string& err);
 crp_status nf_train(NeuralField* nf, const GridView& g, int64_t steps, int64_t batch, double lr0,
                     double lr1, uint64_t seed, float* loss_out, std::string& err);
-crp_status nf_propagate(NeuralField* nf, crp_ctx* ctx, int64_t max_cycles, DevCounters* dc);
-
-// run bookkeeping shared with the grid path (defined in crp_runtime.hip)
-crp_status ctx_run_params(crp_ctx* ctx, int64_t max_cycles, PropParams* P, int* nb, int* bs,
-                          size_t* lds);
-hipStream_t ctx_stream(crp_ctx* ctx);
-void ctx_set_timing(crp_ctx* ctx, double ms, int64_t launches);
+void nf_prop_params(const NeuralField* nf, const GridView& g, NFProp* p);
 
 }  // namespace crp

@@ -1,0 +1,242 @@
+// Neural-field device routines (gfx950): a Fourier-feature MLP evaluated by
+// whole waves with bf16 MFMA (v_mfma_f32_32x32x16_bf16, FP32 accumulation).
+//
+// Network: xhat = frac((x - origin) / (n * spacing)); features
+// [cos 2pi F xhat, sin 2pi F xhat] (F: 64 integer vectors); four 128-wide ReLU
+// layers; a linear 3-output layer; B = b_scale * out.
+//
+// Wave layout.  A wave evaluates 64 points (its 64 lanes' points) as two
+// 32-column blocks.  Layer activations are the MFMA B operand: for column
+// block cb, lane l (group g = l / 32) holds, for point 32 cb + l % 32, the
+// features 16 m + 8 g + j (k-block m = 0..7, j = 0..7) as eight bf16x8.
+// Weight rows inside each 32-row tile are stored permuted (lambda below), so
+// that the accumulator registers of one layer are exactly the next layer's
+// B operand: no data movement between layers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int NF_WIDTH = 128;
+constexpr int NF_FEAT = 64;
+constexpr int NF_LAYER_PARAMS = NF_WIDTH * NF_WIDTH + NF_WIDTH;  // 16512
+constexpr int NF_W5 = 4 * NF_LAYER_PARAMS;                        // 66048
+constexpr int NF_B5 = NF_W5 + 3 * NF_WIDTH;                       // 66432
+constexpr int NF_NPARAM = NF_B5 + 3;                              // 66435
+
+// LDS image of the network (bf16 weights, FP32 biases, FP32 frequencies).
+constexpr int NF_IMG_LAYER = NF_WIDTH * NF_WIDTH;     // bf16 elements per layer
+constexpr size_t NF_LDS_BYTES = 4 * NF_IMG_LAYER * 2   // W1..W4 images
+                                + 3 * NF_WIDTH * 2      // W5 (bf16)
+                                + (4 * NF_WIDTH + 4) * 4  // biases (+pad)
+                                + NF_FEAT * 3 * 4;        // frequencies
+
+// Physical MFMA row rho of a 32-row tile holds logical row lambda(rho):
+// rho = 8 (i / 4) + 4 g + (i % 4)  <->  lambda = 16 (i / 8) + 8 g + (i % 8).
+__host__ __device__ inline int nf_lambda(int rho)
+{
+    const int g = (rho >> 2) & 1;
+    const int i = ((rho >> 3) << 2) | (rho & 3);
+    return 16 * (i >> 3) + 8 * g + (i & 7);
+}
+
+// Element offset of (row, col) in a 128x128 image: 16-byte chunks XOR-swizzled
+// by the row so that the 32 rows read by one MFMA operand load fall on
+// different LDS banks.
+__host__ __device__ inline int nf_img_off(int row, int col)
+{
+    const int chunk = (col >> 3) ^ (row & 15);
+    return row * NF_WIDTH + chunk * 8 + (col & 7);
+}
+
+struct NFView {
+    const __bf16* w[4];     // LDS images of layers 1..4
+    const __bf16* w5;       // LDS [3][128]
+    const float* bias;      // LDS [4][128] then b5[3]
+    const float* freq;      // LDS [64][3]
+    double origin[3];
+    double inv_box[3];      // 1 / (n_a * spacing)
+    float b_scale;
+};
+
+// Carves the LDS image (layout of NF_LDS_BYTES) starting at `base`.
+__device__ __attribute__((always_inline)) inline NFView nf_view_lds(char* base, const double origin[3], const double inv_box[3],
+                                     float b_scale)
+{
+    NFView v;
+    __bf16* w = (__bf16*)base;
+    for (int k = 0; k < 4; ++k)
+        v.w[k] = w + k * NF_IMG_LAYER;
+    v.w5 = w + 4 * NF_IMG_LAYER;
+    float* f = (float*)(base + 4 * NF_IMG_LAYER * 2 + 3 * NF_WIDTH * 2);
+    v.bias = f;
+    v.freq = f + 4 * NF_WIDTH + 4;
+    for (int a = 0; a < 3; ++a) {
+        v.origin[a] = origin[a];
+        v.inv_box[a] = inv_box[a];
+    }
+    v.b_scale = b_scale;
+    return v;
+}
+
+// Cooperative copy of the global network image (same layout) into LDS.
+__device__ __attribute__((always_inline)) inline void nf_stage_lds(char* dst, const char* src)
+{
+    const int4* s = (const int4*)src;
+    int4* d = (int4*)dst;
+    const int n16 = (int)(NF_LDS_BYTES / 16);
+    for (int i = threadIdx.x; i < n16; i += blockDim.x)
+        d[i] = s[i];
+}
+
+__device__ __attribute__((always_inline)) inline float nf_relu(float v) { return v > 0.0f ? v : 0.0f; }
+
+// Hides an LDS pointer's value from the optimiser: inside persistent loops
+// the weight loads must stay next to their MFMAs instead of being hoisted out
+// of the loop (which would need hundreds of registers).
+template <class T>
+__device__ __attribute__((always_inline)) inline const T* nf_launder(const T* p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Fourier features of one point (this lane's half: group g) as B operand.
+__device__ __attribute__((always_inline)) inline void nf_embed(const float* freq, float x0, float x1, float x2, int g,
+                                bf16x8 act[8])
+{
+    freq = nf_launder(freq);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int jj = 16 * m + 8 * g + j;
+            const float ang = (freq[3 * jj] * x0 + freq[3 * jj + 1] * x1) + freq[3 * jj + 2] * x2;
+            act[m][j] = (__bf16)__builtin_amdgcn_cosf(ang);       // cos 2 pi ang
+            act[m + 4][j] = (__bf16)__builtin_amdgcn_sinf(ang);   // sin 2 pi ang
+        }
+    }
+}
+
+// One hidden layer for the two column blocks: out = relu(W in + b) as bf16.
+// If store_pre is given, it receives the activation (bf16) for later use.
+__device__ __attribute__((always_inline)) inline void nf_layer(const __bf16* wimg, const float* bias, const bf16x8 in[2][8],
+                                bf16x8 out[2][8])
+{
+    wimg = nf_launder(wimg);
+    bias = nf_launder(bias);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int rr = lane & 31;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        floatx16 acc0 = {}, acc1 = {};
+        const int row = 32 * r + rr;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const bf16x8 a = *(const bf16x8*)(wimg + nf_img_off(row, 16 * m + 8 * g));
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, in[0][m], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, in[1][m], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int f = 32 * r + 16 * (i >> 3) + 8 * g + (i & 7);
+            const float b = bias[f];
+            out[0][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc0[i] + b);
+            out[1][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc1[i] + b);
+        }
+    }
+}
+
+// Output layer on the vector ALU: partial dot products over this lane's 64
+// features, completed with the partner lane (l ^ 32); every lane returns the
+// outputs of its own point (lanes 0..31: column block 0, 32..63: block 1).
+__device__ __attribute__((always_inline)) inline void nf_output(const __bf16* w5, const float* b5, const bf16x8 h[2][8],
+                                 float out[3])
+{
+    w5 = nf_launder(w5);
+    b5 = nf_launder(b5);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    float part[2][3];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float s = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    s += (float)w5[c * NF_WIDTH + 16 * m + 8 * g + j] * (float)h[cb][m][j];
+            part[cb][c] = s;
+        }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            part[cb][c] += __shfl_xor(part[cb][c], 32);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        out[c] = (g == 0 ? part[0][c] : part[1][c]) + b5[c];
+}
+
+// Normalised position of a point in [0, 1)^3 (FP64, then FP32).
+__device__ __attribute__((always_inline)) inline void nf_xhat(const NFView& v, const double x[3], float xh[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = (x[a] - v.origin[a]) * v.inv_box[a];
+        xh[a] = (float)(f - floor(f));
+    }
+}
+
+// Whole-wave evaluation: every lane passes its own point and receives its
+// own network output (all 64 lanes must call together).
+__device__ __attribute__((always_inline)) inline void nf_eval_wave(const NFView& v, const float xh[3], float out[3])
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    bf16x8 a[2][8], b[2][8];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int src = 32 * cb + (lane & 31);
+        const float x0 = __shfl(xh[0], src), x1 = __shfl(xh[1], src), x2 = __shfl(xh[2], src);
+        nf_embed(v.freq, x0, x1, x2, g, a[cb]);
+    }
+    nf_layer(v.w[0], v.bias, a, b);
+    nf_layer(v.w[1], v.bias + NF_WIDTH, b, a);
+    nf_layer(v.w[2], v.bias + 2 * NF_WIDTH, a, b);
+    nf_layer(v.w[3], v.bias + 3 * NF_WIDTH, b, a);
+    nf_output(v.w5, v.bias + 4 * NF_WIDTH, a, out);
+}
+
+// Field source for the stepper: the trained network (precision form only;
+// the whole wave takes part in every evaluation).
+struct NeuralFieldSrc {
+    NFView v;
+    __device__ inline void fp32(const double p[3], float B[3]) const
+    {
+        float xh[3], o[3];
+        nf_xhat(v, p, xh);
+        nf_eval_wave(v, xh, o);
+        B[0] = v.b_scale * o[0];
+        B[1] = v.b_scale * o[1];
+        B[2] = v.b_scale * o[2];
+    }
+    __device__ inline void fp64(const double p[3], double B[3]) const
+    {
+        float b[3];
+        fp32(p, b);
+        B[0] = b[0];
+        B[1] = b[1];
+        B[2] = b[2];
+    }
+};
+
+}  // namespace crp

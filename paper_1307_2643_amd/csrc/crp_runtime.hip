@@ -19,6 +19,7 @@
 #include "../../include/crp.h"
 #include "crp_internal.hpp"
 #include "crp_nf.hpp"
+#include "crp_nf_device.hpp"
 
 namespace crp {
 template <int MODE, class GT, int LAYOUT, int BS>
@@ -314,8 +315,11 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.tail0 = (unsigned long long)ctx->pending;
     P.refill = ctx->launch.refill;
 
+    const bool neural = c.field_mode == CRP_FIELD_NEURAL;
+    if (neural)
+        nf_prop_params(ctx->nf, P.grid, &P.nf);
     const int layout = ctx->launch.layout;
-    if (layout == CRP_LAYOUT_CORNER) {
+    if (layout == CRP_LAYOUT_CORNER && !neural) {
         crp_status st = ensure_corner(ctx);
         if (st != CRP_OK)
             return st;
@@ -330,6 +334,20 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_params, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
     const PropParams* dp = ctx->d_params;
     hipStream_t s = ctx->stream;
+    if (neural) {
+        const size_t nl = lds + NF_LDS_BYTES;
+        // the network, the tables and the per-lane state share the CU's LDS
+        if (nl + (size_t)256 * (7 * 8 + 7 * 4) + 256 > (size_t)160 * 1024)
+            return fail(ctx, CRP_EINVAL, "neural propagation: tables too large for LDS (n <= 200)");
+        static bool attr_set = false;
+        if (!attr_set) {
+            HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)nl));
+            attr_set = true;
+        }
+        HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        k_propagate<MODE_MIX, float, 3, 256><<<ctx->num_cus, 256, nl, s>>>(dp);
+    } else {
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     if (!mix && !f32)
         launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp);
@@ -343,6 +361,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         launch_propagate<MODE_MIX, float, 2>(nb, bs, lds, s, dp);
     else
         launch_propagate<MODE_MIX, float, 0>(nb, bs, lds, s, dp);
+    }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(dc, ctx->cnt, sizeof *dc, hipMemcpyDeviceToHost, ctx->stream));
@@ -404,7 +423,8 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
         !(c.field_mode == CRP_FIELD_GRID || c.field_mode == CRP_FIELD_NEURAL) ||
         !(c.tol > 0) || !(c.hmin > 0) || !(c.hmax >= c.hmin) || !(c.eps_loss > 0) ||
         !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !(c.obs_radius >= 0) ||
-        c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40))
+        c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40) ||
+        (c.field_mode == CRP_FIELD_NEURAL && c.precision != CRP_MIX))
         return CRP_EINVAL;
     crp_ctx* ctx = new (std::nothrow) crp_ctx();
     if (!ctx)
@@ -737,11 +757,7 @@ crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles)
         return fail(ctx, CRP_ESTATE, "propagate: read finished records first");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     DevCounters dc;
-    crp_status st;
-    if (ctx->cfg.field_mode == CRP_FIELD_NEURAL)
-        st = nf_propagate(ctx->nf, ctx, max_cycles, &dc);
-    else
-        st = run_kernel(ctx, max_cycles, &dc);
+    const crp_status st = run_kernel(ctx, max_cycles, &dc);
     if (st != CRP_OK)
         return st;
     after_run(ctx, dc, true);
@@ -1215,7 +1231,12 @@ crp_status crp_nf_init(crp_ctx* ctx, const int32_t* freq, const float* params, d
         if (!ctx->nf)
             return fail(ctx, CRP_ENOMEM, "nf_init: allocation failed");
     }
-    return nf_load(ctx->nf, freq, params, b_scale, ctx->err);
+    const crp_status st = nf_load(ctx->nf, freq, params, b_scale, ctx->err);
+    if (st != CRP_OK) {
+        nf_destroy(ctx->nf);
+        ctx->nf = nullptr;
+    }
+    return st;
 }
 
 crp_status crp_nf_get_params(crp_ctx* ctx, float* params)
@@ -1252,56 +1273,3 @@ crp_status crp_nf_train(crp_ctx* ctx, int64_t steps, int64_t batch, double lr0, 
 
 }  // extern "C"
 
-// Used by the neural-field propagation path to reuse the run bookkeeping.
-namespace crp {
-crp_status ctx_run_params(crp_ctx* ctx, int64_t max_cycles, PropParams* P, int* nb, int* bs,
-                          size_t* lds)
-{
-    P->q = ctx->q;
-    P->park = ctx->park;
-    P->fin = ctx->fin;
-    P->neu = ctx->neu;
-    P->cnt = ctx->cnt;
-    P->grid = make_view(ctx);
-    P->tab.e = ctx->tab;
-    P->tab.v[0] = ctx->tab + ctx->tab_n;
-    P->tab.v[1] = ctx->tab + 2 * ctx->tab_n;
-    P->tab.v[2] = ctx->tab + 3 * ctx->tab_n;
-    P->tab.n = ctx->tab_n;
-    P->tab.lg0 = ctx->lg0;
-    P->tab.scale = ctx->lgscale;
-    const crp_config& c = ctx->cfg;
-    P->sp.tol = c.tol;
-    P->sp.hmin = c.hmin;
-    P->sp.hmax = c.hmax;
-    P->sp.eps_loss = c.eps_loss;
-    P->sp.kappa_pi = c.kappa_pi;
-    P->sp.e_floor = c.e_floor;
-    for (int a = 0; a < 3; ++a)
-        P->sp.obs[a] = c.obs_center[a];
-    P->sp.obs_r = c.obs_radius;
-    P->sp.seed = c.seed;
-    P->sp.renorm = c.renormalize;
-    P->max_cycles = max_cycles;
-    P->tail0 = (unsigned long long)ctx->pending;
-    P->refill = ctx->launch.refill;
-    *nb = ctx->num_cus * ctx->launch.blocks_per_cu;
-    *bs = ctx->launch.block;
-    *lds = lds_bytes(ctx->tab_n, *bs);
-    DevCounters init;
-    std::memset(&init, 0, sizeof init);
-    init.tail = (unsigned long long)ctx->pending;
-    init.head1 = (unsigned long long)ctx->pending;
-    init.fin_n = (unsigned long long)ctx->fin_unread;
-    init.neu_n = (unsigned long long)ctx->neu_unread;
-    hipError_t e = hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream);
-    return e == hipSuccess ? CRP_OK : CRP_EDEVICE;
-}
-
-hipStream_t ctx_stream(crp_ctx* ctx) { return ctx->stream; }
-void ctx_set_timing(crp_ctx* ctx, double ms, int64_t launches)
-{
-    ctx->last_ms = ms;
-    ctx->last_launches = launches;
-}
-}  // namespace crp
