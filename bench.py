@@ -59,6 +59,10 @@ def main():
     ap.add_argument("--summarize-pmc", type=str, default=None, metavar="DIR",
                     help="offline: per-launch HBM traffic from rocprofv3 --pmc CSV output")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-nf", action="store_true", help="skip the neural-field variant")
+    ap.add_argument("--nf-candidates", type=int, default=1_000_000)
+    ap.add_argument("--nf-steps", type=int, default=1526,
+                    help="training steps of 65536 points (1526 steps = 1e8 points)")
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -252,12 +256,21 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.3e} steps/s on {used} threads")
         del host_grid
 
+    # ---- neural-field form: train on the grid, then replace the gather -------
+    if not args.no_nf:
+        variants["nf"] = neural_variant(args, crp, I, torch, w, grid, tables, stream, launch)
+
     traffic = None
+    traffic_launch = None
     tpath = os.path.join(ROOT, "profiles", "propagate_mix_grid1024_traffic.json")
     if os.path.exists(tpath):
         t = json.load(open(tpath))
-        if t.get("kernel_sources_sha") == kernel_sources_sha() and t.get("launch") == launch:
+        # counters taken on this kernel source and grid layout (the block shape
+        # changes the traffic by cache effects only)
+        if (t.get("kernel_sources_sha") == kernel_sources_sha() and
+                t.get("launch", {}).get("layout") == launch["layout"]):
             traffic = t.get("hbm_bytes_per_launch")
+            traffic_launch = t.get("launch")
 
     out = {
         "metric": "candidate-steps/sec at 1024^3 grid: plain grid vs FP32/neural-field form "
@@ -285,6 +298,83 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
+    """Trains the Fourier-feature network on the 1024^3 grid with the library's
+    own kernels and compares the surrogate with the grid path on a batch of
+    the distance-distributed workload (sources at 1-1000 Mpc, secondaries on)."""
+    wd = I.W_DIST1024
+    nprm = crp.params_for(wd, crp.MIX, device=0, field_mode=crp.FIELD_NEURAL,
+                          queue_capacity=2 * args.nf_candidates,
+                          neutral_capacity=max(args.nf_candidates, 1 << 20))
+    cnf = crp.Context(nprm, stream)
+    cnf.set_field_grid(grid, wd.spacing_m)
+    cnf.set_tables(tables)
+    from oracle import nf_oracle as NO      # parameter flattening only
+    ws, bs = I.nf_init_weights(509)
+    cnf.nf_init(I.nf_frequencies(seed=505), NO.flatten(ws, bs).astype(np.float32), wd.brms_T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = cnf.nf_train(args.nf_steps, 65536, 1e-3, 1e-5, 506)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"[bench] NF trained on {args.nf_steps * 65536:.3g} points in {train_s:.1f}s, "
+        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    # field error on held-out points (the grid path is the judge)
+    box = wd.grid_n * wd.spacing_m
+    pos = I.uniform_points(1_000_000, box, 507)
+    Bn = cnf.eval_field(pos, crp.EVAL_NEURAL)
+    Bg = cnf.eval_field(pos, crp.MIX)
+    rms = float(np.sqrt(((Bn - Bg) ** 2).sum(1).mean()) / wd.brms_T)
+    log(f"[bench] NF RMS field error {rms:.4f} of B_rms")
+    inj = I.inject_distances(args.nf_candidates, 508)
+
+    def run(ctx):
+        ctx.reset_counters()
+        ctx.inject(inj)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ctx.propagate(0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        ms, _ = ctx.last_timing()
+        fin = ctx.read_finished()
+        ctx.discard_finished()
+        c = ctx.counts()
+        return fin, c["steps"] / dt, ms, c
+
+    fin_nf, rate_nf, ms_nf, c_nf = run(cnf)
+    cnf.close()
+    gprm = crp.params_for(wd, crp.MIX, device=0, queue_capacity=2 * args.nf_candidates,
+                          neutral_capacity=max(args.nf_candidates, 1 << 20))
+    cg = crp.Context(gprm, stream)
+    cg.set_field_grid(grid, wd.spacing_m)
+    cg.set_tables(tables)
+    cg.set_launch(**launch)
+    run(cg)                                     # untimed: builds the grid records
+    fin_g, rate_g, ms_g, c_g = run(cg)
+    cg.close()
+
+    def hist(f):
+        th = np.degrees(np.arccos(np.clip((f["u"] * f["u0"]).sum(1), -1, 1)))
+        return np.histogram(th, bins=36, range=(0, 180))[0] / max(len(th), 1), th
+
+    hn, thn = hist(fin_nf)
+    hg, thg = hist(fin_g)
+    from scipy import stats
+    ks = float(stats.ks_2samp(thn, thg).statistic)
+    out = {"steps_per_s": rate_nf, "kernel_ms": ms_nf, "grid_steps_per_s_same_batch": rate_g,
+           "speedup_vs_grid": rate_nf / rate_g, "rms_field_error": rms,
+           "deflection_hist_distance": float(0.5 * np.abs(hn - hg).sum()), "deflection_ks": ks,
+           "train_points": args.nf_steps * 65536, "train_s": train_s,
+           "final_train_loss": float(losses[-1]), "field_bytes_network": 66435 * 2,
+           "field_bytes_grid": int(grid.numel() * 4),
+           "workload": f"{wd.name} subset of {args.nf_candidates} candidates (seed 508)",
+           "steps": {"nf": c_nf["steps"], "grid": c_g["steps"]}}
+    log(f"[bench] NF form: {rate_nf:.3e} steps/s vs grid {rate_g:.3e} on the same batch; "
+        f"deflection histogram distance {out['deflection_hist_distance']:.4f}, KS {ks:.4f}")
+    return out
 
 
 def summarize_pmc(d):
