@@ -77,7 +77,9 @@ typedef struct {
 /* Kernel launch shape of the persistent propagation kernel. */
 typedef struct {
     int32_t block;            /* threads per block: 128 or 256 */
-    int32_t blocks_per_cu;    /* persistent blocks per compute unit (1..64) */
+    int32_t blocks_per_cu;    /* persistent blocks per compute unit (1..64), or 0:
+                                 as many as the kernel's occupancy lets one
+                                 compute unit hold at once */
     int32_t refill;           /* a wave claims new candidates once this many of its
                                  64 lanes are idle (1..64) */
     int32_t layout;           /* CRP_LAYOUT_LINEAR or CRP_LAYOUT_CORNER */
@@ -186,6 +188,7 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* 
                           int32_t mode, int32_t on_device);
 
 /* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
+ * A new context starts with {128, 4, 32, CRP_LAYOUT_LINEAR}.
  * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra
  * device memory (built on first use). */
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);

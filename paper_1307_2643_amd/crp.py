@@ -94,6 +94,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1307_2643_amd.build` (no CPU fallback exists)")
+    # One HIP runtime per process: PyTorch carries its own copy, and of two
+    # copies loaded side by side the second finds no GPU.  Importing torch
+    # first makes the library bind to torch's copy (same soname).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     sig = {
@@ -325,7 +332,7 @@ class Context:
         return out
 
     # -- launch shape / tuning / timing ---------------------------------------
-    def set_launch(self, block=256, blocks_per_cu=4, refill=16, layout=LAYOUT_LINEAR):
+    def set_launch(self, block=128, blocks_per_cu=4, refill=32, layout=LAYOUT_LINEAR):
         lch = Launch(block, blocks_per_cu, refill, layout)
         self._check(self.L.crp_set_launch(self.h, C.byref(lch)))
 

@@ -99,10 +99,16 @@ __device__ inline bool ctrl_ok(int k, double r)
 __device__ inline int ctrl_k(double r)
 {
     const int KMAX = 5121;
-    const double g = (0.95 * 1024.0) * pow(r, -0.2);
-    int k = 0;
-    if (g >= 1.0)   // also false for NaN
-        k = g > (double)KMAX ? KMAX : (int)floor(g);
+    // first guess from the hardware log2/exp2 in FP32 (a few ulp off at most);
+    // the exact search below decides
+    int k = KMAX;
+    if (r > 1e-30) {
+        const float rf = r < 1e30 ? (float)r : 1e30f;
+        const float g = 972.8f * __builtin_amdgcn_exp2f(-0.2f * __builtin_amdgcn_logf(rf));
+        k = g >= (float)KMAX ? KMAX : (g >= 1.0f ? (int)g : 0);
+    } else if (!(r >= 0.0)) {
+        k = 0;   // NaN
+    }
     while (k < KMAX && ctrl_ok(k + 1, r))
         ++k;
     while (k > 0 && !ctrl_ok(k, r))
@@ -117,30 +123,62 @@ struct TableView {
     const double* e;     // LDS: nodes
     const double* v[3];  // LDS: t_pi, t_n, beta_p
     int n;
-    double lg0, scale;   // log10(e[0]), (n - 1) / (log10 e[n-1] - log10 e[0])
+    float lg0, scale;    // log2(e[0]), (n - 1) / (log2 e[n-1] - log2 e[0])
 };
 
-__device__ inline double table_value(const TableView& T, int which, double eps)
+// Bracketing node and fraction of eps, shared by the three tables (they have
+// the same nodes): e[j] <= eps < e[j+1] and t = (eps - e[j]) / (e[j+1] - e[j]);
+// clamp < 0 below the first node, > 0 at or above the last.
+struct TablePos {
+    int j;
+    int clamp;
+    double t;
+};
+
+__device__ inline TablePos table_pos(const TableView& T, double eps)
 {
     const double* e = T.e;
-    const double* v = T.v[which];
     const int n = T.n;
-    if (eps <= e[0])
-        return v[0];
-    if (eps >= e[n - 1])
-        return v[n - 1];
-    // first guess from the log-spaced layout, then exact correction against
-    // the node values: afterwards e[j] <= eps < e[j+1]
-    const double gs = (log10(eps) - T.lg0) * T.scale;
+    TablePos p;
+    p.j = 0;
+    p.t = 0.0;
+    p.clamp = 0;
+    if (eps <= e[0]) {
+        p.clamp = -1;
+        return p;
+    }
+    if (eps >= e[n - 1]) {
+        p.clamp = 1;
+        return p;
+    }
+    // first guess from the log-spaced layout (FP32 hardware log2), then exact
+    // correction against the node values
+    const float gs = (__builtin_amdgcn_logf((float)eps) - T.lg0) * T.scale;
     int j = 0;
-    if (gs > 0.0)   // also false for NaN
-        j = gs > (double)(n - 2) ? n - 2 : (int)gs;
+    if (gs > 0.0f)   // also false for NaN
+        j = gs > (float)(n - 2) ? n - 2 : (int)gs;
     while (j < n - 2 && e[j + 1] <= eps)
         ++j;
     while (j > 0 && e[j] > eps)
         --j;
-    const double t = (eps - e[j]) / (e[j + 1] - e[j]);
-    return v[j] + t * (v[j + 1] - v[j]);
+    p.j = j;
+    p.t = (eps - e[j]) / (e[j + 1] - e[j]);
+    return p;
+}
+
+__device__ inline double table_at(const TableView& T, int which, const TablePos& p)
+{
+    const double* v = T.v[which];
+    if (p.clamp < 0)
+        return v[0];
+    if (p.clamp > 0)
+        return v[T.n - 1];
+    return v[p.j] + p.t * (v[p.j + 1] - v[p.j]);
+}
+
+__device__ inline double table_value(const TableView& T, int which, double eps)
+{
+    return table_at(T, which, table_pos(T, eps));
 }
 
 struct Rates {
@@ -152,12 +190,13 @@ struct Rates {
 __device__ inline Rates species_rates(const TableView& T, int A, int Z, double E)
 {
     const double eps = E / (double)A;
+    const TablePos p = table_pos(T, eps);
     Rates R;
-    R.rpi = (double)A * table_value(T, 0, eps);
-    R.rn = A >= 2 ? (double)A * table_value(T, 1, eps) : 0.0;
+    R.rpi = (double)A * table_at(T, 0, p);
+    R.rn = A >= 2 ? (double)A * table_at(T, 1, p) : 0.0;
     R.r = R.rpi + R.rn;
     const double zz = (double)(Z * Z) / (double)A;
-    R.beta = zz * table_value(T, 2, eps);
+    R.beta = zz * table_at(T, 2, p);
     return R;
 }
 
@@ -245,45 +284,52 @@ __device__ inline void gather_corner(const GridView& g, const Cell& c, float v[8
 }
 
 // Wave-cooperative gather of the 64 lanes' corner records (all 64 lanes of
-// the wave must call it together).  The records are fetched in two rounds of
-// 32: in each round the 32 records x 6 sixteen-byte chunks are spread over
-// the 64 lanes, so one load instruction touches about 11 records (cache lines
-// and address translations) instead of 64 and each line is read by 6
-// neighbouring lanes; the chunks reach their owner lane through `stage`, a
-// 32 x 24-float LDS area private to the wave.
-__device__ inline void gather_corner_coop(const float* corner, int64_t cell, float* stage,
+// the wave must call it together).  The 64 records x 6 sixteen-byte chunks
+// are spread over the lanes in two halves of 32 records, so one load
+// instruction touches about 11 records (cache lines and address translations)
+// instead of 64 and each line is read by 6 neighbouring lanes.  The six loads
+// of a lane go straight from memory into `stage` (a 64 x 24-float LDS area
+// private to the wave; 16-byte global-to-LDS loads, which place lane l's chunk
+// at byte 16 l of the instruction's destination), all in flight together and
+// holding no registers; then every lane reads its own record back.
+constexpr int COOP_STAGE_FLOAT4 = 384;   // float4 slots of one wave's staging area
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+__device__ inline void gather_corner_coop(const float* corner, uint32_t cell, float* stage,
                                           float v[8][3])
 {
     const int lane = (int)(threadIdx.x & 63u);
-    float f[24];
+    float4* st = (float4*)stage;
 #pragma unroll
-    for (int round = 0; round < 2; ++round) {
+    for (int half = 0; half < 2; ++half)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int idx = 64 * j + lane;            // 0..191
-            const int r = idx / 6, c = idx - 6 * r;   // record of the round, chunk
-            const int64_t rc = __shfl(cell, 32 * round + r);
-            const float4 w = ((const float4*)(corner + rc * 32))[c];
-            ((float4*)stage)[idx] = w;
+            const int r = idx / 6, c = idx - 6 * r;   // record within the half, chunk
+            const uint32_t rc = (uint32_t)__shfl((int)cell, 32 * half + r);
+            const float4* src = (const float4*)(corner + (uint64_t)rc * 32u) + c;
+            __builtin_amdgcn_global_load_lds((const void*)src,
+                                             (lds_void_ptr)(st + 192 * half + 64 * j), 16, 0, 0);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if ((lane >> 5) == round) {
-            const float4* my = (const float4*)(stage + (lane & 31) * 24);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float f[24];
+    const float4* my = st + 192 * (lane >> 5) + 6 * (lane & 31);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const float4 w = my[q];
-                f[4 * q + 0] = w.x;
-                f[4 * q + 1] = w.y;
-                f[4 * q + 2] = w.z;
-                f[4 * q + 3] = w.w;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int q = 0; q < 6; ++q) {
+        const float4 x = my[q];
+        f[4 * q + 0] = x.x;
+        f[4 * q + 1] = x.y;
+        f[4 * q + 2] = x.z;
+        f[4 * q + 3] = x.w;
     }
+    // the staging area is rewritten by the wave's next gather
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         v[k][0] = f[3 * k + 0];
@@ -343,7 +389,7 @@ struct GridField {
     __device__ inline void corners(const Cell& c, GT v[8][3]) const
     {
         if constexpr (LAYOUT == 2)
-            gather_corner_coop(g.corner, cell_index(g, c), stage, v);
+            gather_corner_coop(g.corner, (uint32_t)cell_index(g, c), stage, v);
         else if constexpr (LAYOUT == 1)
             gather_corner(g, c, v);
         else

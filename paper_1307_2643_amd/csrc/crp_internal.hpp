@@ -54,7 +54,7 @@ struct TableParams {
     const double* e;
     const double* v[3];
     int n;
-    double lg0, scale;
+    float lg0, scale;    // log2 of the first node, (n - 1) / log2 span of the nodes
 };
 
 struct StepParams {

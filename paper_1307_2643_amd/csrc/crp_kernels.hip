@@ -48,17 +48,14 @@ __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
     q.Z[i] = c.Z;
 }
 
-// Wave-uniform bookkeeping: each per-lane event of an iteration is counted
-// with a ballot, so the counters live in scalar registers.
+// Bookkeeping: block counters in LDS; the per-iteration counts (attempts,
+// accepts, forced accepts) are added once per wave from a ballot, rare events
+// with an LDS atomic where they happen.
 enum {
     WC_STEPS = 0, WC_ATTEMPTS, WC_REJECTS, WC_FORCED, WC_EVENTS, WC_NULL, WC_PI, WC_N,
     WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_COUNT
 };
-enum : uint32_t {
-    EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_EVENT = 1u << 3,
-    EV_NULL = 1u << 4, EV_PI = 1u << 5, EV_N = 1u << 6, EV_FIN = 1u << 7, EV_OBS = 1u << 8,
-    EV_TRAJ = 1u << 9, EV_EFLOOR = 1u << 10, EV_QDROP = 1u << 11, EV_NDROP = 1u << 12
-};
+enum : uint32_t { EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_FIN = 1u << 3 };
 
 __device__ inline unsigned long long count_bit(uint32_t ev, uint32_t bit)
 {
@@ -221,7 +218,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     __shared__ LaneShared<BS> S;              // per-lane cold state
     __shared__ unsigned long long bc[WC_COUNT];   // block bookkeeping counters
     // LDS staging of the wave-cooperative corner gather (LAYOUT 2 only)
-    __shared__ float4 stage_mem[LAYOUT == 2 ? BS / 64 * 192 : 1];
+    __shared__ float4 stage_mem[LAYOUT == 2 ? BS / 64 * COOP_STAGE_FLOAT4 : 1];
     const int t = (int)threadIdx.x;
     const int ntab = PP->tab.n;
     {
@@ -254,7 +251,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         F.v = nf_view_lds(img, PP->nf.origin, PP->nf.inv_box, PP->nf.b_scale);
     } else {
         F.g = PP->grid;
-        F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * 192 : 0));
+        F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * COOP_STAGE_FLOAT4 : 0));
     }
     const StepParams sp = PP->sp;
     const int lane = lane_id();
@@ -460,13 +457,13 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                     const double Eint = E;
                     const Rates ri = species_rates(T, A, Z, Eint);
                     const double Ptot = ri.rpi + ri.rn;
-                    ev |= EV_EVENT;
+                    atomicAdd(&bc[WC_EVENTS], 1ull);
                     if (Ptot > 0.0) {
                         const double Uc = unit_uniform(w.w[0]);
                         if (Uc * Ptot < ri.rpi) {
                             dE = (sp.kappa_pi * Eint) / (double)A;
                             E = Eint - dE;
-                            ev |= EV_PI;
+                            atomicAdd(&bc[WC_PI], 1ull);
                             neutral = true;
                         } else {
                             const int pout = (2 * Z > A) ? 1 : 0;
@@ -475,11 +472,11 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                             A -= 1;
                             E = Eint - Esec;
                             S.azf[t] = pack_azf(A, Z, flag);
-                            ev |= EV_N;
+                            atomicAdd(&bc[WC_N], 1ull);
                             spawn = true;
                         }
                     } else {
-                        ev |= EV_NULL;
+                        atomicAdd(&bc[WC_NULL], 1ull);
                     }
                     // all interaction state is reset after an interaction
                     tau = optical_depth(w.w[1]);
@@ -500,8 +497,11 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                     status = ST_ENERGY_FLOOR;
                 if (status != ST_ACTIVE) {
                     ev |= EV_FIN;
-                    ev |= status == ST_OBSERVED ? EV_OBS
-                                                : (status == ST_MAX_TRAJ ? EV_TRAJ : EV_EFLOOR);
+                    atomicAdd(&bc[WC_FINISHED], 1ull);
+                    atomicAdd(&bc[status == ST_OBSERVED ? WC_OBSERVED
+                                                        : (status == ST_MAX_TRAJ ? WC_MAXTRAJ
+                                                                                 : WC_EFLOOR)],
+                              1ull);
                 } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
                     park = true;
                 }
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                         nq.m[k] = S.m[t];
                         nq.chan[k] = 0;
                     } else {
-                        ev |= EV_NDROP;
+                        atomicAdd(&bc[WC_NDROP], 1ull);
                     }
                 }
             }
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                         __hip_atomic_store(q.ready + i, 1u, __ATOMIC_RELEASE,
                                            __HIP_MEMORY_SCOPE_AGENT);
                     } else {
-                        ev |= EV_QDROP;
+                        atomicAdd(&bc[WC_QDROP], 1ull);
                     }
                 }
             }
@@ -661,26 +661,16 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             }
         }
 
-        // ---- bookkeeping: wave ballots into the block's LDS counters --------
+        // ---- bookkeeping: the frequent counts by wave ballot (rare events were
+        // counted with LDS atomics where they happened) ------------------------
         {
             const unsigned long long att = count_bit(ev, EV_ATTEMPT);
             const unsigned long long acc = count_bit(ev, EV_ACCEPT);
+            const unsigned long long frc = count_bit(ev, EV_FORCED);
             add_count(bc, WC_ATTEMPTS, att);
             add_count(bc, WC_STEPS, acc);
             add_count(bc, WC_REJECTS, att - acc);
-            if (__ballot((ev & ~(EV_ATTEMPT | EV_ACCEPT)) != 0u)) {
-                add_count(bc, WC_FORCED, count_bit(ev, EV_FORCED));
-                add_count(bc, WC_EVENTS, count_bit(ev, EV_EVENT));
-                add_count(bc, WC_NULL, count_bit(ev, EV_NULL));
-                add_count(bc, WC_PI, count_bit(ev, EV_PI));
-                add_count(bc, WC_N, count_bit(ev, EV_N));
-                add_count(bc, WC_FINISHED, count_bit(ev, EV_FIN));
-                add_count(bc, WC_OBSERVED, count_bit(ev, EV_OBS));
-                add_count(bc, WC_MAXTRAJ, count_bit(ev, EV_TRAJ));
-                add_count(bc, WC_EFLOOR, count_bit(ev, EV_EFLOOR));
-                add_count(bc, WC_QDROP, count_bit(ev, EV_QDROP));
-                add_count(bc, WC_NDROP, count_bit(ev, EV_NDROP));
-            }
+            add_count(bc, WC_FORCED, frc);
         }
     }
     __syncthreads();   // every wave of the block has left the loop

@@ -59,7 +59,7 @@ struct crp_ctx {
     bool has_tables = false;
     double* tab = nullptr;
     int tab_n = 0;
-    double lg0 = 0.0, lgscale = 0.0;
+    float lg0 = 0.0f, lgscale = 0.0f;
 
     // buffers
     void* qmem[2] = {nullptr, nullptr};
@@ -213,6 +213,21 @@ size_t lds_bytes(int ntab, int block)
     return (size_t)4 * ntab * sizeof(double);
 }
 
+// Blocks of one propagation kernel that fit on a compute unit at once.
+template <int MODE, class GT, int LAYOUT>
+int resident_blocks(int bs, size_t lds)
+{
+    int nbpm = 0;
+    hipError_t e;
+    if (bs == 128)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 128>, 128, lds);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 256>, 256, lds);
+    return (e == hipSuccess && nbpm > 0) ? nbpm : 1;
+}
+
 template <int MODE, class GT, int LAYOUT>
 void launch_propagate(int nb, int bs, size_t lds, hipStream_t s, const PropParams* dp)
 {
@@ -256,6 +271,8 @@ crp_status ensure_corner(crp_ctx* ctx)
     if (ctx->grid_dtype != CRP_F32)
         return fail(ctx, CRP_EINVAL, "corner layout needs an FP32 grid");
     const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
+    if (ncell >= (1ll << 32))
+        return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
     HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
     GridView g = make_view(ctx);
     k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
@@ -326,10 +343,25 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         P.grid.corner = ctx->corner;
     }
     const int bs = ctx->launch.block;
-    const int nb = ctx->num_cus * ctx->launch.blocks_per_cu;
     const size_t lds = lds_bytes(ctx->tab_n, bs);
     const bool mix = c.precision == CRP_MIX;
     const bool f32 = ctx->grid_dtype == CRP_F32;
+    int bpc = ctx->launch.blocks_per_cu;
+    if (bpc == 0) {   // as many blocks as fit on a compute unit
+        if (!mix && !f32)
+            bpc = resident_blocks<MODE_FP64, double, 0>(bs, lds);
+        else if (!mix && layout == CRP_LAYOUT_CORNER)
+            bpc = resident_blocks<MODE_FP64, float, 2>(bs, lds);
+        else if (!mix)
+            bpc = resident_blocks<MODE_FP64, float, 0>(bs, lds);
+        else if (!f32)
+            bpc = resident_blocks<MODE_MIX, double, 0>(bs, lds);
+        else if (layout == CRP_LAYOUT_CORNER)
+            bpc = resident_blocks<MODE_MIX, float, 2>(bs, lds);
+        else
+            bpc = resident_blocks<MODE_MIX, float, 0>(bs, lds);
+    }
+    const int nb = ctx->num_cus * bpc;
 
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_params, &P, sizeof P, hipMemcpyHostToDevice, ctx->stream));
     const PropParams* dp = ctx->d_params;
@@ -432,9 +464,9 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     ctx->cfg = c;
     ctx->stream = (hipStream_t)stream;
     std::memset(&ctx->totals, 0, sizeof ctx->totals);
-    ctx->launch.block = 256;
+    ctx->launch.block = 128;
     ctx->launch.blocks_per_cu = 4;
-    ctx->launch.refill = 16;
+    ctx->launch.refill = 32;
     ctx->launch.layout = CRP_LAYOUT_LINEAR;
     auto bail = [&](crp_status st, const char* what, hipError_t e) {
         fprintf(stderr, "crp_create: %s: %s\n", what, hipGetErrorString(e));
@@ -598,8 +630,8 @@ crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e, const double
     HIPCHK(ctx, hipMalloc((void**)&ctx->tab, h.size() * sizeof(double)));
     HIPCHK(ctx, hipMemcpy(ctx->tab, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
     ctx->tab_n = n;
-    ctx->lg0 = std::log10(e[0]);
-    ctx->lgscale = (double)(n - 1) / (std::log10(e[n - 1]) - std::log10(e[0]));
+    ctx->lg0 = (float)std::log2(e[0]);
+    ctx->lgscale = (float)((double)(n - 1) / (std::log2(e[n - 1]) - std::log2(e[0])));
     ctx->has_tables = true;
     return CRP_OK;
 }
@@ -939,7 +971,7 @@ crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* l)
 {
     if (!ctx || !l)
         return CRP_EINVAL;
-    if (!(l->block == 128 || l->block == 256) || l->blocks_per_cu < 1 ||
+    if (!(l->block == 128 || l->block == 256) || l->blocks_per_cu < 0 ||
         l->blocks_per_cu > 64 || l->refill < 1 || l->refill > 64 ||
         !(l->layout == CRP_LAYOUT_LINEAR || l->layout == CRP_LAYOUT_CORNER))
         return fail(ctx, CRP_EINVAL, "set_launch: invalid launch shape");
@@ -994,9 +1026,9 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     const bool corner_ok = ctx->grid_dtype == CRP_F32;
     for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
         for (int bs : {128, 256})
-            for (int bpc : {4, 8, 16})
-                for (int rf : {8, 32})
-                    if (bs * bpc <= 2048 && bs * bpc >= 512)
+            for (int bpc : {0, 2, 3, 4, 5, 8})
+                for (int rf : {16, 32})
+                    if (bpc == 0 || (bs * bpc <= 1024 && bs * bpc >= 384))
                         cands.push_back(crp_launch{bs, bpc, rf, layout});
     crp_launch bestl = orig;
     double bestr = -1.0;

@@ -1,0 +1,149 @@
+"""Full-size parity: the 1e7-candidate mixed-nuclei batch on the 1024^3 FP32
+grid, propagated whole on the GPU in the launch the autotuner picks (the
+configuration the benchmark times), checked against the oracle on a sample of
+candidates that the oracle follows one by one, and against properties that
+hold at any size.
+
+Every candidate's history depends only on its own inputs and its counter-based
+random stream (key: seed, id, lineage), so the oracle run on the sampled
+candidates alone must reproduce every record the GPU wrote for them, including
+their secondaries: bitwise here, as both sides take the same operation order.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import crp_inputs as I
+from parity_helpers import compare_neutral, compare_records, say
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+W = I.W_MIXED1024
+N_SAMPLE = 400
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1307_2643_amd import crp
+    crp.load()
+    return crp
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def big():
+    """Device grid, host copy for the oracle, tables and the injection batch."""
+    import torch
+    say(f"generating {W.grid_n}^3 grid on the GPU")
+    grid = W.make_grid(device="cuda:0")
+    torch.cuda.synchronize()
+    host = grid.cpu().numpy()
+    tables = W.make_tables()
+    inj = W.make_injection()
+    d_inj = [torch.as_tensor(a, device="cuda:0") for a in
+             (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+    state = {"grid": grid, "host": host, "tables": tables, "inj": inj, "d_inj": d_inj,
+             "launch": None}
+    yield state
+    state.clear()
+    torch.cuda.empty_cache()
+
+
+def _context(P, big, precision):
+    n = W.n_candidates
+    prm = P.params_for(W, precision, device=0, queue_capacity=2 * n,
+                       neutral_capacity=max(n, 1 << 20))
+    ctx = P.Context(prm)
+    ctx.set_field_grid(big["grid"], W.spacing_m)
+    ctx.set_tables(big["tables"])
+    return ctx
+
+
+def _inject(ctx, d, count=None):
+    s = slice(0, count)
+    ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
+               lmax=d[6][s], on_device=True)
+
+
+def _sample_ids(n):
+    rng = np.random.default_rng(4242)
+    ids = rng.choice(n, N_SAMPLE - 8, replace=False)
+    # the first and last candidates of the batch (its ragged end) as well
+    return np.unique(np.concatenate([ids, np.arange(4), np.arange(n - 4, n)]))
+
+
+def _select(rec, ids):
+    keep = np.isin(rec["id"], ids)
+    return {k: v[keep] for k, v in rec.items()}
+
+
+def _check_whole_batch(P, fin, neu, cnt, n):
+    """Properties of the full output that hold at any size."""
+    key = (fin["id"].astype(np.int64) << 32) | fin["lineage"].astype(np.int64)
+    assert np.unique(key).size == key.size, "duplicate (id, lineage) records"
+    prim = fin["lineage"] == 0
+    assert prim.sum() == n and np.array_equal(np.sort(fin["id"][prim]), np.arange(n))
+    assert cnt["finished"] == len(fin["id"])
+    assert cnt["observed"] + cnt["max_traj"] + cnt["energy_floor"] == cnt["finished"]
+    assert cnt["finished"] == n + cnt["charged_sec"]
+    assert len(neu["id"]) == cnt["neutral_sec"]
+    assert cnt["queue_dropped"] == 0 and cnt["neutral_dropped"] == 0
+    assert np.all(fin["Z"] >= 1) and np.all(fin["Z"] <= fin["A"])
+    assert np.all(np.isfinite(fin["x"])) and np.all(fin["E"] > 0)
+    # the last step is shortened to end on the trajectory budget
+    assert np.all(fin["L"] <= W.lmax_m)
+    un = np.linalg.norm(fin["u"], axis=1)
+    assert np.all(np.abs(un - 1.0) < 1e-6)
+
+
+def test_autotuned_launch(P, big):
+    """The benchmark's tuning step, on the same calibration batch."""
+    ctx = _context(P, big, P.MIX)
+    _inject(ctx, big["d_inj"], 1 << 20)
+    say("autotuning on 2^20 candidates")
+    tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
+    ctx.discard_finished()
+    while not ctx.propagate(0):
+        pass
+    ctx.close()
+    big["launch"] = dict(tuned)
+    say(f"tuned launch {big['launch']} ({rate:.3e} steps/s)")
+    assert rate > 0
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["mix", "fp64"])
+def test_full_batch_sampled_parity(P, O, big, precision):
+    n = W.n_candidates
+    ctx = _context(P, big, precision)
+    if big["launch"]:
+        ctx.set_launch(**big["launch"])
+    launch = ctx.get_launch()
+    say(f"full batch n={n} precision={precision} launch={launch}")
+    _inject(ctx, big["d_inj"])
+    assert ctx.propagate(0)
+    cnt = ctx.counts()
+    fin = ctx.read_finished()
+    neu = ctx.read_neutral()
+    ctx.close()
+    say(f"gpu: {len(fin['id'])} finished, {len(neu['id'])} neutral, {cnt['steps']} steps")
+    _check_whole_batch(P, fin, neu, cnt, n)
+
+    ids = _sample_ids(n)
+    sub = big["inj"].subset(ids)
+    G = O.GridRef(big["host"], W.spacing_m)
+    T = O.TablesRef(big["tables"])
+    threads = len(os.sched_getaffinity(0))
+    fo, no, co, _ = O.propagate(O.config_for(W, precision=precision), G, T, sub,
+                                nthreads=threads)
+    say(f"oracle: {len(fo['id'])} records for {len(ids)} sampled candidates")
+    fg = _select(fin, ids)
+    same = compare_records(fg, fo, f"1024^3 sample p{precision}")
+    assert same.all()
+    compare_neutral(_select(neu, ids), no, f"1024^3 sample neutral p{precision}")
