@@ -389,7 +389,10 @@ def summarize_pmc(d):
             c, k = r["Counter_Name"], r["Kernel_Name"]
             if c not in ("FETCH_SIZE", "WRITE_SIZE"):
                 continue
-            kind = "prop" if "k_propagate" in k else ("copy" if "copyBuffer" in k else None)
+            # the grid propagation kernel (the neural-field instantiation has
+            # layout 3 and is excluded)
+            grid_prop = "k_propagate" in k and ", 3," not in k
+            kind = "prop" if grid_prop else ("copy" if "copyBuffer" in k else None)
             if kind:
                 vals.setdefault((kind, c), []).append(float(r["Counter_Value"]))
     gib = float(1 << 30)
