@@ -297,20 +297,26 @@ constexpr int COOP_STAGE_FLOAT4 = 384;   // float4 slots of one wave's staging a
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 __device__ inline void gather_corner_coop(const float* corner, uint32_t cell, float* stage,
-                                          float v[8][3])
+                                          float v[8][3], bool need)
 {
     const int lane = (int)(threadIdx.x & 63u);
     float4* st = (float4*)stage;
+    // records of lanes that do not need the field (idle lanes, reused values)
+    // are not fetched; those lanes get whatever the staging area holds
+    const uint64_t needm = __ballot(need);
 #pragma unroll
     for (int half = 0; half < 2; ++half)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int idx = 64 * j + lane;            // 0..191
             const int r = idx / 6, c = idx - 6 * r;   // record within the half, chunk
-            const uint32_t rc = (uint32_t)__shfl((int)cell, 32 * half + r);
+            const int owner = 32 * half + r;
+            const uint32_t rc = (uint32_t)__shfl((int)cell, owner);
             const float4* src = (const float4*)(corner + (uint64_t)rc * 32u) + c;
-            __builtin_amdgcn_global_load_lds((const void*)src,
-                                             (lds_void_ptr)(st + 192 * half + 64 * j), 16, 0, 0);
+            if ((needm >> owner) & 1ull)
+                __builtin_amdgcn_global_load_lds((const void*)src,
+                                                 (lds_void_ptr)(st + 192 * half + 64 * j), 16, 0,
+                                                 0);
         }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -386,27 +392,35 @@ template <class GT, int LAYOUT>
 struct GridField {
     GridView g;
     float* stage = nullptr;   // LAYOUT 2: the wave's LDS staging area
-    __device__ inline void corners(const Cell& c, GT v[8][3]) const
+    // need = false: this lane's value will not be used (the cooperative
+    // gather then skips its record; the per-lane gathers skip the loads)
+    __device__ inline void corners(const Cell& c, GT v[8][3], bool need) const
     {
-        if constexpr (LAYOUT == 2)
-            gather_corner_coop(g.corner, (uint32_t)cell_index(g, c), stage, v);
-        else if constexpr (LAYOUT == 1)
-            gather_corner(g, c, v);
-        else
-            gather_linear<GT>(g, c, v);
+        if constexpr (LAYOUT == 2) {
+            gather_corner_coop(g.corner, (uint32_t)cell_index(g, c), stage, v, need);
+        } else if (need) {
+            if constexpr (LAYOUT == 1)
+                gather_corner(g, c, v);
+            else
+                gather_linear<GT>(g, c, v);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                v[k][0] = v[k][1] = v[k][2] = (GT)0;
+        }
     }
-    __device__ inline void fp64(const double p[3], double B[3]) const
+    __device__ inline void fp64(const double p[3], double B[3], bool need = true) const
     {
         const Cell c = locate(g, p);
         GT v[8][3];
-        corners(c, v);
+        corners(c, v, need);
         interp_fp64(c.t, v, B);
     }
-    __device__ inline void fp32(const double p[3], float B[3]) const
+    __device__ inline void fp32(const double p[3], float B[3], bool need = true) const
     {
         const Cell c = locate(g, p);
         GT v[8][3];
-        corners(c, v);
+        corners(c, v, need);
         float vf[8][3];
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -446,11 +460,10 @@ __device__ inline float dot3f(const float a[3], const float b[3])
     return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
 }
 
-template <class F>
-__device__ inline void deriv_fp64(const F& field, double kappa, const double y[6], double k[6])
+__device__ inline void deriv_from_field(double kappa, const double y[6], const double B[3],
+                                         double k[6])
 {
-    double B[3], c[3];
-    field.fp64(y, B);
+    double c[3];
     cross3(y + 3, B, c);
     k[0] = y[3];
     k[1] = y[4];
@@ -460,12 +473,26 @@ __device__ inline void deriv_fp64(const F& field, double kappa, const double y[6
     k[5] = kappa * c[2];
 }
 
+// `need`: this lane's result is used.  `reuse`: b1 already holds B(x) of this
+// very position (a retry after a rejected attempt), so the first stage does
+// not gather it again; otherwise b1 receives B(x).
 template <class F>
 __device__ inline double ck_attempt_fp64(const F& field, double kappa, const double y[6],
-                                         double h, double y5[6])
+                                         double h, double y5[6], bool need, bool reuse,
+                                         double b1[3])
 {
     double K[6][6];
-    deriv_fp64(field, kappa, y, K[0]);
+    {
+        double B[3];
+        field.fp64(y, B, need && !reuse);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (reuse)
+                B[q] = b1[q];
+            b1[q] = B[q];
+        }
+        deriv_from_field(kappa, y, B, K[0]);
+    }
 #pragma unroll
     for (int i = 1; i < 6; ++i) {
         double ys[6];
@@ -477,7 +504,9 @@ __device__ inline double ck_attempt_fp64(const F& field, double kappa, const dou
                 s = s + CK::a[i][j] * K[j][q];
             ys[q] = y[q] + h * s;
         }
-        deriv_fp64(field, kappa, ys, K[i]);
+        double B[3];
+        field.fp64(ys, B, need);
+        deriv_from_field(kappa, ys, B, K[i]);
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -503,12 +532,10 @@ __device__ inline double ck_attempt_fp64(const F& field, double kappa, const dou
 // Precision form: stage increments G_i = (h u_i, (h kappa) u_i x B(x_i)) in
 // FP32 with h and h*kappa formed in FP64 and rounded once; stage positions
 // are the FP64 position plus the FP32 offset; the error is |sum e_i G_i^u|.
-template <class F>
-__device__ inline void incr_fp32(const F& field, float hf, float hk, const double x[3],
-                                 const float u[3], float G[6])
+__device__ inline void incr_from_field(float hf, float hk, const float u[3], const float B[3],
+                                        float G[6])
 {
-    float B[3], c[3];
-    field.fp32(x, B);
+    float c[3];
     cross3f(u, B, c);
     G[0] = hf * u[0];
     G[1] = hf * u[1];
@@ -518,16 +545,26 @@ __device__ inline void incr_fp32(const F& field, float hf, float hk, const doubl
     G[5] = hk * c[2];
 }
 
+// need / reuse / b1 as for ck_attempt_fp64 (b1 in FP32).
 template <class F>
-__device__ inline double ck_attempt_mix(const F& field, double kappa, const double x[3],
-                                        const double ud[3], double h, double x5[3],
-                                        double u5[3])
+__device__ inline double ck_attempt_mix_f(const F& field, double kappa, const double x[3],
+                                          const float u[3], double h, double x5[3],
+                                          float u5[3], bool need, bool reuse, float b1[3])
 {
     const float hf = (float)h;
     const float hk = (float)(h * kappa);
-    const float u[3] = {(float)ud[0], (float)ud[1], (float)ud[2]};
     float G[6][6];
-    incr_fp32(field, hf, hk, x, u, G[0]);
+    {
+        float B[3];
+        field.fp32(x, B, need && !reuse);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            if (reuse)
+                B[q] = b1[q];
+            b1[q] = B[q];
+        }
+        incr_from_field(hf, hk, u, B, G[0]);
+    }
 #pragma unroll
     for (int i = 1; i < 6; ++i) {
         float s[6];
@@ -546,7 +583,9 @@ __device__ inline double ck_attempt_mix(const F& field, double kappa, const doub
             xs[q] = x[q] + (double)s[q];
             us[q] = u[q] + s[3 + q];
         }
-        incr_fp32(field, hf, hk, xs, us, G[i]);
+        float B[3];
+        field.fp32(xs, B, need);
+        incr_from_field(hf, hk, us, B, G[i]);
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -557,7 +596,7 @@ __device__ inline double ck_attempt_mix(const F& field, double kappa, const doub
         if (q < 3)
             x5[q] = x[q] + (double)s;
         else
-            u5[q - 3] = (double)(u[q - 3] + s);
+            u5[q - 3] = u[q - 3] + s;
     }
     float e[3];
 #pragma unroll
@@ -572,36 +611,56 @@ __device__ inline double ck_attempt_mix(const F& field, double kappa, const doub
     return (double)sqrtf(dot3f(e, e));
 }
 
-// Same attempt with the direction held in FP32 (the precision form stores u
-// in FP32, so this is the same arithmetic without the FP64 round trip).
+// The same precision-form attempt with the six stages in a rolled loop, so
+// that the field evaluation appears once in the code.  Used where that
+// evaluation is large (the neural field: an inlined copy per stage would not
+// fit the instruction cache).  The stage sums keep the index order of the
+// unrolled form: a term j >= i is skipped, not added as zero.
 template <class F>
-__device__ inline double ck_attempt_mix_f(const F& field, double kappa, const double x[3],
-                                          const float u[3], double h, double x5[3],
-                                          float u5[3])
+__device__ inline double ck_attempt_mix_rolled(const F& field, double kappa, const double x[3],
+                                               const float u[3], double h, double x5[3],
+                                               float u5[3])
 {
+    static constexpr float A[6][5] = {
+        {(float)CK::a[0][0], (float)CK::a[0][1], (float)CK::a[0][2], (float)CK::a[0][3], (float)CK::a[0][4]},
+        {(float)CK::a[1][0], (float)CK::a[1][1], (float)CK::a[1][2], (float)CK::a[1][3], (float)CK::a[1][4]},
+        {(float)CK::a[2][0], (float)CK::a[2][1], (float)CK::a[2][2], (float)CK::a[2][3], (float)CK::a[2][4]},
+        {(float)CK::a[3][0], (float)CK::a[3][1], (float)CK::a[3][2], (float)CK::a[3][3], (float)CK::a[3][4]},
+        {(float)CK::a[4][0], (float)CK::a[4][1], (float)CK::a[4][2], (float)CK::a[4][3], (float)CK::a[4][4]},
+        {(float)CK::a[5][0], (float)CK::a[5][1], (float)CK::a[5][2], (float)CK::a[5][3], (float)CK::a[5][4]}};
     const float hf = (float)h;
     const float hk = (float)(h * kappa);
     float G[6][6];
-    incr_fp32(field, hf, hk, x, u, G[0]);
 #pragma unroll
-    for (int i = 1; i < 6; ++i) {
-        float s[6];
+    for (int j = 0; j < 6; ++j)
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-            float acc = (float)CK::a[i][0] * G[0][q];
-#pragma unroll
-            for (int j = 1; j < i; ++j)
-                acc = acc + (float)CK::a[i][j] * G[j][q];
-            s[q] = acc;
-        }
+        for (int q = 0; q < 6; ++q)
+            G[j][q] = 0.0f;
+#pragma unroll 1
+    for (int i = 0; i < 6; ++i) {
         double xs[3];
         float us[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            xs[q] = x[q] + (double)s[q];
-            us[q] = u[q] + s[3 + q];
+        for (int q = 0; q < 6; ++q) {
+            float acc = A[i][0] * G[0][q];
+#pragma unroll
+            for (int j = 1; j < 5; ++j) {
+                const float t = acc + A[i][j] * G[j][q];
+                acc = j < i ? t : acc;
+            }
+            if (q < 3)
+                xs[q] = i == 0 ? x[q] : x[q] + (double)acc;
+            else
+                us[q - 3] = i == 0 ? u[q - 3] : u[q - 3] + acc;
         }
-        incr_fp32(field, hf, hk, xs, us, G[i]);
+        float B[3], Gi[6];
+        field.fp32(xs, B, true);
+        incr_from_field(hf, hk, us, B, Gi);
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                G[j][q] = j == i ? Gi[q] : G[j][q];
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {

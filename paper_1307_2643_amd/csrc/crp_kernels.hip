@@ -267,6 +267,10 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     double h = 0.0, kappa = 0.0;
     int64_t slot = 0;
     bool active = false, fresh = true;
+    // field at the current position, kept for the retry after a rejection
+    using BT = typename DirType<MODE>::T;
+    BT b1[3] = {0, 0, 0};
+    bool reuse = false;
     bool dry = false, initial_left = true;
     uint32_t iter = 0;
 
@@ -319,6 +323,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                         S.azf[t] = pack_azf(q.A[slot], q.Z[slot], LIM_CTRL);
                         active = true;
                         fresh = true;
+                        reuse = false;
                     }
                 }
             }
@@ -383,14 +388,17 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             if constexpr (MODE == MODE_FP64) {
                 const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
-                err = ck_attempt_fp64(F, kappa, y, h, y5);
+                err = ck_attempt_fp64(F, kappa, y, h, y5, active, reuse, b1);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     x5[q] = y5[q];
                     u5[q] = y5[3 + q];
                 }
             } else {
-                err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5);
+                if constexpr (LAYOUT == 3)
+                    err = ck_attempt_mix_rolled(F, kappa, x, u, h, x5, u5);
+                else
+                    err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5, active, reuse, b1);
             }
         }
         if (active) {
@@ -398,6 +406,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             const double r = err / sp.tol;
             if (r <= 1.0 || h <= sp.hmin) {
                 ev |= EV_ACCEPT;
+                reuse = false;
                 if (r > 1.0)
                     ev |= EV_FORCED;
                 double fac = 5.0;
@@ -507,6 +516,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                 }
                 fresh = true;
             } else {
+                reuse = true;             // same position: b1 holds its field
                 S.nrej[t] += 1u;
                 double fac = (double)ctrl_k(r) / 1024.0;
                 if (fac < 0.1)

@@ -220,8 +220,10 @@ __device__ __attribute__((always_inline)) inline void nf_eval_wave(const NFView&
 // the whole wave takes part in every evaluation).
 struct NeuralFieldSrc {
     NFView v;
-    __device__ inline void fp32(const double p[3], float B[3]) const
+    // the whole wave evaluates the network together, so `need` saves nothing
+    __device__ inline void fp32(const double p[3], float B[3], bool need = true) const
     {
+        (void)need;
         float xh[3], o[3];
         nf_xhat(v, p, xh);
         nf_eval_wave(v, xh, o);
@@ -229,10 +231,10 @@ struct NeuralFieldSrc {
         B[1] = v.b_scale * o[1];
         B[2] = v.b_scale * o[2];
     }
-    __device__ inline void fp64(const double p[3], double B[3]) const
+    __device__ inline void fp64(const double p[3], double B[3], bool need = true) const
     {
         float b[3];
-        fp32(p, b);
+        fp32(p, b, need);
         B[0] = b[0];
         B[1] = b[1];
         B[2] = b[2];

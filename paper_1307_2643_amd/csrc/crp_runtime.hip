@@ -1018,8 +1018,16 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     const size_t qbytes = queue_layout(nullptr, ctx->q.cap, nullptr);
     void* backup = nullptr;
     HIPCHK(ctx, hipMalloc(&backup, qbytes));
-    HIPCHK(ctx, hipMemcpyAsync(backup, ctx->qmem[0], qbytes, hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    {
+        hipError_t e =
+            hipMemcpyAsync(backup, ctx->qmem[0], qbytes, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(backup);
+            return fail(ctx, CRP_EDEVICE, std::string("tune: ") + hipGetErrorString(e));
+        }
+    }
     const crp_launch orig = ctx->launch;
     const int64_t fin0 = ctx->fin_unread, neu0 = ctx->neu_unread;
     std::vector<crp_launch> cands;
@@ -1033,26 +1041,37 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     crp_launch bestl = orig;
     double bestr = -1.0;
     crp_status st = CRP_OK;
+    // every shape is timed twice on the same work and keeps its better rate
+    // (a single short trial is too noisy to separate shapes a few % apart)
     for (const crp_launch& l : cands) {
-        // restore the queue (the park buffer swap may have moved it)
-        ctx->q = QueueSoA();
-        queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
-        HIPCHK(ctx, hipMemcpyAsync(ctx->qmem[0], backup, qbytes, hipMemcpyDeviceToDevice,
-                                   ctx->stream));
-        queue_layout((char*)ctx->qmem[1], ctx->park.cap, &ctx->park);
-        ctx->pending = np;
-        ctx->fin_unread = fin0;
-        ctx->neu_unread = neu0;
-        ctx->launch = l;
-        DevCounters dc;
-        st = run_kernel(ctx, max_cycles, &dc);
+        for (int rep = 0; rep < 2 && st == CRP_OK; ++rep) {
+            // restore the queue (the park buffer swap may have moved it)
+            ctx->q = QueueSoA();
+            queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
+            const hipError_t e = hipMemcpyAsync(ctx->qmem[0], backup, qbytes,
+                                                hipMemcpyDeviceToDevice, ctx->stream);
+            if (e != hipSuccess) {
+                st = fail(ctx, CRP_EDEVICE, std::string("tune: ") + hipGetErrorString(e));
+                break;
+            }
+            queue_layout((char*)ctx->qmem[1], ctx->park.cap, &ctx->park);
+            ctx->pending = np;
+            ctx->fin_unread = fin0;
+            ctx->neu_unread = neu0;
+            ctx->launch = l;
+            DevCounters dc;
+            st = run_kernel(ctx, max_cycles, &dc);
+            if (st != CRP_OK)
+                break;
+            const double rate =
+                ctx->last_ms > 0 ? (double)dc.steps / (ctx->last_ms * 1e-3) : 0.0;
+            if (rate > bestr) {
+                bestr = rate;
+                bestl = l;
+            }
+        }
         if (st != CRP_OK)
             break;
-        const double rate = ctx->last_ms > 0 ? (double)dc.steps / (ctx->last_ms * 1e-3) : 0.0;
-        if (rate > bestr) {
-            bestr = rate;
-            bestl = l;
-        }
     }
     // restore the pending work exactly as it was
     queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
