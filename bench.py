@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
     ap.add_argument("--nf-steps", type=int, default=1526,
                     help="training steps of 65536 points (1526 steps = 1e8 points)")
+    ap.add_argument("--nf-only", action="store_true",
+                    help="diagnostic: only the neural-field variant (training, field error, "
+                         "surrogate vs grid); prints that variant's JSON")
     ap.add_argument("--batching", type=int, default=0, metavar="NBATCH",
                     help="also run the batching form: NBATCH batches of 1e7 candidates at "
                          "distances 1..1000 Mpc (10 = the 1e8-candidate stream)")
@@ -105,6 +108,15 @@ def main():
     inj = w.make_injection(n)
     d_inj = [torch.as_tensor(a, device=dev) for a in
              (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+
+    if args.nf_only:
+        lch = dict(block=128, blocks_per_cu=4, refill=32, layout=1)
+        if args.launch:
+            b, bpc, rf, lay = [int(v) for v in args.launch.split(",")]
+            lch = dict(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
+        nf = neural_variant(args, crp, I, torch, w, grid, tables, stream, lch)
+        print(json.dumps({"variant": "nf", **nf}), flush=True)
+        return
 
     def context(precision):
         prm = crp.params_for(w, precision, device=0, queue_capacity=2 * n,
@@ -440,7 +452,15 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
            "final_train_loss": float(losses[-1]), "field_bytes_network": 66435 * 2,
            "field_bytes_grid": int(grid.numel() * 4),
            "workload": f"{wd.name} subset of {args.nf_candidates} candidates (seed 508)",
-           "steps": {"nf": c_nf["steps"], "grid": c_g["steps"]}}
+           "steps": {"nf": c_nf["steps"], "grid": c_g["steps"]},
+           "attempts": {"nf": c_nf["attempts"], "grid": c_g["attempts"]},
+           "kernel_time_ratio_nf_over_grid": ms_nf / ms_g}
+    # MFMA work of the network: four 128x128 layers per evaluation, six
+    # evaluations per Cash-Karp attempt (the 128->3 output layer runs on the VALU)
+    flop = 6 * 4 * 2 * 128 * 128
+    achieved = c_nf["attempts"] * flop / (ms_nf * 1e-3) / 1e12
+    out["mfma"] = {"bound": "mfma", "flop_per_attempt": flop, "achieved": achieved,
+                   "peak": 2500.0, "unit": "TFLOP/s", "frac": achieved / 2500.0}
     log(f"[bench] NF form: {rate_nf:.3e} steps/s vs grid {rate_g:.3e} on the same batch; "
         f"deflection histogram distance {out['deflection_hist_distance']:.4f}, KS {ks:.4f}")
     return out

@@ -99,11 +99,17 @@ __device__ __attribute__((always_inline)) inline float nf_relu(float v) { return
 // Hides an LDS pointer's value from the optimiser: inside persistent loops
 // the weight loads must stay next to their MFMAs instead of being hoisted out
 // of the loop (which would need hundreds of registers).
+// The pointer is hidden as its 32-bit LDS address and turned back into a
+// pointer from the LDS address space, so that the loads through it remain LDS
+// loads (a laundered generic pointer would turn them into flat loads, each
+// waited for on its own).
 template <class T>
 __device__ __attribute__((always_inline)) inline const T* nf_launder(const T* p)
 {
-    asm volatile("" : "+s"(p));
-    return p;
+    typedef const __attribute__((address_space(3))) T* lds_ptr;
+    uint32_t a = (uint32_t)(uintptr_t)(lds_ptr)p;
+    asm volatile("" : "+s"(a));
+    return (const T*)(lds_ptr)(uintptr_t)a;
 }
 
 // Fourier features of one point (this lane's half: group g) as B operand.
@@ -153,9 +159,11 @@ __device__ __attribute__((always_inline)) inline void nf_layer(const __bf16* wim
     }
 }
 
-// Output layer on the vector ALU: partial dot products over this lane's 64
-// features, completed with the partner lane (l ^ 32); every lane returns the
-// outputs of its own point (lanes 0..31: column block 0, 32..63: block 1).
+// Output layer on the matrix cores: W5 (3 x 128) is the A operand of a
+// 32-row tile whose rows 3..31 are zero, so rows 0..2 of the result (the three
+// outputs) land in registers 0..2 of lanes 0..31 for the 32 points of each
+// column block.  Every lane returns the outputs of its own point (lanes 0..31:
+// column block 0, 32..63: block 1, moved across by a lane swap).
 __device__ __attribute__((always_inline)) inline void nf_output(const __bf16* w5, const float* b5, const bf16x8 h[2][8],
                                  float out[3])
 {
@@ -163,27 +171,23 @@ __device__ __attribute__((always_inline)) inline void nf_output(const __bf16* w5
     b5 = nf_launder(b5);
     const int lane = (int)(threadIdx.x & 63u);
     const int g = lane >> 5;
-    float part[2][3];
+    const int row = lane & 31;
+    const bool live = row < 3;
+    const __bf16* wrow = w5 + (live ? row : 0) * NF_WIDTH + 8 * g;
+    floatx16 acc0 = {}, acc1 = {};
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int m = 0; m < 8; ++m) {
+        bf16x8 a = *(const bf16x8*)(wrow + 16 * m);
+        if (!live)
+            a = bf16x8{};
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, h[0][m], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, h[1][m], acc1, 0, 0, 0);
+    }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float s = 0.0f;
-#pragma unroll
-            for (int m = 0; m < 8; ++m)
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    s += (float)w5[c * NF_WIDTH + 16 * m + 8 * g + j] * (float)h[cb][m][j];
-            part[cb][c] = s;
-        }
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            part[cb][c] += __shfl_xor(part[cb][c], 32);
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-        out[c] = (g == 0 ? part[0][c] : part[1][c]) + b5[c];
+    for (int c = 0; c < 3; ++c) {
+        const float other = __shfl_xor(acc1[c], 32);
+        out[c] = (g == 0 ? acc0[c] : other) + b5[c];
+    }
 }
 
 // Normalised position of a point in [0, 1)^3 (FP64, then FP32).

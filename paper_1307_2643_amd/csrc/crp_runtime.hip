@@ -330,7 +330,9 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.sp.renorm = c.renormalize;
     P.max_cycles = max_cycles;
     P.tail0 = (unsigned long long)ctx->pending;
-    P.refill = ctx->launch.refill;
+    // the neural-field stepper costs the same per wave however many lanes are
+    // busy, so it refills a lane as soon as it is idle
+    P.refill = c.field_mode == CRP_FIELD_NEURAL ? 1 : ctx->launch.refill;
 
     const bool neural = c.field_mode == CRP_FIELD_NEURAL;
     if (neural)
