@@ -143,7 +143,12 @@ def main():
         ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
     elif not args.no_tune:
         t0 = time.time()
-        inject(ctx, min(n, 1 << 20))
+        # calibration: 4M candidates (about 20 per lane, so that the ramp at the
+        # end of a short trial does not favour small launches), timed on the
+        # spread-out state after 64 cycles rather than on the first cycles near
+        # the common source (whose field reads share the L2)
+        inject(ctx, min(n, 1 << 22))
+        ctx.propagate(64)
         tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
         ctx.discard_finished()
         while not ctx.propagate(0):
@@ -186,6 +191,16 @@ def main():
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     log(f"[bench] precision form: {value:.4e} steps/s, {ms_per_step:.1f} ms/step, "
         f"kernel {kernel_ms:.1f} ms, {achieved:.1f} GB/s algorithmic")
+
+    # ---- the gather pattern alone on the same corner records (diagnostic) ---
+    ceiling = None
+    if launch["layout"] == crp.LAYOUT_CORNER:
+        rec_s = ctx.gather_ceiling(20000)
+        ceiling = {"records_per_s": rec_s, "algorithmic_GBps": rec_s * 96 / 1e9,
+                   "line_GBps": rec_s * 128 / 1e9,
+                   "kernel_frac_of_ceiling": achieved / (rec_s * 96 / 1e9)}
+        log(f"[bench] gather pattern alone: {rec_s:.3e} records/s = {rec_s * 96 / 1e9:.0f} GB/s "
+            f"algorithmic ({rec_s * 128 / 1e9:.0f} GB/s in 128-byte lines)")
 
     # ---- sample for the stated error: MIX (GPU) vs FP64 oracle --------------
     nsample = 0 if args.no_sample else min(n, 2000)
@@ -313,6 +328,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_propagate<MIX,float,%s>" % ("corner-coop" if launch["layout"] else "linear"),
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "gather_ceiling": ceiling,
                      "attempts_per_launch": attempts_per_launch},
         "cpu_baseline": cpu,
     }
@@ -347,7 +363,8 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
         ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
                    lmax=d[6][s], on_device=True)
 
-    inject(batches[0], 1 << 20)
+    inject(batches[0], 1 << 22)
+    ctx.propagate(64)
     tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
     ctx.discard_finished()
     while not ctx.propagate(0):

@@ -188,7 +188,7 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* 
                           int32_t mode, int32_t on_device);
 
 /* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
- * A new context starts with {128, 4, 32, CRP_LAYOUT_LINEAR}.
+ * A new context starts with {128, 0, 32, CRP_LAYOUT_LINEAR}.
  * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra
  * device memory (built on first use). */
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);
@@ -205,6 +205,15 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path,
 /* Timing of the last crp_propagate: summed duration of its propagation
  * kernel launches (HIP events on the context stream), ms, and launch count. */
 crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches);
+
+/* Diagnostic, not a step of the method: times the field-gather pattern alone
+ * (the cooperative corner-record gather of the propagation kernel) on this
+ * context's corner records (built on first use, as for CRP_LAYOUT_CORNER),
+ * `iters` random records per lane with the context's blocks per CU (block
+ * 128).  records_per_s: gathered records per second, the practical ceiling of
+ * the field evaluation.  CRP_ESTATE without a grid, CRP_EINVAL for an FP64 grid
+ * or iters < 1. */
+crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s);
 
 /* Checkpoint: pending candidates, undrained records and counters.  The blob
  * is allocated by the library and released with crp_free. */

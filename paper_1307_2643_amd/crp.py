@@ -30,7 +30,8 @@ NF_NPARAM = 66435
 EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_tables", "crp_inject",
            "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_peek_pending",
            "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_set_launch",
-           "crp_get_launch", "crp_tune", "crp_last_timing", "crp_snapshot", "crp_restore",
+           "crp_get_launch", "crp_tune", "crp_last_timing", "crp_gather_ceiling",
+           "crp_snapshot", "crp_restore",
            "crp_free", "crp_nf_init", "crp_nf_get_params", "crp_nf_loss_grad", "crp_nf_train",
            "crp_last_error")
 
@@ -120,6 +121,7 @@ def load():
         "crp_get_launch": ([vp, _P(Launch)], C.c_int),
         "crp_tune": ([vp, i64, C.c_char_p, _P(Launch), _P(dbl)], C.c_int),
         "crp_last_timing": ([vp, _P(dbl), _P(i64)], C.c_int),
+        "crp_gather_ceiling": ([vp, i32, _P(dbl)], C.c_int),
         "crp_snapshot": ([vp, _P(vp), _P(C.c_size_t)], C.c_int),
         "crp_restore": ([vp, vp, C.c_size_t], C.c_int),
         "crp_free": ([vp], None),
@@ -332,7 +334,7 @@ class Context:
         return out
 
     # -- launch shape / tuning / timing ---------------------------------------
-    def set_launch(self, block=128, blocks_per_cu=4, refill=32, layout=LAYOUT_LINEAR):
+    def set_launch(self, block=128, blocks_per_cu=0, refill=32, layout=LAYOUT_LINEAR):
         lch = Launch(block, blocks_per_cu, refill, layout)
         self._check(self.L.crp_set_launch(self.h, C.byref(lch)))
 
@@ -355,6 +357,12 @@ class Context:
         return ms.value, n.value
 
     # -- checkpoint -----------------------------------------------------------
+    def gather_ceiling(self, iters=2000):
+        """Records/s of the cooperative field gather alone (diagnostic)."""
+        r = C.c_double(0)
+        self._check(self.L.crp_gather_ceiling(self.h, int(iters), C.byref(r)))
+        return r.value
+
     def snapshot(self) -> bytes:
         p = C.c_void_p()
         n = C.c_size_t(0)

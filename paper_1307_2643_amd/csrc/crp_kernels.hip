@@ -201,9 +201,11 @@ struct DirType<MODE_MIX> {
 };
 
 // Minimum waves per SIMD the register allocation targets (occupancy vs
-// spills), per precision form.
+// spills), per precision form.  Measured on the 1e7 batch, 1024^3 grid:
+// the precision form is fastest at 3 (12 waves per CU, a few rare-path
+// spills), the FP64 form at 2 (at 3 it spills in the attempt itself).
 #ifndef CRP_WAVES_MIX
-#define CRP_WAVES_MIX 2
+#define CRP_WAVES_MIX 3
 #endif
 #ifndef CRP_WAVES_FP64
 #define CRP_WAVES_FP64 2
@@ -793,6 +795,41 @@ template __global__ void k_eval_field<float, 1>(GridView, int64_t, const double*
 // -------------------------------------------------------------------------
 // Corner-replicated layout: record of cell (i,j,k) = the 8 corner vectors
 // (c = dx + 2 dy + 4 dz) of an FP32 linear grid, padded to 128 bytes.
+// -------------------------------------------------------------------------
+// Diagnostic (not a step of the method): the field-gather pattern alone.
+// Every wave repeatedly gathers the corner records of 64 pseudo-random cells
+// with the propagation kernel's cooperative gather and folds one value of
+// each into a checksum, so the rate it reaches is the practical ceiling of
+// the field evaluation on this buffer.
+// -------------------------------------------------------------------------
+__device__ inline uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void __launch_bounds__(128) k_gather_ceiling(const float* corner, uint32_t ncell,
+                                                        int iters, float* sink)
+{
+    __shared__ float4 stage[2 * COOP_STAGE_FLOAT4];
+    const int t = (int)threadIdx.x;
+    float* st = (float*)(stage + (t >> 6) * COOP_STAGE_FLOAT4);
+    uint32_t s = mix32((uint32_t)blockIdx.x * 128u + (uint32_t)t + 0x9e3779b9u);
+    float acc = 0.0f;
+    for (int it = 0; it < iters; ++it) {
+        s = mix32(s + 0x9e3779b9u);
+        const uint32_t cell = (uint32_t)(((uint64_t)s * ncell) >> 32);   // < ncell
+        float v[8][3];
+        gather_corner_coop(corner, cell, st, v, true);
+        acc += v[t & 7][0];
+    }
+    sink[(int64_t)blockIdx.x * 128 + t] = acc;
+}
+
 // -------------------------------------------------------------------------
 __global__ void k_corner_relayout(GridView g, float* out)
 {

@@ -34,6 +34,7 @@ __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id
                          const double* pos, const double* dir, const double* lmax,
                          uint64_t seed, double hmin, int mix);
 __global__ void k_corner_relayout(GridView g, float* out);
+__global__ void k_gather_ceiling(const float* corner, uint32_t ncell, int iters, float* sink);
 }  // namespace crp
 
 using namespace crp;
@@ -467,7 +468,7 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     ctx->stream = (hipStream_t)stream;
     std::memset(&ctx->totals, 0, sizeof ctx->totals);
     ctx->launch.block = 128;
-    ctx->launch.blocks_per_cu = 4;
+    ctx->launch.blocks_per_cu = 0;
     ctx->launch.refill = 32;
     ctx->launch.layout = CRP_LAYOUT_LINEAR;
     auto bail = [&](crp_status st, const char* what, hipError_t e) {
@@ -999,6 +1000,41 @@ crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches)
         *kernel_ms = ctx->last_ms;
     if (launches)
         *launches = ctx->last_launches;
+    return CRP_OK;
+}
+
+// ---- diagnostic: the gather pattern alone -------------------------------
+crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s)
+{
+    if (!ctx || !records_per_s || iters < 1)
+        return CRP_EINVAL;
+    if (!ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "gather_ceiling: set the grid first");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    crp_status st = ensure_corner(ctx);
+    if (st != CRP_OK)
+        return st;
+    const int bpc = ctx->launch.blocks_per_cu > 0 ? ctx->launch.blocks_per_cu : 4;
+    const int nb = ctx->num_cus * bpc;
+    float* sink = nullptr;
+    HIPCHK(ctx, hipMalloc((void**)&sink, (size_t)nb * 128 * sizeof(float)));
+    const uint32_t ncell = (uint32_t)(ctx->gn[0] * ctx->gn[1] * ctx->gn[2]);
+    hipError_t e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess) {
+        k_gather_ceiling<<<nb, 128, 0, ctx->stream>>>(ctx->corner, ncell, iters, sink);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(ctx->ev1);
+    float ms = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    (void)hipFree(sink);
+    if (e != hipSuccess)
+        return fail(ctx, CRP_EDEVICE, std::string("gather_ceiling: ") + hipGetErrorString(e));
+    *records_per_s = (double)nb * 128.0 * (double)iters / ((double)ms * 1e-3);
     return CRP_OK;
 }
 
