@@ -143,13 +143,11 @@ def main():
         ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
     elif not args.no_tune:
         t0 = time.time()
-        # calibration: 4M candidates (about 20 per lane, so that the ramp at the
-        # end of a short trial does not favour small launches), timed on the
-        # spread-out state after 64 cycles rather than on the first cycles near
-        # the common source (whose field reads share the L2)
-        inject(ctx, min(n, 1 << 22))
-        ctx.propagate(64)
-        tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
+        # calibration: 6M candidates (about 30 per lane of a full launch) run to
+        # completion, so that every trial includes the end of a run (its tail
+        # and the secondaries' phase) in the proportion of the timed batch
+        inject(ctx, min(n, 6_000_000))
+        tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
         ctx.discard_finished()
         while not ctx.propagate(0):
             pass
@@ -222,7 +220,9 @@ def main():
         ctx.discard_finished()
     ctx.close()
 
-    variants = {"mix": {"steps_per_s": value, "kernel_ms": kernel_ms, "launch": launch}}
+    variants = {"mix": {"steps_per_s": value, "kernel_ms": kernel_ms, "launch": launch,
+                        "attempts_per_launch": attempts_per_launch,
+                        "lane_utilisation": attempts_total / max(cnt["lane_slots"], 1)}}
 
     # ---- FP64 method on the same FP32 grid ("plain grid") ----------------------
     fp64_fin = None
@@ -363,9 +363,8 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
         ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
                    lmax=d[6][s], on_device=True)
 
-    inject(batches[0], 1 << 22)
-    ctx.propagate(64)
-    tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
+    inject(batches[0], 6_000_000)
+    tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
     ctx.discard_finished()
     while not ctx.propagate(0):
         pass

@@ -81,7 +81,9 @@ typedef struct {
                                  as many as the kernel's occupancy lets one
                                  compute unit hold at once */
     int32_t refill;           /* a wave claims new candidates once this many of its
-                                 64 lanes are idle (1..64) */
+                                 64 lanes are idle (1..64); secondaries appended
+                                 during the run are claimed once at least
+                                 max(refill, 32) lanes are idle */
     int32_t layout;           /* CRP_LAYOUT_LINEAR or CRP_LAYOUT_CORNER */
 } crp_launch;
 
@@ -108,6 +110,9 @@ typedef struct {
     int64_t queue_dropped, neutral_dropped;
     int64_t pending;          /* candidates waiting for the next propagate */
     int64_t finished_unread, neutral_unread;
+    int64_t lane_slots;       /* 64 x wave iterations of the propagation kernel:
+                                 attempts / lane_slots is the fraction of lanes
+                                 that carried a candidate */
 } crp_counters;
 
 typedef struct crp_ctx crp_ctx;

@@ -77,7 +77,7 @@ class NeutralSoA(C.Structure):
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts",
                 "rejects", "forced", "events", "null_events", "inter_pi", "inter_n",
                 "charged_sec", "neutral_sec", "queue_dropped", "neutral_dropped", "pending",
-                "finished_unread", "neutral_unread")
+                "finished_unread", "neutral_unread", "lane_slots")
 
 
 class Counters(C.Structure):

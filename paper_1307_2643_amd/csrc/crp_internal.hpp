@@ -47,6 +47,7 @@ struct DevCounters {
     unsigned long long charged_sec, neutral_sec;
     unsigned long long finished, observed, max_traj, energy_floor;
     unsigned long long queue_dropped, neutral_dropped;
+    unsigned long long lane_slots;          // 64 x wave iterations
     unsigned long long error;               // nonzero: a wait timed out
 };
 

@@ -53,7 +53,7 @@ __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
 // with an LDS atomic where they happen.
 enum {
     WC_STEPS = 0, WC_ATTEMPTS, WC_REJECTS, WC_FORCED, WC_EVENTS, WC_NULL, WC_PI, WC_N,
-    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_COUNT
+    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_LANES, WC_COUNT
 };
 enum : uint32_t { EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_FIN = 1u << 3 };
 
@@ -74,7 +74,8 @@ __device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* 
     unsigned long long* dst[WC_COUNT] = {
         &cnt->steps, &cnt->attempts, &cnt->rejects, &cnt->forced, &cnt->events,
         &cnt->null_events, &cnt->inter_pi, &cnt->inter_n, &cnt->finished, &cnt->observed,
-        &cnt->max_traj, &cnt->energy_floor, &cnt->queue_dropped, &cnt->neutral_dropped};
+        &cnt->max_traj, &cnt->energy_floor, &cnt->queue_dropped, &cnt->neutral_dropped,
+        &cnt->lane_slots};
     const int i = (int)threadIdx.x;
     if (i < WC_COUNT && bc[i] != 0ull) {
         atomicAdd(dst[i], bc[i]);
@@ -86,6 +87,8 @@ __device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* 
             atomicAdd(&cnt->charged_sec, bc[i]);
     }
 }
+
+constexpr int APPEND_REFILL = 32;   // idle lanes before a wave claims appended slots
 
 // Claims up to `want` slots: first from the region written before the launch
 // with one atomicAdd (overshoot past tail0 is harmless there), then from the
@@ -124,6 +127,7 @@ __device__ inline void claim_slots(DevCounters* cnt, unsigned long long tail0,
             take = n;
             return;
         }
+        __builtin_amdgcn_s_sleep(2);   // back off: another wave won the cursor
     }
 }
 
@@ -216,7 +220,9 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     k_propagate(const PropParams* __restrict__ PP)
 {
     using UT = typename DirType<MODE>::T;   // direction storage: FP64 or FP32
-    extern __shared__ double lds[];           // interaction tables
+    // interaction tables, then (neural field) the network image, whose 16-byte
+    // operand loads need 16-byte alignment whatever the static LDS size
+    extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ LaneShared<BS> S;              // per-lane cold state
     __shared__ unsigned long long bc[WC_COUNT];   // block bookkeeping counters
     // LDS staging of the wave-cooperative corner gather (LAYOUT 2 only)
@@ -280,14 +286,21 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         // ---- refill idle lanes from the queue -------------------------------
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
-        if (dry && nidle >= refill && (iter & 63u) == 0u && idle != ~0ull) {
+        // claims from the region appended during the run go through a
+        // compare-and-swap on one cursor; they wait for at least APPEND_REFILL
+        // idle lanes, so that few waves contend for that cursor at a time (the
+        // neural-field stepper's iterations are long enough not to contend)
+        const int need = LAYOUT == 3 || initial_left || refill >= APPEND_REFILL
+                             ? refill
+                             : APPEND_REFILL;
+        if (dry && nidle >= need && (iter & 63u) == 0u && idle != ~0ull) {
             bool avail = false;
             if (lane == 0)
                 avail = appended_available(cnt, qcap);
             if (__shfl((int)avail, 0))
                 dry = false;
         }
-        if (idle == ~0ull || (!dry && nidle >= refill)) {
+        if (idle == ~0ull || (!dry && nidle >= need)) {
             unsigned long long base = 0, take = 0;
             bool left = false;
             if (lane == 0)
@@ -683,6 +696,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             add_count(bc, WC_STEPS, acc);
             add_count(bc, WC_REJECTS, att - acc);
             add_count(bc, WC_FORCED, frc);
+            add_count(bc, WC_LANES, 64ull);
         }
     }
     __syncthreads();   // every wave of the block has left the loop

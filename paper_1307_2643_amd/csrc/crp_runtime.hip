@@ -434,6 +434,7 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
         t.neutral_sec += dc.neutral_sec;
         t.queue_dropped += dc.queue_dropped;
         t.neutral_dropped += dc.neutral_dropped;
+        t.lane_slots += dc.lane_slots;
     }
     ctx->pending = (int64_t)dc.park_n;
     if (dc.park_n > 0) {
@@ -1071,11 +1072,10 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     std::vector<crp_launch> cands;
     const bool corner_ok = ctx->grid_dtype == CRP_F32;
     for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
-        for (int bs : {128, 256})
-            for (int bpc : {0, 2, 3, 4, 5, 8})
-                for (int rf : {16, 32})
-                    if (bpc == 0 || (bs * bpc <= 1024 && bs * bpc >= 384))
-                        cands.push_back(crp_launch{bs, bpc, rf, layout});
+        for (const crp_launch& l : {crp_launch{128, 0, 32, 0}, crp_launch{128, 0, 16, 0},
+                                    crp_launch{128, 4, 32, 0}, crp_launch{128, 5, 32, 0},
+                                    crp_launch{256, 0, 32, 0}})
+            cands.push_back(crp_launch{l.block, l.blocks_per_cu, l.refill, layout});
     crp_launch bestl = orig;
     double bestr = -1.0;
     crp_status st = CRP_OK;

@@ -106,13 +106,9 @@ def _check_whole_batch(P, fin, neu, cnt, n):
 def test_autotuned_launch(P, big):
     """The benchmark's tuning step, on the same calibration batch."""
     ctx = _context(P, big, P.MIX)
-    _inject(ctx, big["d_inj"], 1 << 22)
-    say("autotuning on 2^22 candidates")
-    assert not ctx.propagate(64)
-    tuned, rate = ctx.tune(max_cycles=48, cache_path=None)
-    ctx.discard_finished()
-    while not ctx.propagate(0):
-        pass
+    _inject(ctx, big["d_inj"], 6_000_000)
+    say("autotuning on 6e6 candidates")
+    tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
     ctx.close()
     big["launch"] = dict(tuned)
     say(f"tuned launch {big['launch']} ({rate:.3e} steps/s)")
