@@ -190,6 +190,24 @@ def main():
     log(f"[bench] precision form: {value:.4e} steps/s, {ms_per_step:.1f} ms/step, "
         f"kernel {kernel_ms:.1f} ms, {achieved:.1f} GB/s algorithmic")
 
+    # ---- the same step across the host boundary (not the headline) ---------
+    # host arrays in, finished and neutral records back to host arrays: the
+    # rate a caller that keeps its data on the host sees (PCIe and host-side
+    # record conversion included)
+    ctx.reset_counters()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.inject(inj)
+    ctx.propagate(0)
+    hf = ctx.read_finished()
+    hn = ctx.read_neutral()
+    torch.cuda.synchronize()
+    host_wall = time.perf_counter() - t1
+    host_rate = ctx.counts()["steps"] / host_wall
+    log(f"[bench] across the host boundary: {host_rate:.4e} steps/s ({host_wall:.2f} s, "
+        f"{len(hf['id'])} finished and {len(hn['id'])} neutral records read back)")
+    del hf, hn
+
     # ---- the gather pattern alone on the same corner records (diagnostic) ---
     ceiling = None
     if launch["layout"] == crp.LAYOUT_CORNER:
@@ -222,7 +240,8 @@ def main():
 
     variants = {"mix": {"steps_per_s": value, "kernel_ms": kernel_ms, "launch": launch,
                         "attempts_per_launch": attempts_per_launch,
-                        "lane_utilisation": attempts_total / max(cnt["lane_slots"], 1)}}
+                        "lane_utilisation": attempts_total / max(cnt["lane_slots"], 1),
+                        "host_boundary_steps_per_s": host_rate}}
 
     # ---- FP64 method on the same FP32 grid ("plain grid") ----------------------
     fp64_fin = None
