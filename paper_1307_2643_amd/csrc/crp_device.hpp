@@ -296,13 +296,12 @@ constexpr int COOP_STAGE_FLOAT4 = 384;   // float4 slots of one wave's staging a
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
-__device__ inline void gather_corner_coop(const float* corner, uint32_t cell, float* stage,
-                                          float v[8][3], bool need)
+// Issue half: the loads of the records of lanes with `need` into the staging
+// area (records no lane needs are not fetched).
+__device__ inline void coop_issue(const float* corner, uint32_t cell, float* stage, bool need)
 {
     const int lane = (int)(threadIdx.x & 63u);
     float4* st = (float4*)stage;
-    // records of lanes that do not need the field (idle lanes, reused values)
-    // are not fetched; those lanes get whatever the staging area holds
     const uint64_t needm = __ballot(need);
 #pragma unroll
     for (int half = 0; half < 2; ++half)
@@ -318,12 +317,19 @@ __device__ inline void gather_corner_coop(const float* corner, uint32_t cell, fl
                                                  (lds_void_ptr)(st + 192 * half + 64 * j), 16, 0,
                                                  0);
         }
+}
+
+// Consume half: waits for the loads, then every lane reads its own record
+// (lanes whose record was not fetched get whatever the area holds).
+__device__ inline void coop_consume(const float* stage, float v[8][3])
+{
+    const int lane = (int)(threadIdx.x & 63u);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float f[24];
-    const float4* my = st + 192 * (lane >> 5) + 6 * (lane & 31);
+    const float4* my = (const float4*)stage + 192 * (lane >> 5) + 6 * (lane & 31);
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
         const float4 x = my[q];
@@ -342,6 +348,13 @@ __device__ inline void gather_corner_coop(const float* corner, uint32_t cell, fl
         v[k][1] = f[3 * k + 1];
         v[k][2] = f[3 * k + 2];
     }
+}
+
+__device__ inline void gather_corner_coop(const float* corner, uint32_t cell, float* stage,
+                                          float v[8][3], bool need)
+{
+    coop_issue(corner, cell, stage, need);
+    coop_consume(stage, v);
 }
 
 __device__ inline int64_t cell_index(const GridView& g, const Cell& c)
@@ -428,6 +441,30 @@ struct GridField {
             for (int q = 0; q < 3; ++q)
                 vf[k][q] = (float)v[k][q];
         interp_fp32(c.t, vf, B);
+    }
+
+    // Split evaluation (cooperative layout only): prefetch() issues the loads
+    // of B(p) for the lanes with `need`; a later *_prefetched(p) with the same
+    // p completes it.  Nothing else may use the staging area in between.
+    __device__ inline void prefetch(const double p[3], bool need) const
+    {
+        static_assert(LAYOUT == 2, "split evaluation needs the cooperative layout");
+        const Cell c = locate(g, p);
+        coop_issue(g.corner, (uint32_t)cell_index(g, c), stage, need);
+    }
+    __device__ inline void fp32_prefetched(const double p[3], float B[3]) const
+    {
+        const Cell c = locate(g, p);
+        float v[8][3];
+        coop_consume(stage, v);
+        interp_fp32(c.t, v, B);
+    }
+    __device__ inline void fp64_prefetched(const double p[3], double B[3]) const
+    {
+        const Cell c = locate(g, p);
+        float v[8][3];
+        coop_consume(stage, v);
+        interp_fp64(c.t, v, B);
     }
 };
 

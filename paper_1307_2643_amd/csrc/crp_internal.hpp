@@ -48,7 +48,7 @@ struct DevCounters {
     unsigned long long finished, observed, max_traj, energy_floor;
     unsigned long long queue_dropped, neutral_dropped;
     unsigned long long lane_slots;          // 64 x wave iterations
-    unsigned long long error;               // nonzero: a wait timed out
+    unsigned long long error;               // nonzero: a wave gave up waiting
 };
 
 struct TableParams {
@@ -85,6 +85,7 @@ struct PropParams {
     StepParams sp;
     int64_t max_cycles;          // <= 0: no limit
     unsigned long long tail0;    // slots below were written before the launch
+    unsigned long long fin0;     // finished-record count at the launch
     int refill;                  // idle lanes that trigger a claim (1..64)
     NFProp nf;                   // used by the neural-field instantiation only
 };

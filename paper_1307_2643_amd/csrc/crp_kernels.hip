@@ -88,73 +88,44 @@ __device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* 
     }
 }
 
-constexpr int APPEND_REFILL = 32;   // idle lanes before a wave claims appended slots
-
-// Claims up to `want` slots: first from the region written before the launch
-// with one atomicAdd (overshoot past tail0 is harmless there), then from the
-// region appended during the run with a compare-and-swap on its own cursor.
-__device__ inline void claim_slots(DevCounters* cnt, unsigned long long tail0,
-                                   unsigned long long cap, int want, bool try_initial,
-                                   unsigned long long& base, unsigned long long& take,
-                                   bool& initial_left)
+// Claims up to `want` slots of the region written before the launch with one
+// atomicAdd (overshoot past tail0 is harmless: that region does not grow).
+__device__ inline void claim_initial(DevCounters* cnt, unsigned long long tail0, int want,
+                                     unsigned long long& base, unsigned long long& take,
+                                     bool& left)
 {
+    const unsigned long long b = atomicAdd(&cnt->head, (unsigned long long)want);
+    base = b;
     take = 0;
-    base = 0;
-    initial_left = false;
-    if (try_initial) {
-        const unsigned long long b = atomicAdd(&cnt->head, (unsigned long long)want);
-        if (b < tail0) {
-            base = b;
-            take = tail0 - b < (unsigned long long)want ? tail0 - b : (unsigned long long)want;
-            initial_left = b + take < tail0;
-            return;
-        }
-    }
-    unsigned long long h = __hip_atomic_load(&cnt->head1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        unsigned long long t =
-            __hip_atomic_load(&cnt->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (t > cap)
-            t = cap;
-        if (h >= t)
-            return;
-        unsigned long long n = t - h;
-        if (n > (unsigned long long)want)
-            n = (unsigned long long)want;
-        if (__hip_atomic_compare_exchange_strong(&cnt->head1, &h, h + n, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            base = h;
-            take = n;
-            return;
-        }
-        __builtin_amdgcn_s_sleep(2);   // back off: another wave won the cursor
+    left = false;
+    if (b < tail0) {
+        take = tail0 - b < (unsigned long long)want ? tail0 - b : (unsigned long long)want;
+        left = b + take < tail0;
     }
 }
 
-__device__ inline bool appended_available(DevCounters* cnt, unsigned long long cap)
+// True once every candidate of this run is finished or parked: then none is
+// active, so no secondary can be appended any more.  The done counts are read
+// (acquire) before the append cursor; all three only grow and done never
+// exceeds the written slots, so equality means that at the last read every
+// written slot was done.  Slots past the queue capacity are never written.
+__device__ inline bool run_drained(DevCounters* cnt, unsigned long long fin0,
+                                   unsigned long long cap)
 {
-    unsigned long long h = __hip_atomic_load(&cnt->head1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long f =
+        __hip_atomic_load(&cnt->fin_n, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long p =
+        __hip_atomic_load(&cnt->park_n, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long t = __hip_atomic_load(&cnt->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (t > cap)
         t = cap;
-    return h < t;
+    return (f - fin0) + p == t;
 }
 
-// Waits until a slot appended during this run is published.  The producer
-// writes the slot and publishes it in the same straight-line code right after
-// reserving it, so the wait is short; it is bounded all the same.
-__device__ inline bool wait_published(uint32_t* flag, DevCounters* cnt)
-{
-    for (uint32_t spin = 0; spin < (1u << 26); ++spin) {
-        if (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-            *flag = 0u;   // clean for the next run
-            return true;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    atomicAdd(&cnt->error, 1ull);
-    return false;
-}
+// Bound on the sleeps of a wave with nothing to do before the run drains
+// (2^23 sleeps of ~3.4 us, about 28 s): a wave that reaches it records an
+// error and leaves.
+constexpr uint32_t IDLE_SLEEP_LIMIT = 1u << 23;
 
 // Per-lane candidate state that is not needed inside a Cash-Karp attempt,
 // kept in LDS (structure of arrays over the block's lanes) so that only the
@@ -279,71 +250,99 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     using BT = typename DirType<MODE>::T;
     BT b1[3] = {0, 0, 0};
     bool reuse = false;
-    bool dry = false, initial_left = true;
-    uint32_t iter = 0;
+    // cooperative layout: the field at the position an accepted attempt moved
+    // to is fetched while the rest of its cycle runs, for the next attempt
+    bool pref = false;
+    bool initial_left = true;
+    // this wave's reservation of appended slots [rb, re): taken with one
+    // atomicAdd, handed to idle lanes as their producers publish them
+    unsigned long long rb = 0, re = 0;
+    uint32_t iter = 0, sleeps = 0;
+    const unsigned long long fin0 = PP->fin0;
 
     for (;;) {
         // ---- refill idle lanes from the queue -------------------------------
         const uint64_t idle = __ballot(!active);
         const int nidle = __popcll(idle);
-        // claims from the region appended during the run go through a
-        // compare-and-swap on one cursor; they wait for at least APPEND_REFILL
-        // idle lanes, so that few waves contend for that cursor at a time (the
-        // neural-field stepper's iterations are long enough not to contend)
-        const int need = LAYOUT == 3 || initial_left || refill >= APPEND_REFILL
-                             ? refill
-                             : APPEND_REFILL;
-        if (dry && nidle >= need && (iter & 63u) == 0u && idle != ~0ull) {
-            bool avail = false;
-            if (lane == 0)
-                avail = appended_available(cnt, qcap);
-            if (__shfl((int)avail, 0))
-                dry = false;
-        }
-        if (idle == ~0ull || (!dry && nidle >= need)) {
+        if (idle == ~0ull || nidle >= refill) {
+            const int rank = lanes_below(idle);
             unsigned long long base = 0, take = 0;
-            bool left = false;
-            if (lane == 0)
-                claim_slots(cnt, tail0, qcap, nidle, initial_left, base, take, left);
-            base = __shfl(base, 0);
-            take = __shfl(take, 0);
-            initial_left = __shfl((int)left, 0) != 0;
-            dry = take < (unsigned long long)nidle;
-            if (!active) {
-                const int rank = lanes_below(idle);
-                if ((unsigned long long)rank < take) {
-                    const unsigned long long sl = base + (unsigned long long)rank;
-                    bool ok = true;
-                    if (sl >= tail0)
-                        ok = wait_published(opaque(PP)->q.ready + sl, cnt);
-                    if (ok) {
-                        const QueueSoA& q = opaque(PP)->q;
-                        slot = (int64_t)sl;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            x[a] = q.x[a * q.cap + slot];
-                            u[a] = (UT)q.u[a * q.cap + slot];
-                        }
-                        S.E[t] = q.E[slot];
-                        S.L[t] = q.L[slot];
-                        S.Lmax[t] = q.Lmax[slot];
-                        S.hctrl[t] = q.hctrl[slot];
-                        S.tau[t] = q.tau[slot];
-                        S.id[t] = q.id[slot];
-                        S.lineage[t] = q.lineage[slot];
-                        S.m[t] = q.m[slot];
-                        S.nsteps[t] = q.nsteps[slot];
-                        S.nrej[t] = q.nrej[slot];
-                        S.cycles[t] = 0u;
-                        S.azf[t] = pack_azf(q.A[slot], q.Z[slot], LIM_CTRL);
-                        active = true;
-                        fresh = true;
-                        reuse = false;
-                    }
+            if (initial_left) {
+                bool left = false;
+                if (lane == 0)
+                    claim_initial(cnt, tail0, nidle, base, take, left);
+                base = __shfl(base, 0);
+                take = __shfl(take, 0);
+                initial_left = __shfl((int)left, 0) != 0;
+            } else {
+                if (rb >= re) {
+                    unsigned long long b = 0;
+                    if (lane == 0)
+                        b = atomicAdd(&cnt->head1, (unsigned long long)nidle);
+                    rb = __shfl(b, 0);
+                    re = rb + (unsigned long long)nidle;
                 }
+                // idle lane of rank r looks at slot rb + r; the published
+                // prefix of the reservation is handed out in order
+                const unsigned long long sl = rb + (unsigned long long)rank;
+                const bool mine = !active && sl < re;
+                bool pub = false;
+                if (mine && sl < qcap)
+                    pub = __hip_atomic_load(opaque(PP)->q.ready + sl, __ATOMIC_ACQUIRE,
+                                            __HIP_MEMORY_SCOPE_AGENT) != 0u;
+                const uint64_t gap = __ballot(mine && !pub);
+                if (gap)
+                    take = (unsigned long long)__popcll(idle & ((1ull << __builtin_ctzll(gap)) - 1ull));
+                else
+                    take = re - rb < (unsigned long long)nidle ? re - rb : (unsigned long long)nidle;
+                base = rb;
+                rb += take;
             }
-            if (__ballot(active) == 0ull)
+            if (!active && (unsigned long long)rank < take) {
+                const QueueSoA& q = opaque(PP)->q;
+                slot = (int64_t)(base + (unsigned long long)rank);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    x[a] = q.x[a * q.cap + slot];
+                    u[a] = (UT)q.u[a * q.cap + slot];
+                }
+                S.E[t] = q.E[slot];
+                S.L[t] = q.L[slot];
+                S.Lmax[t] = q.Lmax[slot];
+                S.hctrl[t] = q.hctrl[slot];
+                S.tau[t] = q.tau[slot];
+                S.id[t] = q.id[slot];
+                S.lineage[t] = q.lineage[slot];
+                S.m[t] = q.m[slot];
+                S.nsteps[t] = q.nsteps[slot];
+                S.nrej[t] = q.nrej[slot];
+                S.cycles[t] = 0u;
+                S.azf[t] = pack_azf(q.A[slot], q.Z[slot], LIM_CTRL);
+                if ((unsigned long long)slot >= tail0)
+                    q.ready[slot] = 0u;   // clean for the next run
+                active = true;
+                fresh = true;
+                reuse = false;
+                pref = false;
+            }
+        }
+        if (__ballot(active) == 0ull) {
+            // nothing to do: leave once the run has drained, else wait for
+            // secondaries that busy waves may still append
+            if (!initial_left) {
+                bool drained = false;
+                if (lane == 0)
+                    drained = run_drained(cnt, fin0, qcap);
+                if (__shfl((int)drained, 0))
+                    break;
+            }
+            if (++sleeps >= IDLE_SLEEP_LIMIT) {
+                if (lane == 0)
+                    atomicAdd(&cnt->error, 1ull);
                 break;
+            }
+            __builtin_amdgcn_s_sleep(127);
+            continue;
         }
         ++iter;
 
@@ -388,6 +387,24 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             fresh = false;
         }
 
+        // ---- the first-stage field of this position may already be on its way
+        if constexpr (LAYOUT == 2) {
+            if (__ballot(pref) != 0ull) {
+                BT bp[3];
+                if constexpr (MODE == MODE_FP64)
+                    F.fp64_prefetched(x, bp);
+                else
+                    F.fp32_prefetched(x, bp);
+                if (pref) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        b1[q] = bp[q];
+                    reuse = true;
+                }
+                pref = false;
+            }
+        }
+
         // ---- one Cash-Karp attempt -------------------------------------------
         uint32_t ev = 0u;
         int status = ST_ACTIVE;
@@ -415,6 +432,14 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                 else
                     err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5, active, reuse, b1);
             }
+        }
+        if constexpr (LAYOUT == 2) {
+            // accepted lanes move to x5: start fetching B(x5) now, so that the
+            // loads overlap the rest of the cycle
+            const bool acc = active && (err / sp.tol <= 1.0 || h <= sp.hmin);
+            if (__ballot(acc) != 0ull)
+                F.prefetch(x5, acc);
+            pref = acc;
         }
         if (active) {
             ev |= EV_ATTEMPT;

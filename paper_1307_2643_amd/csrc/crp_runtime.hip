@@ -331,6 +331,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.sp.renorm = c.renormalize;
     P.max_cycles = max_cycles;
     P.tail0 = (unsigned long long)ctx->pending;
+    P.fin0 = init.fin_n;
     // the neural-field stepper costs the same per wave however many lanes are
     // busy, so it refills a lane as soon as it is idle
     P.refill = c.field_mode == CRP_FIELD_NEURAL ? 1 : ctx->launch.refill;
@@ -406,7 +407,8 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     ctx->last_ms = ms;
     ctx->last_launches = 1;
     if (dc->error)
-        return fail(ctx, CRP_EDEVICE, "propagation kernel: a queue publication wait timed out");
+        return fail(ctx, CRP_EDEVICE,
+                    "propagation kernel: a wave waited too long for the run to drain");
     return CRP_OK;
 }
 
