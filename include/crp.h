@@ -81,9 +81,7 @@ typedef struct {
                                  as many as the kernel's occupancy lets one
                                  compute unit hold at once */
     int32_t refill;           /* a wave claims new candidates once this many of its
-                                 64 lanes are idle (1..64); secondaries appended
-                                 during the run are claimed once at least
-                                 max(refill, 32) lanes are idle */
+                                 64 lanes are idle (1..64) */
     int32_t layout;           /* CRP_LAYOUT_LINEAR or CRP_LAYOUT_CORNER */
 } crp_launch;
 
@@ -193,7 +191,7 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* 
                           int32_t mode, int32_t on_device);
 
 /* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
- * A new context starts with {128, 0, 32, CRP_LAYOUT_LINEAR}.
+ * A new context starts with {128, 0, 4, CRP_LAYOUT_LINEAR}.
  * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra
  * device memory (built on first use). */
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);

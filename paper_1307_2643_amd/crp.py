@@ -334,7 +334,7 @@ class Context:
         return out
 
     # -- launch shape / tuning / timing ---------------------------------------
-    def set_launch(self, block=128, blocks_per_cu=0, refill=32, layout=LAYOUT_LINEAR):
+    def set_launch(self, block=128, blocks_per_cu=0, refill=4, layout=LAYOUT_LINEAR):
         lch = Launch(block, blocks_per_cu, refill, layout)
         self._check(self.L.crp_set_launch(self.h, C.byref(lch)))
 

@@ -122,9 +122,11 @@ __device__ inline bool run_drained(DevCounters* cnt, unsigned long long fin0,
     return (f - fin0) + p == t;
 }
 
-// Bound on the sleeps of a wave with nothing to do before the run drains
-// (2^23 sleeps of ~3.4 us, about 28 s): a wave that reaches it records an
-// error and leaves.
+// A wave with nothing to do sleeps in units of s_sleep 127 (~3.4 us), one
+// unit more per idle iteration up to IDLE_BACKOFF (its polls of the queue
+// must not load the memory system that busy waves use); after IDLE_SLEEP_LIMIT
+// units (about 28 s) without the run draining it records an error and leaves.
+constexpr uint32_t IDLE_BACKOFF = 16u;
 constexpr uint32_t IDLE_SLEEP_LIMIT = 1u << 23;
 
 // Per-lane candidate state that is not needed inside a Cash-Karp attempt,
@@ -176,11 +178,12 @@ struct DirType<MODE_MIX> {
 };
 
 // Minimum waves per SIMD the register allocation targets (occupancy vs
-// spills), per precision form.  Measured on the 1e7 batch, 1024^3 grid:
-// the precision form is fastest at 3 (12 waves per CU, a few rare-path
-// spills), the FP64 form at 2 (at 3 it spills in the attempt itself).
+// spills), per precision form.  Measured on the 1e7 batch, 1024^3 grid: both
+// forms are fastest at 2 (8 waves per CU, no spills); at 3 the precision form
+// spills (1.36 s vs 1.30 s per batch) and the FP64 form spills inside the
+// attempt.
 #ifndef CRP_WAVES_MIX
-#define CRP_WAVES_MIX 3
+#define CRP_WAVES_MIX 2
 #endif
 #ifndef CRP_WAVES_FP64
 #define CRP_WAVES_FP64 2
@@ -257,7 +260,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     // this wave's reservation of appended slots [rb, re): taken with one
     // atomicAdd, handed to idle lanes as their producers publish them
     unsigned long long rb = 0, re = 0;
-    uint32_t iter = 0, sleeps = 0;
+    uint32_t iter = 0, sleeps = 0, backoff = 0;
     const unsigned long long fin0 = PP->fin0;
 
     for (;;) {
@@ -336,14 +339,19 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                 if (__shfl((int)drained, 0))
                     break;
             }
-            if (++sleeps >= IDLE_SLEEP_LIMIT) {
+            if (backoff < IDLE_BACKOFF)
+                ++backoff;
+            for (uint32_t k = 0; k < backoff; ++k)
+                __builtin_amdgcn_s_sleep(127);
+            sleeps += backoff;
+            if (sleeps >= IDLE_SLEEP_LIMIT) {
                 if (lane == 0)
                     atomicAdd(&cnt->error, 1ull);
                 break;
             }
-            __builtin_amdgcn_s_sleep(127);
             continue;
         }
+        backoff = 0;
         ++iter;
 
         // ---- start of a cycle: rates and step proposal -----------------------

@@ -472,7 +472,7 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     std::memset(&ctx->totals, 0, sizeof ctx->totals);
     ctx->launch.block = 128;
     ctx->launch.blocks_per_cu = 0;
-    ctx->launch.refill = 32;
+    ctx->launch.refill = 4;
     ctx->launch.layout = CRP_LAYOUT_LINEAR;
     auto bail = [&](crp_status st, const char* what, hipError_t e) {
         fprintf(stderr, "crp_create: %s: %s\n", what, hipGetErrorString(e));
@@ -1074,9 +1074,9 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     std::vector<crp_launch> cands;
     const bool corner_ok = ctx->grid_dtype == CRP_F32;
     for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
-        for (const crp_launch& l : {crp_launch{128, 0, 32, 0}, crp_launch{128, 0, 16, 0},
-                                    crp_launch{128, 4, 32, 0}, crp_launch{128, 5, 32, 0},
-                                    crp_launch{256, 0, 32, 0}})
+        for (const crp_launch& l : {crp_launch{128, 0, 4, 0}, crp_launch{128, 0, 16, 0},
+                                    crp_launch{128, 3, 4, 0}, crp_launch{256, 0, 4, 0},
+                                    crp_launch{256, 0, 16, 0}})
             cands.push_back(crp_launch{l.block, l.blocks_per_cu, l.refill, layout});
     crp_launch bestl = orig;
     double bestr = -1.0;
