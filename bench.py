@@ -382,7 +382,10 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
         ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
                    lmax=d[6][s], on_device=True)
 
-    inject(batches[0], 6_000_000)
+    # calibration: 1e6 candidates of the first batch run to completion (the
+    # distance workload's trajectories are up to 10x the mixed batch's)
+    log("[bench] batching: inputs on the device; tuning on 1e6 candidates")
+    inject(batches[0], 1_000_000)
     tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
     ctx.discard_finished()
     while not ctx.propagate(0):
