@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
     ap.add_argument("--nf-steps", type=int, default=1526,
                     help="training steps of 65536 points (1526 steps = 1e8 points)")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper-shaped context run (protons, 1 Gpc, 256^3 grid)")
+    ap.add_argument("--paper-n", type=int, default=1_000_000)
     ap.add_argument("--nf-only", action="store_true",
                     help="diagnostic: only the neural-field variant (training, field error, "
                          "surrogate vs grid); prints that variant's JSON")
@@ -305,6 +308,10 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.3e} steps/s on {used} threads")
         del host_grid
 
+    # ---- the paper's own benchmark shape, for context ------------------------
+    if not args.no_paper:
+        variants["paper_comparable"] = paper_comparable(args, crp, I, torch, stream)
+
     # ---- batching form: a stream of 1e7-candidate batches -------------------
     if args.batching:
         variants["batching"] = batching_variant(args, crp, I, torch, grid, tables, stream)
@@ -352,6 +359,62 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def paper_comparable(args, crp, I, torch, stream):
+    """The shape of the paper's 3D benchmark (section 6: protons, log-flat
+    1-1000 EeV, 1 Gpc, losses off; here the 256^3 FP64 grid and the FP64
+    method): GPU trajectories per second, and the oracle's single-core time
+    per trajectory beside the paper's 1.0 ms (Intel i5-3317U, 1.7 GHz)."""
+    w = I.W_PAPER256
+    n = args.paper_n
+    grid = w.make_grid()
+    tables = w.make_tables()
+    inj = w.make_injection(n)
+    dev = torch.device("cuda:0")
+    d = [torch.as_tensor(a, device=dev) for a in
+         (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+    prm = crp.params_for(w, crp.FP64, device=0, queue_capacity=2 * n, neutral_capacity=1 << 16)
+    ctx = crp.Context(prm, stream)
+    ctx.set_field_grid(grid, w.spacing_m)
+    ctx.set_tables(tables)
+
+    def run():
+        ctx.reset_counters()
+        ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
+                   on_device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate(0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        c = ctx.counts()
+        ctx.discard_finished()
+        return wall, c
+
+    run()                                        # untimed first run
+    wall, c = run()
+    ctx.close()
+    out = {"workload": f"{w.name} ({n} protons, FP64 method)", "gpu_trajectories_per_s": n / wall,
+           "gpu_us_per_trajectory": 1e6 * wall / n, "gpu_steps_per_s": c["steps"] / wall,
+           "steps_per_trajectory": c["steps"] / n,
+           "paper_ms_per_trajectory": 1.0,
+           "paper_hardware": "Intel Core i5-3317U @ 1.7 GHz, Python steering (section 6)"}
+    log(f"[bench] paper-shaped 3D workload: GPU {n / wall:.3e} trajectories/s "
+        f"({1e6 * wall / n:.3f} us each, {c['steps'] / n:.0f} steps per trajectory)")
+    if not args.no_cpu:
+        from oracle import oracle as O
+        G = O.GridRef(grid, w.spacing_m)
+        T = O.TablesRef(tables)
+        m = 200
+        t0 = time.perf_counter()
+        _, _, co, used = O.propagate(O.config_for(w), G, T, inj.subset(slice(0, m)), nthreads=1)
+        t1 = time.perf_counter() - t0
+        out["oracle_ms_per_trajectory_one_core"] = 1e3 * t1 / m
+        out["oracle_sample"] = f"first {m} trajectories, {co['steps']} steps, 1 thread"
+        log(f"[bench] oracle on one host core: {1e3 * t1 / m:.2f} ms per trajectory "
+            f"(paper: 1.0 ms on an i5-3317U)")
+    return out
 
 
 def batching_variant(args, crp, I, torch, grid, tables, stream):

@@ -286,6 +286,8 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
     def make_tables(self):
+        if self.tables == "none":
+            return tables_constant()
         return tables_full() if self.tables == "full" else tables_loss_only()
 
     def make_injection(self, n=None, id0=0):
@@ -322,7 +324,13 @@ W_DIST1024 = Workload("dist1e7_grid1024_fp32", 1024, 10 * KPC_M, (2.0, 16.0), 3,
                       "full", "distances", 10_000_000, 404, 1000 * MPC_M,
                       observer=(0.0, 0.0, 0.0), obs_radius_m=1 * MPC_M, philox_seed=4)
 
-WORKLOADS = {w.name: w for w in (W_SMALL, W_MIXED256, W_MIXED1024, W_DIST1024)}
+# The shape of the paper's 3D benchmark (section 6): protons with a log-flat
+# spectrum over 1-1000 EeV, 1 Gpc trajectories, energy losses off, here on the
+# 256^3 FP64 turbulent grid (1 nG RMS).
+W_PAPER256 = Workload("p_logflat_1gpc_grid256_fp64", 256, 50 * KPC_M, (16.0, 128.0), 2,
+                      np.float64, "none", "logflat", 1_000_000, 606, 1000 * MPC_M, philox_seed=6)
+
+WORKLOADS = {w.name: w for w in (W_SMALL, W_MIXED256, W_MIXED1024, W_DIST1024, W_PAPER256)}
 
 
 # --------------------------------------------------------------------------
