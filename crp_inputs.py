@@ -261,6 +261,36 @@ def inject_protons_logflat(n, seed, e1=1e18, e2=1e21, lmax_m=1000 * MPC_M, id0=0
 
 
 # --------------------------------------------------------------------------
+# Galactic propagation (section 4): a synthetic analytic field and observed
+# events to backtrack.
+# --------------------------------------------------------------------------
+MICROGAUSS_T = 1e-10
+EARTH_KPC = (-8.5, 0.0, 0.02)          # galactocentric position of the observer
+
+# Disk / halo / X-field model of the JF12 structure with rational profiles
+# (the JF12 fit parameters are not available); galactocentric, axis z.
+GALACTIC_FIELD = {
+    "center": (0.0, 0.0, 0.0),
+    "b_disk": 6.0 * MICROGAUSS_T, "r_disk": 5.0 * KPC_M, "h_disk": 0.4 * KPC_M,
+    "b_halo": 4.0 * MICROGAUSS_T, "r_halo": 6.0 * KPC_M, "h_halo": 2.0 * KPC_M,
+    "b_x": 1.5 * MICROGAUSS_T, "r_x": 4.0 * KPC_M, "h_x": 3.0 * KPC_M,
+}
+
+
+def inject_galactic(n, seed, e1=1e18, e2=1e20, lmax_m=100 * KPC_M, id0=0):
+    """Events observed at Earth, to be backtracked: H/He/N/Fe (id mod 4),
+    log-flat energies on [e1, e2], isotropic directions (the reversed arrival
+    directions), all starting at the observer's position."""
+    rng = np.random.default_rng(seed)
+    ids = np.arange(id0, id0 + n, dtype=np.uint32)
+    az = np.array(SPECIES_AZ, dtype=np.int32)[ids % 4]
+    e = 10.0 ** (np.log10(e1) + rng.random(n) * (np.log10(e2) - np.log10(e1)))
+    pos = np.tile(np.array(EARTH_KPC) * KPC_M, (n, 1))
+    d = isotropic(rng, n)
+    return Injection(ids, az[:, 0].copy(), az[:, 1].copy(), e, pos, d, np.full(n, lmax_m))
+
+
+# --------------------------------------------------------------------------
 # Workload descriptions.
 # --------------------------------------------------------------------------
 @dataclass
@@ -284,6 +314,10 @@ class Workload:
     hmax_m: float = 1 * MPC_M
     brms_T: float = 1 * NG_T
     extra: dict = field(default_factory=dict)
+    charge_sign: int = 1                  # -1: backtracking (antiparticle)
+    boundary_center: tuple = (0.0, 0.0, 0.0)
+    boundary_radius_m: float = 0.0        # spherical boundary (0: none)
+    field: str = "grid"                   # 'grid' | 'analytic'
 
     def make_tables(self):
         if self.tables == "none":
@@ -300,6 +334,8 @@ class Workload:
             return inject_distances(n, self.inject_seed, id0=id0)
         if self.inject == "logflat":
             return inject_protons_logflat(n, self.inject_seed, lmax_m=self.lmax_m, id0=id0)
+        if self.inject == "galactic":
+            return inject_galactic(n, self.inject_seed, lmax_m=self.lmax_m, id0=id0)
         raise ValueError(self.inject)
 
     def make_grid(self, device=None):
@@ -330,7 +366,15 @@ W_DIST1024 = Workload("dist1e7_grid1024_fp32", 1024, 10 * KPC_M, (2.0, 16.0), 3,
 W_PAPER256 = Workload("p_logflat_1gpc_grid256_fp64", 256, 50 * KPC_M, (16.0, 128.0), 2,
                       np.float64, "none", "logflat", 1_000_000, 606, 1000 * MPC_M, philox_seed=6)
 
-WORKLOADS = {w.name: w for w in (W_SMALL, W_MIXED256, W_MIXED1024, W_DIST1024, W_PAPER256)}
+# Galactic backtracking: observed events at Earth traced back (charge -Z,
+# reversed direction) through the analytic field to a 20 kpc sphere.
+W_GALBACK = Workload("galback1e6_analytic", 1, 1.0, (0.0, 0.0), 0, np.float64, "none",
+                     "galactic", 1_000_000, 707, 100 * KPC_M, philox_seed=7,
+                     hmin_m=1e-3 * KPC_M, hmax_m=1.0 * KPC_M, charge_sign=-1,
+                     boundary_radius_m=20.0 * KPC_M, field="analytic")
+
+WORKLOADS = {w.name: w for w in (W_SMALL, W_MIXED256, W_MIXED1024, W_DIST1024, W_PAPER256,
+                                 W_GALBACK)}
 
 
 # --------------------------------------------------------------------------

@@ -84,8 +84,37 @@ static void axis_cell(const or_grid* g, int a, double p, int64_t idx[2], double*
     *t = f - fl;
 }
 
+/* Analytic galactic field (model in crp_oracle.h), FP64 in the order written:
+ * derived constants first, then the toroidal factor g with B_t = g (-y, x, 0),
+ * then the X-field B_x = x q, B_y = y q, B_z = b_x / D - b_x r^2 / (r_x^2 D^2)
+ * with q = b_x z / (h_x^2 D^2). */
+static void field_analytic(const or_analytic* a, const double p[3], double B[3])
+{
+    double kd = 1.0 / (a->r_disk * a->r_disk), ld = 1.0 / (a->h_disk * a->h_disk);
+    double kh = 1.0 / (a->r_halo * a->r_halo), lh = 1.0 / (a->h_halo * a->h_halo);
+    double ih = 1.0 / a->h_halo;
+    double kx = 1.0 / (a->r_x * a->r_x), lx = 1.0 / (a->h_x * a->h_x);
+    double dx = p[0] - a->center[0], dy = p[1] - a->center[1], dz = p[2] - a->center[2];
+    double r2 = dx * dx + dy * dy;
+    double z2 = dz * dz;
+    double gd = a->b_disk / ((a->r_disk * (1.0 + r2 * kd)) * (1.0 + z2 * ld));
+    double wh = 1.0 + z2 * lh;
+    double gh = (a->b_halo * (dz * ih)) / ((a->r_halo * (1.0 + r2 * kh)) * (wh * wh));
+    double g = gd + gh;
+    double D = (1.0 + r2 * kx) + z2 * lx;
+    double D2 = D * D;
+    double q = (a->b_x * (dz * lx)) / D2;
+    B[0] = (-g) * dy + dx * q;
+    B[1] = g * dx + dy * q;
+    B[2] = a->b_x / D - (a->b_x * (r2 * kx)) / D2;
+}
+
 static void field_fp64(const or_grid* g, const double p[3], double B[3])
 {
+    if (g->analytic) {
+        field_analytic(g->analytic, p, B);
+        return;
+    }
     int64_t idx[3][2];
     double w[3][2];
     for (int a = 0; a < 3; ++a) {
@@ -110,6 +139,13 @@ static void field_fp64(const or_grid* g, const double p[3], double B[3])
 /* Precision form: offsets in FP64, weights and accumulation in FP32. */
 static void field_mix(const or_grid* g, const double p[3], float B[3])
 {
+    if (g->analytic) {      /* the analytic field in FP64, rounded once */
+        double b[3];
+        field_analytic(g->analytic, p, b);
+        for (int c = 0; c < 3; ++c)
+            B[c] = (float)b[c];
+        return;
+    }
     int64_t idx[3][2];
     float w[3][2];
     for (int a = 0; a < 3; ++a) {
@@ -455,6 +491,15 @@ static double dist_obs(const or_config* cfg, const double x[3])
     return sqrt(dot_d(d, d));
 }
 
+/* Distance from the boundary centre (the spherical boundary module ends a
+ * candidate once it is at or beyond the radius after a cycle). */
+static double dist_bnd(const or_config* cfg, const double x[3])
+{
+    double d[3] = {x[0] - cfg->bnd_center[0], x[1] - cfg->bnd_center[1],
+                   x[2] - cfg->bnd_center[2]};
+    return sqrt(dot_d(d, d));
+}
+
 static void emit_finished(or_finished* fin, int64_t* n_fin, const cand_t* c, or_counts* cnt)
 {
     int64_t k;
@@ -545,7 +590,8 @@ static void run_candidate(const or_config* cfg, const or_grid* g, const or_table
         }
 
         /* integration module: adaptive Cash-Karp with retries */
-        double kappa = ((double)c->Z * C_LIGHT) / c->E;
+        /* backtracking follows the antiparticle: charge -Z */
+        double kappa = ((double)(cfg->charge_sign * c->Z) * C_LIGHT) / c->E;
         double x5[3], u5[3], r;
         for (;;) {
             double err;
@@ -688,6 +734,8 @@ static void run_candidate(const or_config* cfg, const or_grid* g, const or_table
         c->cycles++;
         if (cfg->obs_r > 0.0 && dist_obs(cfg, c->x) <= cfg->obs_r)
             c->status = OR_OBSERVED;
+        else if (cfg->bnd_r > 0.0 && dist_bnd(cfg, c->x) >= cfg->bnd_r)
+            c->status = OR_BOUNDARY;
         else if (flag == LIM_TRAJ || c->L >= c->Lmax)
             c->status = OR_MAX_TRAJ;
         else if (c->E < cfg->e_floor)
@@ -700,6 +748,10 @@ static void run_candidate(const or_config* cfg, const or_grid* g, const or_table
         break;
     case OR_MAX_TRAJ:
         cnt->max_traj++;
+        cnt->finished++;
+        break;
+    case OR_BOUNDARY:
+        cnt->boundary++;
         cnt->finished++;
         break;
     case OR_ENERGY_FLOOR:

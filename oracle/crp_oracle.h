@@ -22,7 +22,7 @@ extern "C" {
 
 enum { OR_FP64 = 0, OR_MIX = 1 };
 enum { OR_GRID_F32 = 0, OR_GRID_F64 = 1 };
-enum { OR_ACTIVE = 0, OR_OBSERVED = 1, OR_MAX_TRAJ = 2, OR_ENERGY_FLOOR = 3 };
+enum { OR_ACTIVE = 0, OR_OBSERVED = 1, OR_MAX_TRAJ = 2, OR_ENERGY_FLOOR = 3, OR_BOUNDARY = 4 };
 enum { OR_CHAN_PI = 0, OR_CHAN_N = 1 };
 
 typedef struct {
@@ -37,7 +37,27 @@ typedef struct {
     double obs_r;           /* observer radius, m (0: no observer) */
     uint64_t seed;          /* Philox key word 0 */
     int64_t max_cycles;     /* per-candidate cycle cap (<= 0: none) */
+    int32_t charge_sign;    /* +1 forward tracking, -1 backtracking (charge -Z) */
+    int32_t pad_;
+    double bnd_center[3];   /* spherical boundary centre, m */
+    double bnd_r;           /* boundary radius, m (0: none); leaving it ends a candidate */
 } or_config;
+
+/* Synthetic analytic galactic field (section 4, galactic propagation: the
+ * code offers analytic field models; the JF12 parameters are not available,
+ * so this is a disk/halo/X-field model of the same structure with rational
+ * profiles).  Cylindrical coordinates about `center`, axis z:
+ *   disk toroidal  B_phi = b_disk (r/r_disk) / ((1 + r^2/r_disk^2)(1 + z^2/h_disk^2))
+ *   halo toroidal  B_phi = b_halo (z/h_halo)(r/r_halo) / ((1 + r^2/r_halo^2)(1 + z^2/h_halo^2)^2)
+ *   X-field        B = curl(A_phi e_phi), A_phi = b_x r / (2 D),
+ *                  D = 1 + r^2/r_x^2 + z^2/h_x^2.
+ * Every part is divergence-free. */
+typedef struct {
+    double center[3];
+    double b_disk, r_disk, h_disk;
+    double b_halo, r_halo, h_halo;
+    double b_x, r_x, h_x;
+} or_analytic;
 
 typedef struct {
     const void* data;       /* [nx][ny][nz][3] tesla, C order */
@@ -46,6 +66,7 @@ typedef struct {
     int64_t n[3];
     double spacing;         /* m */
     double origin[3];       /* m */
+    const or_analytic* analytic;   /* non-NULL: this analytic field instead of the grid */
 } or_grid;
 
 typedef struct {
@@ -77,6 +98,7 @@ typedef struct {
     int64_t events, null_events, inter_pi, inter_n;
     int64_t charged_sec, neutral_sec;
     int64_t fin_dropped, neu_dropped;
+    int64_t boundary;
 } or_counts;
 
 /* Propagate n injected candidates to completion (or max_cycles). Returns the

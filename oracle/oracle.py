@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "crp_oracle.c")
 
 FP64, MIX = 0, 1
 GRID_F32, GRID_F64 = 0, 1
-ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR = 0, 1, 2, 3
+ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR, BOUNDARY = 0, 1, 2, 3, 4
 CHAN_PI, CHAN_N = 0, 1
 
 
@@ -39,12 +39,20 @@ class Config(C.Structure):
     _fields_ = [("precision", C.c_int32), ("renormalize", C.c_int32), ("tol", C.c_double),
                 ("hmin", C.c_double), ("hmax", C.c_double), ("eps_loss", C.c_double),
                 ("kappa_pi", C.c_double), ("e_floor", C.c_double), ("obs", C.c_double * 3),
-                ("obs_r", C.c_double), ("seed", C.c_uint64), ("max_cycles", C.c_int64)]
+                ("obs_r", C.c_double), ("seed", C.c_uint64), ("max_cycles", C.c_int64),
+                ("charge_sign", C.c_int32), ("pad_", C.c_int32), ("bnd_center", C.c_double * 3),
+                ("bnd_r", C.c_double)]
+
+
+class Analytic(C.Structure):
+    _fields_ = [("center", C.c_double * 3)] + [(k, C.c_double) for k in (
+        "b_disk", "r_disk", "h_disk", "b_halo", "r_halo", "h_halo", "b_x", "r_x", "h_x")]
 
 
 class Grid(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("pad_", C.c_int32),
-                ("n", C.c_int64 * 3), ("spacing", C.c_double), ("origin", C.c_double * 3)]
+                ("n", C.c_int64 * 3), ("spacing", C.c_double), ("origin", C.c_double * 3),
+                ("analytic", _P(Analytic))]
 
 
 class Tables(C.Structure):
@@ -67,7 +75,8 @@ class Neutral(C.Structure):
 
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "still_active", "steps",
                 "attempts", "rejects", "forced", "events", "null_events", "inter_pi",
-                "inter_n", "charged_sec", "neutral_sec", "fin_dropped", "neu_dropped")
+                "inter_n", "charged_sec", "neutral_sec", "fin_dropped", "neu_dropped",
+                "boundary")
 
 
 class Counts(C.Structure):
@@ -128,6 +137,25 @@ class GridRef:
         self.s.spacing = float(spacing)
 
 
+class AnalyticRef:
+    """The analytic galactic field as a field source (no grid array)."""
+
+    def __init__(self, model):
+        self.a = Analytic()
+        for a in range(3):
+            self.a.center[a] = float(model["center"][a])
+        for k in ("b_disk", "r_disk", "h_disk", "b_halo", "r_halo", "h_halo", "b_x", "r_x",
+                  "h_x"):
+            setattr(self.a, k, float(model[k]))
+        self.s = Grid()
+        self.s.data = None
+        self.s.dtype = GRID_F64
+        for a in range(3):
+            self.s.n[a] = 1
+        self.s.spacing = 1.0
+        self.s.analytic = C.pointer(self.a)
+
+
 class TablesRef:
     def __init__(self, t):
         self.arrs = [np.ascontiguousarray(np.asarray(a, np.float64))
@@ -140,7 +168,7 @@ class TablesRef:
 
 def make_config(precision=FP64, tol=1e-4, hmin=None, hmax=None, eps_loss=0.1, kappa_pi=0.2,
                 e_floor=1e16, observer=(0.0, 0.0, 0.0), obs_r=0.0, seed=1, renormalize=1,
-                max_cycles=0):
+                max_cycles=0, charge_sign=1, bnd_center=(0.0, 0.0, 0.0), bnd_r=0.0):
     kpc = 3.0856775814913673e19
     c = Config()
     c.precision = precision
@@ -156,13 +184,18 @@ def make_config(precision=FP64, tol=1e-4, hmin=None, hmax=None, eps_loss=0.1, ka
     c.obs_r = obs_r
     c.seed = seed
     c.max_cycles = max_cycles
+    c.charge_sign = charge_sign
+    for a in range(3):
+        c.bnd_center[a] = bnd_center[a]
+    c.bnd_r = bnd_r
     return c
 
 
 def config_for(workload, precision=FP64, **kw):
     args = dict(precision=precision, tol=workload.tol, hmin=workload.hmin_m,
                 hmax=workload.hmax_m, observer=workload.observer, obs_r=workload.obs_radius_m,
-                seed=workload.philox_seed)
+                seed=workload.philox_seed, charge_sign=workload.charge_sign,
+                bnd_center=workload.boundary_center, bnd_r=workload.boundary_radius_m)
     args.update(kw)
     return make_config(**args)
 
