@@ -63,6 +63,9 @@ def main():
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
     ap.add_argument("--nf-steps", type=int, default=1526,
                     help="training steps of 65536 points (1526 steps = 1e8 points)")
+    ap.add_argument("--no-galactic", action="store_true",
+                    help="skip the galactic backtracking variant (analytic field)")
+    ap.add_argument("--gal-n", type=int, default=10_000_000)
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper-shaped context run (protons, 1 Gpc, 256^3 grid)")
     ap.add_argument("--paper-n", type=int, default=1_000_000)
@@ -308,6 +311,10 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.3e} steps/s on {used} threads")
         del host_grid
 
+    # ---- galactic backtracking through the analytic field --------------------
+    if not args.no_galactic:
+        variants["galactic"] = galactic_variant(args, crp, I, torch, stream)
+
     # ---- the paper's own benchmark shape, for context ------------------------
     if not args.no_paper:
         variants["paper_comparable"] = paper_comparable(args, crp, I, torch, stream)
@@ -359,6 +366,70 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+# FP64 operations of one Cash-Karp attempt of the FP64 method with the analytic
+# field: 6 field evaluations x 44 (3 differences, 3 for r^2, 1 for z^2, 7 disk,
+# 2 + 8 halo, 1, 4 + 1 for D and D^2, 3 for q, 3 + 3 + 5 for B) plus the stages:
+# 6 x 12 derivative, 210 stage sums, 54 fifth-order sum, 34 error estimate.
+ANALYTIC_FLOP_PER_ATTEMPT = 6 * 44 + 6 * 12 + 210 + 54 + 34
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def galactic_variant(args, crp, I, torch, stream):
+    """Galactic backtracking (section 4): observed events at Earth traced back
+    as antiparticles through the analytic disk/halo/X-field model to a 20 kpc
+    sphere; ALU-bound (no field memory)."""
+    w = I.W_GALBACK
+    n = args.gal_n
+    inj = w.make_injection(n)
+    dev = torch.device("cuda:0")
+    d = [torch.as_tensor(a, device=dev) for a in
+         (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+    out = {"workload": f"{w.name} x {n} events (H/He/N/Fe, 1-100 EeV, 20 kpc sphere)"}
+    for name, prec in (("fp64", crp.FP64), ("mix", crp.MIX)):
+        prm = crp.params_for(w, prec, device=0, queue_capacity=2 * n, neutral_capacity=1 << 16)
+        ctx = crp.Context(prm, stream)
+        ctx.set_field_analytic(I.GALACTIC_FIELD)
+        ctx.set_tables(w.make_tables())
+        rate = None
+        for rep in range(2):                     # the first run is untimed
+            ctx.reset_counters()
+            ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
+                       on_device=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.propagate(0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms, _ = ctx.last_timing()
+            c = ctx.counts()
+            ctx.discard_finished()
+        ctx.close()
+        r = {"steps_per_s": c["steps"] / wall, "events_per_s": n / wall, "kernel_ms": ms,
+             "steps": c["steps"], "attempts": c["attempts"], "boundary": c["boundary"],
+             "max_traj": c["max_traj"]}
+        if prec == crp.FP64:
+            achieved = c["attempts"] * ANALYTIC_FLOP_PER_ATTEMPT / (ms * 1e-3) / 1e12
+            r["roofline"] = {"bound": "alu", "flop_per_attempt": ANALYTIC_FLOP_PER_ATTEMPT,
+                             "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS}
+        out[name] = r
+        log(f"[bench] galactic backtracking ({name}): {c['steps'] / wall:.3e} steps/s, "
+            f"{n / wall:.3e} events/s, kernel {ms:.1f} ms")
+    if not args.no_cpu:
+        from oracle import oracle as O
+        m = 20000
+        t0 = time.perf_counter()
+        _, _, co, used = O.propagate(O.config_for(w), O.AnalyticRef(I.GALACTIC_FIELD),
+                                     O.TablesRef(w.make_tables()), inj.subset(slice(0, m)),
+                                     nthreads=len(os.sched_getaffinity(0)))
+        t1 = time.perf_counter() - t0
+        out["oracle"] = {"steps_per_s": co["steps"] / t1, "cores": used,
+                         "sample": f"first {m} events, FP64"}
+        log(f"[bench] galactic backtracking oracle: {co['steps'] / t1:.3e} steps/s on {used} "
+            f"threads")
+    return out
 
 
 def paper_comparable(args, crp, I, torch, stream):

@@ -46,10 +46,11 @@ typedef enum {
 } crp_status;
 
 enum { CRP_FP64 = 0, CRP_MIX = 1 };                     /* stage precision        */
-enum { CRP_FIELD_GRID = 0, CRP_FIELD_NEURAL = 1 };      /* field source           */
+enum { CRP_FIELD_GRID = 0, CRP_FIELD_NEURAL = 1, CRP_FIELD_ANALYTIC = 2 }; /* field source */
 enum { CRP_F32 = 0, CRP_F64 = 1 };                      /* grid element type      */
 enum { CRP_LAYOUT_LINEAR = 0, CRP_LAYOUT_CORNER = 1 };  /* grid layout in HBM     */
-enum { CRP_ACTIVE = 0, CRP_OBSERVED = 1, CRP_MAX_TRAJ = 2, CRP_ENERGY_FLOOR = 3 };
+enum { CRP_ACTIVE = 0, CRP_OBSERVED = 1, CRP_MAX_TRAJ = 2, CRP_ENERGY_FLOOR = 3,
+       CRP_BOUNDARY = 4 };
 enum { CRP_CHAN_PI = 0, CRP_CHAN_N = 1 };
 
 /* Run configuration (copied at crp_create). */
@@ -58,8 +59,9 @@ typedef struct {
                                  increments, field interpolation and direction in
                                  FP32; position, length, step control, energy and
                                  interactions in FP64. */
-    int32_t field_mode;       /* CRP_FIELD_GRID or CRP_FIELD_NEURAL (needs crp_nf_init and
-                                 precision CRP_MIX) */
+    int32_t field_mode;       /* CRP_FIELD_GRID, CRP_FIELD_NEURAL (needs crp_nf_init and
+                                 precision CRP_MIX) or CRP_FIELD_ANALYTIC (needs
+                                 crp_set_field_analytic) */
     int32_t renormalize;      /* 1: |u| renormalised after every accepted step */
     int32_t device;           /* HIP device ordinal */
     double tol;               /* direction error tolerance per step */
@@ -72,7 +74,30 @@ typedef struct {
     uint64_t seed;            /* Philox4x64-10 key word 0 */
     int64_t queue_capacity;   /* max pending + spawned candidates per propagate (> 0) */
     int64_t neutral_capacity; /* max undrained neutral records (> 0) */
+    int32_t charge_sign;      /* +1 (or 0): forward tracking; -1: backtracking, i.e. the
+                                 antiparticle (charge -Z) from the observer along the
+                                 reversed arrival direction (section 4) */
+    int32_t pad_;
+    double boundary_center[3];/* spherical boundary centre, m */
+    double boundary_radius;   /* m; 0 disables it.  A candidate at or beyond the radius
+                                 after a cycle stops with status CRP_BOUNDARY */
 } crp_config;
+
+/* Analytic galactic field (section 4: the code offers analytic field models;
+ * the JF12 fit parameters are not available, so this is a synthetic model of
+ * the same disk / halo / X-field structure with rational profiles).
+ * Cylindrical coordinates about `center`, axis z; tesla and metres:
+ *   disk toroidal  B_phi = b_disk (r/r_disk) / ((1 + r^2/r_disk^2)(1 + z^2/h_disk^2))
+ *   halo toroidal  B_phi = b_halo (z/h_halo)(r/r_halo) / ((1 + r^2/r_halo^2)(1 + z^2/h_halo^2)^2)
+ *   X-field        B = curl(A_phi e_phi), A_phi = b_x r / (2 D),
+ *                  D = 1 + r^2/r_x^2 + z^2/h_x^2
+ * evaluated in FP64 (the precision form rounds the result to FP32). */
+typedef struct {
+    double center[3];
+    double b_disk, r_disk, h_disk;
+    double b_halo, r_halo, h_halo;
+    double b_x, r_x, h_x;
+} crp_analytic_field;
 
 /* Kernel launch shape of the persistent propagation kernel. */
 typedef struct {
@@ -111,6 +136,7 @@ typedef struct {
     int64_t lane_slots;       /* 64 x wave iterations of the propagation kernel:
                                  attempts / lane_slots is the fraction of lanes
                                  that carried a candidate */
+    int64_t boundary;         /* candidates stopped by the spherical boundary */
 } crp_counters;
 
 typedef struct crp_ctx crp_ctx;
@@ -134,6 +160,10 @@ crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int
                               int64_t nx, int64_t ny, int64_t nz, double spacing_m,
                               const double origin_m[3]);
 
+/* Analytic field for CRP_FIELD_ANALYTIC (model above); copied.  Radii and
+ * heights must be positive and every value finite.  Errors: CRP_EINVAL. */
+crp_status crp_set_field_analytic(crp_ctx* ctx, const crp_analytic_field* field);
+
 /* Interaction tables per nucleon at eps = E/A on n strictly increasing nodes
  * (eV): pion-like rate, nucleon-loss-like rate, proton relative loss rate
  * (all 1/m, >= 0).  A nucleus (A, Z) uses R_pi = A t_pi(E/A),
@@ -151,7 +181,8 @@ crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e_nodes_eV,
  * host memory (on_device = 0) or device memory (on_device = 1).  Injected
  * candidates start with L = 0, step h_min, event count 0, lineage 0.
  * Errors: CRP_EINVAL (first bad index in crp_last_error; only checked for
- * host input), CRP_EQUEUE (capacity), CRP_ESTATE (no grid yet). */
+ * host input), CRP_EQUEUE (capacity), CRP_ESTATE (no field yet).  With the
+ * analytic field the grid-cell bound on |pos| + lmax does not apply. */
 crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t* A,
                       const int32_t* Z, const double* E_eV, const double* pos_m,
                       const double* dir, const double* lmax_m, int32_t on_device);
@@ -185,8 +216,9 @@ crp_status crp_reset_counters(crp_ctx* ctx);
 
 /* Field at n positions pos [n][3] (m) into B [n][3] (T), with the stepper's
  * own interpolation: mode CRP_FP64 (FP64 weights), CRP_MIX (FP32 weights and
- * sums) or CRP_FIELD_NEURAL + 16 (the trained network).  Pointers are host
- * (on_device = 0) or device memory.  Errors: CRP_ESTATE, CRP_EINVAL. */
+ * sums), CRP_FIELD_NEURAL + 16 (the trained network) or CRP_FIELD_ANALYTIC + 16
+ * (the analytic field, FP64).  Pointers are host (on_device = 0) or device
+ * memory.  Errors: CRP_ESTATE, CRP_EINVAL. */
 crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* B_T,
                           int32_t mode, int32_t on_device);
 

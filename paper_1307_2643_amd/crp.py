@@ -20,14 +20,16 @@ OK, INCOMPLETE, EOVERFLOW = 0, 1, 2
 STATUS_NAMES = {0: "CRP_OK", 1: "CRP_INCOMPLETE", 2: "CRP_EOVERFLOW", -1: "CRP_EINVAL",
                 -2: "CRP_EDEVICE", -3: "CRP_ENOMEM", -4: "CRP_ESTATE", -5: "CRP_EQUEUE"}
 FP64, MIX = 0, 1
-FIELD_GRID, FIELD_NEURAL = 0, 1
+FIELD_GRID, FIELD_NEURAL, FIELD_ANALYTIC = 0, 1, 2
 EVAL_NEURAL = 16 + FIELD_NEURAL
+EVAL_ANALYTIC = 16 + FIELD_ANALYTIC
 F32, F64 = 0, 1
 LAYOUT_LINEAR, LAYOUT_CORNER = 0, 1
-ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR = 0, 1, 2, 3
+ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR, BOUNDARY = 0, 1, 2, 3, 4
 NF_NPARAM = 66435
 
-EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_tables", "crp_inject",
+EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_field_analytic",
+           "crp_set_tables", "crp_inject",
            "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_peek_pending",
            "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_set_launch",
            "crp_get_launch", "crp_tune", "crp_last_timing", "crp_gather_ceiling",
@@ -48,7 +50,14 @@ class Config(C.Structure):
                 ("hmax", C.c_double), ("eps_loss", C.c_double), ("kappa_pi", C.c_double),
                 ("e_floor", C.c_double), ("obs_center", C.c_double * 3),
                 ("obs_radius", C.c_double), ("seed", C.c_uint64),
-                ("queue_capacity", C.c_int64), ("neutral_capacity", C.c_int64)]
+                ("queue_capacity", C.c_int64), ("neutral_capacity", C.c_int64),
+                ("charge_sign", C.c_int32), ("pad_", C.c_int32),
+                ("boundary_center", C.c_double * 3), ("boundary_radius", C.c_double)]
+
+
+class AnalyticField(C.Structure):
+    _fields_ = [("center", C.c_double * 3)] + [(k, C.c_double) for k in (
+        "b_disk", "r_disk", "h_disk", "b_halo", "r_halo", "h_halo", "b_x", "r_x", "h_x")]
 
 
 class Launch(C.Structure):
@@ -77,7 +86,7 @@ class NeutralSoA(C.Structure):
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts",
                 "rejects", "forced", "events", "null_events", "inter_pi", "inter_n",
                 "charged_sec", "neutral_sec", "queue_dropped", "neutral_dropped", "pending",
-                "finished_unread", "neutral_unread", "lane_slots")
+                "finished_unread", "neutral_unread", "lane_slots", "boundary")
 
 
 class Counters(C.Structure):
@@ -108,6 +117,7 @@ def load():
         "crp_create": ([_P(Config), vp, _P(vp)], C.c_int),
         "crp_destroy": ([vp], None),
         "crp_set_field_grid": ([vp, vp, i32, i32, i64, i64, i64, dbl, vp], C.c_int),
+        "crp_set_field_analytic": ([vp, _P(AnalyticField)], C.c_int),
         "crp_set_tables": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "crp_inject": ([vp, i64, vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "crp_propagate": ([vp, i64], C.c_int),
@@ -185,6 +195,10 @@ class Params:
     seed: int = 1
     queue_capacity: int = 1 << 16
     neutral_capacity: int = 1 << 16
+    charge_sign: int = 1
+    pad_: int = 0
+    boundary_center: tuple = (0.0, 0.0, 0.0)
+    boundary_radius: float = 0.0
 
 
 class Context:
@@ -195,9 +209,9 @@ class Context:
         c = Config()
         for k, _ in Config._fields_:
             v = getattr(params, k)
-            if k == "obs_center":
+            if k in ("obs_center", "boundary_center"):
                 for a in range(3):
-                    c.obs_center[a] = float(v[a])
+                    getattr(c, k)[a] = float(v[a])
             else:
                 setattr(c, k, v)
         self.params = params
@@ -251,6 +265,16 @@ class Context:
         self._check(self.L.crp_set_field_grid(self.h, _ptr(grid), dt, int(on_dev),
                                               grid.shape[0], grid.shape[1], grid.shape[2],
                                               float(spacing), org))
+
+    def set_field_analytic(self, model):
+        """The analytic galactic field: a dict with center (3, m), b_disk, r_disk,
+        h_disk, b_halo, r_halo, h_halo, b_x, r_x, h_x (tesla, metres)."""
+        f = AnalyticField()
+        for a in range(3):
+            f.center[a] = float(model["center"][a])
+        for k, _ in AnalyticField._fields_[1:]:
+            setattr(f, k, float(model[k]))
+        self._check(self.L.crp_set_field_analytic(self.h, C.byref(f)))
 
     def set_tables(self, tables):
         arrs = [np.ascontiguousarray(a, np.float64) for a in
@@ -409,7 +433,10 @@ def params_for(workload, precision=FP64, **kw):
     """Params matching a workload description (see crp_inputs.Workload)."""
     p = Params(precision=precision, tol=workload.tol, hmin=workload.hmin_m,
                hmax=workload.hmax_m, obs_center=workload.observer,
-               obs_radius=workload.obs_radius_m, seed=workload.philox_seed)
+               obs_radius=workload.obs_radius_m, seed=workload.philox_seed,
+               charge_sign=workload.charge_sign, boundary_center=workload.boundary_center,
+               boundary_radius=workload.boundary_radius_m,
+               field_mode=FIELD_ANALYTIC if workload.field == "analytic" else FIELD_GRID)
     for k, v in kw.items():
         setattr(p, k, v)
     return p

@@ -468,6 +468,49 @@ struct GridField {
     }
 };
 
+// Analytic galactic field (section 4: analytic field models for galactic
+// propagation; a synthetic disk / halo / X-field model, see crp.h), FP64 in
+// the order written: the toroidal factor g with B_t = g (-y, x, 0), then the
+// X-field B_x = x q, B_y = y q, B_z = b_x / D - b_x r^2 / (r_x^2 D^2) with
+// q = b_x z / (h_x^2 D^2).  The precision form rounds the result to FP32.
+// Analytic galactic field: the model parameters and the derived constants
+// (1/r_disk^2, 1/h_disk^2, 1/r_halo^2, 1/h_halo^2, 1/h_halo, 1/r_x^2, 1/h_x^2),
+// each formed on the host as one FP64 operation on the squared value.
+struct AnalyticParams {
+    double center[3];
+    double b_disk, r_disk, b_halo, r_halo, b_x;
+    double kd, ld, kh, lh, ih, kx, lx;
+};
+
+struct AnalyticFieldSrc {
+    AnalyticParams a;
+    __device__ inline void fp64(const double p[3], double B[3], bool need = true) const
+    {
+        (void)need;
+        const double dx = p[0] - a.center[0], dy = p[1] - a.center[1], dz = p[2] - a.center[2];
+        const double r2 = dx * dx + dy * dy;
+        const double z2 = dz * dz;
+        const double gd = a.b_disk / ((a.r_disk * (1.0 + r2 * a.kd)) * (1.0 + z2 * a.ld));
+        const double wh = 1.0 + z2 * a.lh;
+        const double gh = (a.b_halo * (dz * a.ih)) / ((a.r_halo * (1.0 + r2 * a.kh)) * (wh * wh));
+        const double g = gd + gh;
+        const double D = (1.0 + r2 * a.kx) + z2 * a.lx;
+        const double D2 = D * D;
+        const double q = (a.b_x * (dz * a.lx)) / D2;
+        B[0] = (-g) * dy + dx * q;
+        B[1] = g * dx + dy * q;
+        B[2] = a.b_x / D - (a.b_x * (r2 * a.kx)) / D2;
+    }
+    __device__ inline void fp32(const double p[3], float B[3], bool need = true) const
+    {
+        double b[3];
+        fp64(p, b, need);
+        B[0] = (float)b[0];
+        B[1] = (float)b[1];
+        B[2] = (float)b[2];
+    }
+};
+
 // -------------------------------------------------------------------------
 // One Cash-Karp attempt.  FP64 form: state y = (x, u), derivative
 // K = (u, kappa u x B(x)), kappa = Z c / E.  Returns the error estimate

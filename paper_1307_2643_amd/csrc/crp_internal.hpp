@@ -48,6 +48,7 @@ struct DevCounters {
     unsigned long long finished, observed, max_traj, energy_floor;
     unsigned long long queue_dropped, neutral_dropped;
     unsigned long long lane_slots;          // 64 x wave iterations
+    unsigned long long boundary;            // stopped by the spherical boundary
     unsigned long long error;               // nonzero: a wave gave up waiting
 };
 
@@ -63,7 +64,10 @@ struct StepParams {
     double obs[3], obs_r;
     uint64_t seed;
     int renorm;
+    int charge_sign;             // +1 forward, -1 backtracking
+    double bnd[3], bnd_r;        // spherical boundary (bnd_r = 0: none)
 };
+
 
 // Neural-field source of the propagation kernel: the network image in global
 // memory (staged into LDS by every block) and the grid period it was fit on.
@@ -88,6 +92,7 @@ struct PropParams {
     unsigned long long fin0;     // finished-record count at the launch
     int refill;                  // idle lanes that trigger a claim (1..64)
     NFProp nf;                   // used by the neural-field instantiation only
+    AnalyticParams ana;          // used by the analytic-field instantiation only
 };
 
 enum { MODE_FP64 = 0, MODE_MIX = 1 };

@@ -16,7 +16,7 @@
 namespace crp {
 
 enum { LIM_CTRL = 0, LIM_TRAJ = 1, LIM_INTER = 2, LIM_LOSS = 3, LIM_OBS = 4 };
-enum { ST_ACTIVE = 0, ST_OBSERVED = 1, ST_MAX_TRAJ = 2, ST_ENERGY_FLOOR = 3 };
+enum { ST_ACTIVE = 0, ST_OBSERVED = 1, ST_MAX_TRAJ = 2, ST_ENERGY_FLOOR = 3, ST_BOUNDARY = 4 };
 
 struct Cand {
     double x[3], u[3], u0[3];
@@ -53,7 +53,8 @@ __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
 // with an LDS atomic where they happen.
 enum {
     WC_STEPS = 0, WC_ATTEMPTS, WC_REJECTS, WC_FORCED, WC_EVENTS, WC_NULL, WC_PI, WC_N,
-    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_LANES, WC_COUNT
+    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_LANES, WC_BOUNDARY,
+    WC_COUNT
 };
 enum : uint32_t { EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_FIN = 1u << 3 };
 
@@ -75,7 +76,7 @@ __device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* 
         &cnt->steps, &cnt->attempts, &cnt->rejects, &cnt->forced, &cnt->events,
         &cnt->null_events, &cnt->inter_pi, &cnt->inter_n, &cnt->finished, &cnt->observed,
         &cnt->max_traj, &cnt->energy_floor, &cnt->queue_dropped, &cnt->neutral_dropped,
-        &cnt->lane_slots};
+        &cnt->lane_slots, &cnt->boundary};
     const int i = (int)threadIdx.x;
     if (i < WC_COUNT && bc[i] != 0ull) {
         atomicAdd(dst[i], bc[i]);
@@ -158,7 +159,8 @@ __device__ inline const T* opaque(const T* p)
 }
 
 // Field source of a layout: 0 linear grid, 1 corner records (per lane),
-// 2 corner records gathered by the whole wave, 3 the neural field.
+// 2 corner records gathered by the whole wave, 3 the neural field, 4 the
+// analytic galactic field.
 template <class GT, int LAYOUT>
 struct FieldOf {
     using T = GridField<GT, LAYOUT>;
@@ -166,6 +168,10 @@ struct FieldOf {
 template <class GT>
 struct FieldOf<GT, 3> {
     using T = NeuralFieldSrc;
+};
+template <class GT>
+struct FieldOf<GT, 4> {
+    using T = AnalyticFieldSrc;
 };
 
 template <int MODE>
@@ -231,6 +237,8 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         nf_stage_lds(img, PP->nf.img);
         __syncthreads();
         F.v = nf_view_lds(img, PP->nf.origin, PP->nf.inv_box, PP->nf.b_scale);
+    } else if constexpr (LAYOUT == 4) {
+        F.a = PP->ana;
     } else {
         F.g = PP->grid;
         F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * COOP_STAGE_FLOAT4 : 0));
@@ -388,7 +396,8 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                     flag = LIM_OBS;
                 }
             }
-            kappa = ((double)Z * kC) / E;
+            // backtracking follows the antiparticle: charge -Z
+            kappa = ((double)(sp.charge_sign * Z) * kC) / E;
             S.R[t] = R;
             S.beta[t] = beta;
             S.azf[t] = pack_azf(A, Z, flag);
@@ -424,7 +433,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         double x5[3];
         UT u5[3];
         double err = 0.0;
-        if (active || LAYOUT >= 2) {
+        if (active || LAYOUT == 2 || LAYOUT == 3) {
             if constexpr (MODE == MODE_FP64) {
                 const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
@@ -548,6 +557,11 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                     if (sqrt(dot3(d, d)) <= sp.obs_r)
                         status = ST_OBSERVED;
                 }
+                if (status == ST_ACTIVE && sp.bnd_r > 0.0) {
+                    const double d[3] = {x[0] - sp.bnd[0], x[1] - sp.bnd[1], x[2] - sp.bnd[2]};
+                    if (sqrt(dot3(d, d)) >= sp.bnd_r)
+                        status = ST_BOUNDARY;
+                }
                 if (status == ST_ACTIVE && (flag == LIM_TRAJ || L >= S.Lmax[t]))
                     status = ST_MAX_TRAJ;
                 if (status == ST_ACTIVE && E < sp.e_floor)
@@ -555,9 +569,10 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                 if (status != ST_ACTIVE) {
                     ev |= EV_FIN;
                     atomicAdd(&bc[WC_FINISHED], 1ull);
-                    atomicAdd(&bc[status == ST_OBSERVED ? WC_OBSERVED
-                                                        : (status == ST_MAX_TRAJ ? WC_MAXTRAJ
-                                                                                 : WC_EFLOOR)],
+                    atomicAdd(&bc[status == ST_OBSERVED   ? WC_OBSERVED
+                                  : status == ST_BOUNDARY ? WC_BOUNDARY
+                                  : status == ST_MAX_TRAJ ? WC_MAXTRAJ
+                                                          : WC_EFLOOR],
                               1ull);
                 } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
                     park = true;
@@ -742,6 +757,8 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     template __global__ void k_propagate<MODE, GT, LAYOUT, 128>(const PropParams*); \
     template __global__ void k_propagate<MODE, GT, LAYOUT, 256>(const PropParams*);
 CRP_INST(MODE_FP64, double, 0)
+CRP_INST(MODE_FP64, double, 4)
+CRP_INST(MODE_MIX, double, 4)
 CRP_INST(MODE_FP64, float, 0)
 CRP_INST(MODE_FP64, float, 2)
 CRP_INST(MODE_MIX, double, 0)
@@ -842,6 +859,23 @@ template __global__ void k_eval_field<float, 1>(GridView, int64_t, const double*
 // -------------------------------------------------------------------------
 // Corner-replicated layout: record of cell (i,j,k) = the 8 corner vectors
 // (c = dx + 2 dy + 4 dz) of an FP32 linear grid, padded to 128 bytes.
+// The analytic field at n positions (FP64).
+__global__ void k_eval_analytic(AnalyticParams a, int64_t n, const double* __restrict__ pos,
+                                double* __restrict__ B)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    AnalyticFieldSrc F;
+    F.a = a;
+    const double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    double b[3];
+    F.fp64(p, b);
+    B[3 * i] = b[0];
+    B[3 * i + 1] = b[1];
+    B[3 * i + 2] = b[2];
+}
+
 // -------------------------------------------------------------------------
 // Diagnostic (not a step of the method): the field-gather pattern alone.
 // Every wave repeatedly gathers the corner records of 64 pseudo-random cells

@@ -35,6 +35,7 @@ __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id
                          uint64_t seed, double hmin, int mix);
 __global__ void k_corner_relayout(GridView g, float* out);
 __global__ void k_gather_ceiling(const float* corner, uint32_t ncell, int iters, float* sink);
+__global__ void k_eval_analytic(AnalyticParams a, int64_t n, const double* pos, double* B);
 }  // namespace crp
 
 using namespace crp;
@@ -58,6 +59,8 @@ struct crp_ctx {
 
     // tables (device: e, tpi, tn, bp consecutive)
     bool has_tables = false;
+    bool has_analytic = false;
+    AnalyticParams ana{};
     double* tab = nullptr;
     int tab_n = 0;
     float lg0 = 0.0f, lgscale = 0.0f;
@@ -329,6 +332,11 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.sp.obs_r = c.obs_radius;
     P.sp.seed = c.seed;
     P.sp.renorm = c.renormalize;
+    P.sp.charge_sign = c.charge_sign == -1 ? -1 : 1;
+    for (int a = 0; a < 3; ++a)
+        P.sp.bnd[a] = c.boundary_center[a];
+    P.sp.bnd_r = c.boundary_radius;
+    P.ana = ctx->ana;
     P.max_cycles = max_cycles;
     P.tail0 = (unsigned long long)ctx->pending;
     P.fin0 = init.fin_n;
@@ -339,8 +347,9 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     const bool neural = c.field_mode == CRP_FIELD_NEURAL;
     if (neural)
         nf_prop_params(ctx->nf, P.grid, &P.nf);
+    const bool analytic = c.field_mode == CRP_FIELD_ANALYTIC;
     const int layout = ctx->launch.layout;
-    if (layout == CRP_LAYOUT_CORNER && !neural) {
+    if (layout == CRP_LAYOUT_CORNER && !neural && !analytic) {
         crp_status st = ensure_corner(ctx);
         if (st != CRP_OK)
             return st;
@@ -352,7 +361,10 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     const bool f32 = ctx->grid_dtype == CRP_F32;
     int bpc = ctx->launch.blocks_per_cu;
     if (bpc == 0) {   // as many blocks as fit on a compute unit
-        if (!mix && !f32)
+        if (analytic)
+            bpc = mix ? resident_blocks<MODE_MIX, double, 4>(bs, lds)
+                      : resident_blocks<MODE_FP64, double, 4>(bs, lds);
+        else if (!mix && !f32)
             bpc = resident_blocks<MODE_FP64, double, 0>(bs, lds);
         else if (!mix && layout == CRP_LAYOUT_CORNER)
             bpc = resident_blocks<MODE_FP64, float, 2>(bs, lds);
@@ -385,7 +397,11 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         k_propagate<MODE_MIX, float, 3, 256><<<ctx->num_cus, 256, nl, s>>>(dp);
     } else {
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (!mix && !f32)
+    if (analytic && mix)
+        launch_propagate<MODE_MIX, double, 4>(nb, bs, lds, s, dp);
+    else if (analytic)
+        launch_propagate<MODE_FP64, double, 4>(nb, bs, lds, s, dp);
+    else if (!mix && !f32)
         launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp);
     else if (!mix && layout == CRP_LAYOUT_CORNER)
         launch_propagate<MODE_FP64, float, 2>(nb, bs, lds, s, dp);
@@ -437,6 +453,7 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
         t.queue_dropped += dc.queue_dropped;
         t.neutral_dropped += dc.neutral_dropped;
         t.lane_slots += dc.lane_slots;
+        t.boundary += dc.boundary;
     }
     ctx->pending = (int64_t)dc.park_n;
     if (dc.park_n > 0) {
@@ -458,7 +475,12 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     *out = nullptr;
     const crp_config& c = *cfg;
     if (!(c.precision == CRP_FP64 || c.precision == CRP_MIX) ||
-        !(c.field_mode == CRP_FIELD_GRID || c.field_mode == CRP_FIELD_NEURAL) ||
+        !(c.field_mode == CRP_FIELD_GRID || c.field_mode == CRP_FIELD_NEURAL ||
+          c.field_mode == CRP_FIELD_ANALYTIC) ||
+        !(c.charge_sign == -1 || c.charge_sign == 0 || c.charge_sign == 1) ||
+        !(c.boundary_radius >= 0) || !std::isfinite(c.boundary_radius) ||
+        !std::isfinite(c.boundary_center[0]) || !std::isfinite(c.boundary_center[1]) ||
+        !std::isfinite(c.boundary_center[2]) ||
         !(c.tol > 0) || !(c.hmin > 0) || !(c.hmax >= c.hmin) || !(c.eps_loss > 0) ||
         !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !(c.obs_radius >= 0) ||
         c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40) ||
@@ -606,6 +628,37 @@ crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int
     return CRP_OK;
 }
 
+crp_status crp_set_field_analytic(crp_ctx* ctx, const crp_analytic_field* f)
+{
+    if (!ctx || !f)
+        return CRP_EINVAL;
+    const double vals[] = {f->center[0], f->center[1], f->center[2], f->b_disk, f->b_halo, f->b_x};
+    for (double v : vals)
+        if (!std::isfinite(v))
+            return fail(ctx, CRP_EINVAL, "analytic field: values must be finite");
+    const double lens[] = {f->r_disk, f->h_disk, f->r_halo, f->h_halo, f->r_x, f->h_x};
+    for (double v : lens)
+        if (!(v > 0) || !std::isfinite(v))
+            return fail(ctx, CRP_EINVAL, "analytic field: radii and heights must be positive");
+    AnalyticParams& a = ctx->ana;
+    for (int k = 0; k < 3; ++k)
+        a.center[k] = f->center[k];
+    a.b_disk = f->b_disk;
+    a.r_disk = f->r_disk;
+    a.b_halo = f->b_halo;
+    a.r_halo = f->r_halo;
+    a.b_x = f->b_x;
+    a.kd = 1.0 / (f->r_disk * f->r_disk);
+    a.ld = 1.0 / (f->h_disk * f->h_disk);
+    a.kh = 1.0 / (f->r_halo * f->r_halo);
+    a.lh = 1.0 / (f->h_halo * f->h_halo);
+    a.ih = 1.0 / f->h_halo;
+    a.kx = 1.0 / (f->r_x * f->r_x);
+    a.lx = 1.0 / (f->h_x * f->h_x);
+    ctx->has_analytic = true;
+    return CRP_OK;
+}
+
 crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e, const double* tpi,
                           const double* tn, const double* bp)
 {
@@ -692,12 +745,16 @@ crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t
         return CRP_OK;
     if (!id || !A || !Z || !E || !pos || !dir || !lmax)
         return fail(ctx, CRP_EINVAL, "inject: null array");
-    if (!ctx->has_grid)
-        return fail(ctx, CRP_ESTATE, "inject: set the field grid first");
+    const bool analytic = ctx->cfg.field_mode == CRP_FIELD_ANALYTIC;
+    if (analytic ? !ctx->has_analytic : !ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "inject: set the field first");
     if (ctx->pending + n > ctx->q.cap)
         return fail(ctx, CRP_EQUEUE, "inject: queue capacity exceeded");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
-    const double max_extent = std::ldexp(1.0, 30) * ctx->spacing;
+    // the grid's cell indices bound the reach of a candidate; the analytic
+    // field has no such bound
+    const double max_extent =
+        analytic ? HUGE_VAL : std::ldexp(1.0, 30) * ctx->spacing;
     const uint32_t* d_id = id;
     const int32_t *d_A = A, *d_Z = Z;
     const double *d_E = E, *d_pos = pos, *d_dir = dir, *d_lmax = lmax;
@@ -783,6 +840,8 @@ crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles)
         return CRP_EINVAL;
     if (!ctx->has_grid && ctx->cfg.field_mode == CRP_FIELD_GRID)
         return fail(ctx, CRP_ESTATE, "propagate: no field grid");
+    if (!ctx->has_analytic && ctx->cfg.field_mode == CRP_FIELD_ANALYTIC)
+        return fail(ctx, CRP_ESTATE, "propagate: no analytic field");
     if (!ctx->has_tables)
         return fail(ctx, CRP_ESTATE, "propagate: no tables");
     if (ctx->cfg.field_mode == CRP_FIELD_NEURAL && !ctx->nf)
@@ -927,10 +986,11 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
     if (n == 0)
         return CRP_OK;
     const bool neural = mode == 16 + CRP_FIELD_NEURAL;
-    if (!(mode == CRP_FP64 || mode == CRP_MIX || neural))
+    const bool analytic = mode == 16 + CRP_FIELD_ANALYTIC;
+    if (!(mode == CRP_FP64 || mode == CRP_MIX || neural || analytic))
         return fail(ctx, CRP_EINVAL, "eval_field: bad mode");
-    if (!ctx->has_grid)
-        return fail(ctx, CRP_ESTATE, "eval_field: no field grid");
+    if (analytic ? !ctx->has_analytic : !ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "eval_field: no such field set");
     if (neural && !ctx->nf)
         return fail(ctx, CRP_ESTATE, "eval_field: neural field not initialised");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
@@ -944,7 +1004,10 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
         HIPCHK(ctx, hipMemcpyAsync((void*)dpos, pos, n * 24, hipMemcpyHostToDevice, ctx->stream));
     }
     hipError_t e = hipSuccess;
-    if (neural) {
+    if (analytic) {
+        k_eval_analytic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->ana, n, dpos, dB);
+        e = hipGetLastError();
+    } else if (neural) {
         crp_status st = nf_eval(ctx->nf, make_view(ctx), n, dpos, dB, ctx->stream);
         if (st != CRP_OK) {
             if (stage)

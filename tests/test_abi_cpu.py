@@ -56,7 +56,8 @@ def _c_struct_size(decl, name):
 @pytest.mark.parametrize("cname,pyname", [("crp_config", "Config"), ("crp_launch", "Launch"),
                                           ("crp_finished_soa", "FinishedSoA"),
                                           ("crp_neutral_soa", "NeutralSoA"),
-                                          ("crp_counters", "Counters")])
+                                          ("crp_counters", "Counters"),
+                                          ("crp_analytic_field", "AnalyticField")])
 def test_binding_struct_sizes_match_header(cname, pyname):
     from paper_1307_2643_amd import crp
     assert C.sizeof(getattr(crp, pyname)) == _c_struct_size(HEADER, cname)

@@ -1,0 +1,90 @@
+"""GPU parity of the galactic-propagation path (section 4): the analytic field,
+backtracking (charge -Z, reversed direction) and the spherical boundary,
+against the oracle on the same seeded events.  Bitwise, as both sides take the
+same FP64 operations in the same order (the field is rational: no libm)."""
+import numpy as np
+import pytest
+
+import crp_inputs as I
+from parity_helpers import CNT_KEYS, compare_counts, compare_records, say
+
+pytestmark = pytest.mark.gpu
+
+W = I.W_GALBACK
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1307_2643_amd import crp
+    crp.load()
+    return crp
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def make(P, precision, **kw):
+    prm = P.params_for(W, precision, queue_capacity=1 << 16, neutral_capacity=1 << 16, **kw)
+    ctx = P.Context(prm)
+    ctx.set_field_analytic(I.GALACTIC_FIELD)
+    ctx.set_tables(W.make_tables())
+    return ctx
+
+
+def test_analytic_field_bitwise(P, O):
+    ctx = make(P, P.FP64)
+    rng = np.random.default_rng(11)
+    pos = rng.uniform(-25, 25, (50_000, 3)) * I.KPC_M
+    pos[:3] = 0.0                                          # the centre itself
+    say("analytic field")
+    got = ctx.eval_field(pos, P.EVAL_ANALYTIC)
+    ref = O.eval_field(O.AnalyticRef(I.GALACTIC_FIELD), pos, O.FP64)
+    assert np.array_equal(got, ref)
+    ctx.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mix"])
+def test_backtracking_parity(P, O, precision):
+    inj = W.make_injection(3000)
+    ctx = make(P, precision)
+    say(f"galactic backtracking precision={precision}")
+    ctx.inject(inj)
+    assert ctx.propagate()
+    fg, cg = ctx.read_finished(), ctx.counts()
+    ctx.close()
+    fo, _, co, _ = O.propagate(O.config_for(W, precision=precision),
+                               O.AnalyticRef(I.GALACTIC_FIELD), O.TablesRef(W.make_tables()),
+                               inj, nthreads=0)
+    compare_counts(cg, co, "galactic")
+    assert cg["boundary"] == co["boundary"] and co["boundary"] > 2000
+    assert co["max_traj"] > 0                    # some low-rigidity nuclei stay confined
+    same = compare_records(fg, fo, f"galactic p{precision}")
+    assert same.all()
+
+
+def test_forward_tracking_and_launch_shapes(P, O):
+    """Charge +Z from the observer outwards, in two launch shapes."""
+    inj = W.make_injection(1000)
+    results = []
+    for launch in (dict(block=128, blocks_per_cu=0, refill=4),
+                   dict(block=256, blocks_per_cu=1, refill=64)):
+        ctx = make(P, P.FP64, charge_sign=1)
+        ctx.set_launch(**launch)
+        say(f"forward tracking launch={launch}")
+        ctx.inject(inj)
+        assert ctx.propagate()
+        results.append((P.sort_finished(ctx.read_finished()), ctx.counts()))
+        ctx.close()
+    fo, _, co, _ = O.propagate(O.config_for(W, charge_sign=1), O.AnalyticRef(I.GALACTIC_FIELD),
+                               O.TablesRef(W.make_tables()), inj)
+    for fg, cg in results:
+        compare_counts(cg, co, "forward")
+        assert compare_records(fg, fo, "forward").all()
+    for k in results[0][0]:
+        assert np.array_equal(results[0][0][k], results[1][0][k])
+    for k in CNT_KEYS:
+        assert results[0][1][k] == results[1][1][k]
