@@ -548,10 +548,31 @@ static void emit_neutral(or_neutral* neu, int64_t* n_neu, const cand_t* c, doubl
     }
 }
 
+/* Output module: one trajectory point of candidate c after its cycle. */
+static void emit_traj(or_traj* tr, int64_t* n_tr, const cand_t* c, or_counts* cnt)
+{
+    int64_t k;
+#pragma omp atomic capture
+    k = (*n_tr)++;
+    if (k >= tr->cap) {
+        cnt->traj_dropped++;
+        return;
+    }
+    tr->id[k] = c->id;
+    tr->lineage[k] = c->lineage;
+    tr->n[k] = c->nsteps;
+    tr->A[k] = c->A;
+    tr->L[k] = c->L;
+    tr->E[k] = c->E;
+    for (int q = 0; q < 3; ++q)
+        tr->x[3 * k + q] = c->x[q];
+}
+
 /* Runs one candidate until its active flag drops (or the cycle cap). */
 static void run_candidate(const or_config* cfg, const or_grid* g, const or_tables* tab,
                           cand_t* c, stack_t_* spawn, or_finished* fin, int64_t* n_fin,
-                          or_neutral* neu, int64_t* n_neu, or_counts* cnt)
+                          or_neutral* neu, int64_t* n_neu, or_traj* tr, int64_t* n_tr,
+                          or_counts* cnt)
 {
     const int mix = cfg->precision == OR_MIX;
     while (c->status == OR_ACTIVE) {
@@ -740,6 +761,11 @@ static void run_candidate(const or_config* cfg, const or_grid* g, const or_table
             c->status = OR_MAX_TRAJ;
         else if (c->E < cfg->e_floor)
             c->status = OR_ENERGY_FLOOR;
+
+        /* output module: every traj_every-th step and the last one */
+        if (tr && cfg->traj_every > 0 && c->id < cfg->traj_ids &&
+            (c->nsteps % (uint32_t)cfg->traj_every == 0 || c->status != OR_ACTIVE))
+            emit_traj(tr, n_tr, c, cnt);
     }
     switch (c->status) {
     case OR_OBSERVED:
@@ -782,10 +808,23 @@ int oracle_propagate(const or_config* cfg, const or_grid* grid, const or_tables*
                      or_finished* fin, or_neutral* neu, or_counts* counts,
                      int64_t* n_fin, int64_t* n_neu)
 {
+    return oracle_propagate_traj(cfg, grid, tab, n, id, A, Z, E, pos, dir, lmax, nthreads, fin,
+                                 neu, counts, n_fin, n_neu, NULL, NULL);
+}
+
+int oracle_propagate_traj(const or_config* cfg, const or_grid* grid, const or_tables* tab,
+                          int64_t n, const uint32_t* id, const int32_t* A, const int32_t* Z,
+                          const double* E, const double* pos, const double* dir,
+                          const double* lmax, int nthreads,
+                          or_finished* fin, or_neutral* neu, or_counts* counts,
+                          int64_t* n_fin, int64_t* n_neu, or_traj* traj, int64_t* n_traj)
+{
     int used = 1;
     memset(counts, 0, sizeof *counts);
     *n_fin = 0;
     *n_neu = 0;
+    if (n_traj)
+        *n_traj = 0;
 #ifdef _OPENMP
     if (nthreads <= 0)
         nthreads = omp_get_max_threads();
@@ -826,11 +865,13 @@ int oracle_propagate(const or_config* cfg, const or_grid* grid, const or_tables*
             uint64_t w[4];
             draw(cfg->seed, c.id, 0, 0, w);
             c.tau = oracle_texp(w[1]);
-            run_candidate(cfg, grid, tab, &c, &spawn, fin, n_fin, neu, n_neu, &local);
+            run_candidate(cfg, grid, tab, &c, &spawn, fin, n_fin, neu, n_neu, traj, n_traj,
+                          &local);
             /* secondaries after their parent, last in first out */
             while (spawn.n > 0) {
                 cand_t s = spawn.v[--spawn.n];
-                run_candidate(cfg, grid, tab, &s, &spawn, fin, n_fin, neu, n_neu, &local);
+                run_candidate(cfg, grid, tab, &s, &spawn, fin, n_fin, neu, n_neu, traj, n_traj,
+                              &local);
             }
         }
         free(spawn.v);

@@ -41,6 +41,8 @@ typedef struct {
     int32_t pad_;
     double bnd_center[3];   /* spherical boundary centre, m */
     double bnd_r;           /* boundary radius, m (0: none); leaving it ends a candidate */
+    int32_t traj_every;     /* per-step output: every k-th accepted step (0: none) */
+    uint32_t traj_ids;      /* per-step output only for candidates with id < traj_ids */
 } or_config;
 
 /* Synthetic analytic galactic field (section 4, galactic propagation: the
@@ -92,6 +94,17 @@ typedef struct {            /* neutral secondaries (pion-like channel products) 
     double *E, *x, *u;                 /* x, u: n x 3 */
 } or_neutral;
 
+/* Per-step trajectory output (section 3: output modules may record the
+ * candidate after every step).  A point is recorded after the cycle of every
+ * traj_every-th accepted step and after the cycle that ends the candidate;
+ * the injection point itself is not recorded. */
+typedef struct {
+    int64_t cap;
+    uint32_t *id, *lineage, *n;        /* n: accepted steps so far */
+    int32_t* A;
+    double *L, *E, *x;                 /* x: n x 3 */
+} or_traj;
+
 typedef struct {
     int64_t finished, observed, max_traj, energy_floor, still_active;
     int64_t steps, attempts, rejects, forced;
@@ -99,6 +112,7 @@ typedef struct {
     int64_t charged_sec, neutral_sec;
     int64_t fin_dropped, neu_dropped;
     int64_t boundary;
+    int64_t traj_dropped;              /* trajectory points beyond the capacity */
 } or_counts;
 
 /* Propagate n injected candidates to completion (or max_cycles). Returns the
@@ -109,6 +123,15 @@ int oracle_propagate(const or_config* cfg, const or_grid* grid, const or_tables*
                      const double* lmax, int nthreads,
                      or_finished* fin, or_neutral* neu, or_counts* counts,
                      int64_t* n_fin, int64_t* n_neu);
+
+/* As oracle_propagate, also recording per-step trajectory points into traj
+ * (config traj_every / traj_ids); *n_traj receives the number recorded. */
+int oracle_propagate_traj(const or_config* cfg, const or_grid* grid, const or_tables* tab,
+                          int64_t n, const uint32_t* id, const int32_t* A, const int32_t* Z,
+                          const double* E, const double* pos, const double* dir,
+                          const double* lmax, int nthreads,
+                          or_finished* fin, or_neutral* neu, or_counts* counts,
+                          int64_t* n_fin, int64_t* n_neu, or_traj* traj, int64_t* n_traj);
 
 /* Field at n positions; mode OR_FP64 or OR_MIX (MIX results are FP32 values). */
 void oracle_eval_field(const or_grid* grid, int32_t mode, int64_t n, const double* pos,

@@ -41,7 +41,7 @@ class Config(C.Structure):
                 ("kappa_pi", C.c_double), ("e_floor", C.c_double), ("obs", C.c_double * 3),
                 ("obs_r", C.c_double), ("seed", C.c_uint64), ("max_cycles", C.c_int64),
                 ("charge_sign", C.c_int32), ("pad_", C.c_int32), ("bnd_center", C.c_double * 3),
-                ("bnd_r", C.c_double)]
+                ("bnd_r", C.c_double), ("traj_every", C.c_int32), ("traj_ids", C.c_uint32)]
 
 
 class Analytic(C.Structure):
@@ -73,10 +73,16 @@ class Neutral(C.Structure):
                 ("x", _P(C.c_double)), ("u", _P(C.c_double))]
 
 
+class Traj(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("id", _P(C.c_uint32)), ("lineage", _P(C.c_uint32)),
+                ("n", _P(C.c_uint32)), ("A", _P(C.c_int32)), ("L", _P(C.c_double)),
+                ("E", _P(C.c_double)), ("x", _P(C.c_double))]
+
+
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "still_active", "steps",
                 "attempts", "rejects", "forced", "events", "null_events", "inter_pi",
                 "inter_n", "charged_sec", "neutral_sec", "fin_dropped", "neu_dropped",
-                "boundary")
+                "boundary", "traj_dropped")
 
 
 class Counts(C.Structure):
@@ -97,6 +103,9 @@ def lib():
             _P(Config), _P(Grid), _P(Tables), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, _P(Finished), _P(Neutral),
             _P(Counts), _P(C.c_int64), _P(C.c_int64)]
+        L.oracle_propagate_traj.restype = C.c_int
+        L.oracle_propagate_traj.argtypes = L.oracle_propagate.argtypes + [_P(Traj),
+                                                                          _P(C.c_int64)]
         L.oracle_eval_field.restype = None
         L.oracle_eval_field.argtypes = [_P(Grid), C.c_int32, C.c_int64, C.c_void_p, C.c_void_p]
         L.oracle_ck_attempt.restype = None
@@ -168,7 +177,8 @@ class TablesRef:
 
 def make_config(precision=FP64, tol=1e-4, hmin=None, hmax=None, eps_loss=0.1, kappa_pi=0.2,
                 e_floor=1e16, observer=(0.0, 0.0, 0.0), obs_r=0.0, seed=1, renormalize=1,
-                max_cycles=0, charge_sign=1, bnd_center=(0.0, 0.0, 0.0), bnd_r=0.0):
+                max_cycles=0, charge_sign=1, bnd_center=(0.0, 0.0, 0.0), bnd_r=0.0,
+                traj_every=0, traj_ids=0):
     kpc = 3.0856775814913673e19
     c = Config()
     c.precision = precision
@@ -188,6 +198,8 @@ def make_config(precision=FP64, tol=1e-4, hmin=None, hmax=None, eps_loss=0.1, ka
     for a in range(3):
         c.bnd_center[a] = bnd_center[a]
     c.bnd_r = bnd_r
+    c.traj_every = traj_every
+    c.traj_ids = traj_ids
     return c
 
 
@@ -206,19 +218,36 @@ FIN_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "nsteps": n
               "u0": np.float64, "E0": np.float64}
 NEU_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "chan": np.int32,
               "E": np.float64, "x": np.float64, "u": np.float64}
+TRAJ_FIELDS = {"id": np.uint32, "lineage": np.uint32, "n": np.uint32, "A": np.int32,
+               "L": np.float64, "E": np.float64, "x": np.float64}
 VEC3 = ("x", "u", "u0")
 
 
 def _alloc(fields, cap):
     out = {}
     for k, dt in fields.items():
-        out[k] = np.zeros((cap, 3) if k in VEC3 else cap, dtype=dt)
+        out[k] = np.zeros((max(cap, 1), 3) if k in VEC3 else max(cap, 1), dtype=dt)
     return out
 
 
 def propagate(cfg, grid: GridRef, tables: TablesRef, inj, nthreads=0, fin_cap=None,
               neu_cap=None):
     """Run the oracle; returns (finished dict, neutral dict, counts dict, threads)."""
+    fin, neu, counts, used, _ = _run(cfg, grid, tables, inj, nthreads, fin_cap, neu_cap, None)
+    return fin, neu, counts, used
+
+
+def propagate_traj(cfg, grid: GridRef, tables: TablesRef, inj, traj_cap, nthreads=0,
+                   fin_cap=None, neu_cap=None):
+    """Run the oracle with per-step trajectory output (config traj_every /
+    traj_ids); returns (finished, neutral, counts, trajectory points), the
+    points as a dict of arrays (id, lineage, n, A, L, E, x)."""
+    fin, neu, counts, _, traj = _run(cfg, grid, tables, inj, nthreads, fin_cap, neu_cap,
+                                     int(traj_cap))
+    return fin, neu, counts, traj
+
+
+def _run(cfg, grid, tables, inj, nthreads, fin_cap, neu_cap, traj_cap):
     n = len(inj)
     fin_cap = fin_cap if fin_cap is not None else max(16, 64 * n)
     neu_cap = neu_cap if neu_cap is not None else max(16, 64 * n)
@@ -242,16 +271,28 @@ def propagate(cfg, grid: GridRef, tables: TablesRef, inj, nthreads=0, fin_cap=No
     cnt = Counts()
     nf = C.c_int64(0)
     nn = C.c_int64(0)
-    used = lib().oracle_propagate(C.byref(cfg), C.byref(grid.s), C.byref(tables.s), n, _ptr(ids),
-                                  _ptr(A), _ptr(Z), _ptr(E), _ptr(pos), _ptr(d), _ptr(lm),
-                                  int(nthreads), C.byref(fs), C.byref(ns), C.byref(cnt),
-                                  C.byref(nf), C.byref(nn))
+    args = [C.byref(cfg), C.byref(grid.s), C.byref(tables.s), n, _ptr(ids), _ptr(A), _ptr(Z),
+            _ptr(E), _ptr(pos), _ptr(d), _ptr(lm), int(nthreads), C.byref(fs), C.byref(ns),
+            C.byref(cnt), C.byref(nf), C.byref(nn)]
+    traj = None
+    if traj_cap is None:
+        used = lib().oracle_propagate(*args)
+    else:
+        traj = _alloc(TRAJ_FIELDS, traj_cap)
+        ts = Traj()
+        ts.cap = traj_cap
+        for k in TRAJ_FIELDS:
+            setattr(ts, k, traj[k].ctypes.data_as(dict(Traj._fields_)[k]))
+        nt = C.c_int64(0)
+        used = lib().oracle_propagate_traj(*args, C.byref(ts), C.byref(nt))
+        nt = min(nt.value, traj_cap)
+        traj = {k: v[:nt] for k, v in traj.items()}
     nf = min(nf.value, fin_cap)
     nn = min(nn.value, neu_cap)
     fin = {k: v[:nf] for k, v in fin.items()}
     neu = {k: v[:nn] for k, v in neu.items()}
     counts = {k: getattr(cnt, k) for k in COUNT_FIELDS}
-    return fin, neu, counts, used
+    return fin, neu, counts, used, traj
 
 
 def eval_field(grid: GridRef, pos, mode=FP64):
@@ -302,6 +343,12 @@ def sort_finished(fin):
     """Order finished records by their key (id, lineage)."""
     order = np.lexsort((fin["lineage"], fin["id"]))
     return {k: v[order] for k, v in fin.items()}
+
+
+def sort_traj(tr):
+    """Order trajectory points by (id, lineage, step)."""
+    order = np.lexsort((tr["n"], tr["lineage"], tr["id"]))
+    return {k: v[order] for k, v in tr.items()}
 
 
 def sort_neutral(neu):
