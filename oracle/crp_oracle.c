@@ -109,6 +109,52 @@ static void field_analytic(const or_analytic* a, const double p[3], double B[3])
     B[2] = a->b_x / D - (a->b_x * (r2 * kx)) / D2;
 }
 
+/* Multi-resolution grid: the cell that holds position p.  The base cell
+ * (wrapped index i0, offset t in cell units) gives the position within one
+ * period, i0 + t; a patch k sees it at r = ((i0 - offset) + t) * refine in its
+ * own cell units and contains it if 0 <= r < n - 1 on every axis.  The last
+ * containing patch wins.  On return: *level = -1 (base) or the patch index,
+ * idx the vertex index pairs and t the offsets within the chosen cell. */
+static void nested_cell(const or_grid* g, const double p[3], int* level, int64_t idx[3][2],
+                        double t[3])
+{
+    for (int a = 0; a < 3; ++a)
+        axis_cell(g, a, p[a], idx[a], &t[a]);
+    *level = -1;
+    for (int k = g->n_patches - 1; k >= 0; --k) {
+        const or_patch* q = &g->patches[k];
+        double r[3];
+        int inside = 1;
+        for (int a = 0; a < 3; ++a) {
+            r[a] = ((double)(idx[a][0] - q->offset[a]) + t[a]) * (double)q->refine;
+            if (!(r[a] >= 0.0 && r[a] < (double)(q->n[a] - 1)))
+                inside = 0;
+        }
+        if (!inside)
+            continue;
+        for (int a = 0; a < 3; ++a) {
+            double fl = floor(r[a]);
+            idx[a][0] = (int64_t)fl;
+            idx[a][1] = idx[a][0] + 1;
+            t[a] = r[a] - fl;
+        }
+        *level = k;
+        return;
+    }
+}
+
+/* Vertex value of the base grid (level -1) or of patch `level`. */
+static double level_value(const or_grid* g, int level, int64_t i, int64_t j, int64_t k, int c)
+{
+    if (level < 0)
+        return grid_value(g, i, j, k, c);
+    const or_patch* q = &g->patches[level];
+    int64_t off = ((i * q->n[1] + j) * q->n[2] + k) * 3 + c;
+    if (g->dtype == OR_GRID_F64)
+        return ((const double*)q->data)[off];
+    return (double)((const float*)q->data)[off];
+}
+
 static void field_fp64(const or_grid* g, const double p[3], double B[3])
 {
     if (g->analytic) {
@@ -116,18 +162,18 @@ static void field_fp64(const or_grid* g, const double p[3], double B[3])
         return;
     }
     int64_t idx[3][2];
-    double w[3][2];
+    double w[3][2], t[3];
+    int level;
+    nested_cell(g, p, &level, idx, t);
     for (int a = 0; a < 3; ++a) {
-        double t;
-        axis_cell(g, a, p[a], idx[a], &t);
-        w[a][0] = 1.0 - t;
-        w[a][1] = t;
+        w[a][0] = 1.0 - t[a];
+        w[a][1] = t[a];
     }
     for (int c = 0; c < 8; ++c) {
         int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
         double wt = (w[0][dx] * w[1][dy]) * w[2][dz];
         for (int comp = 0; comp < 3; ++comp) {
-            double v = grid_value(g, idx[0][dx], idx[1][dy], idx[2][dz], comp);
+            double v = level_value(g, level, idx[0][dx], idx[1][dy], idx[2][dz], comp);
             if (c == 0)
                 B[comp] = wt * v;
             else
@@ -148,10 +194,11 @@ static void field_mix(const or_grid* g, const double p[3], float B[3])
     }
     int64_t idx[3][2];
     float w[3][2];
+    double t[3];
+    int level;
+    nested_cell(g, p, &level, idx, t);
     for (int a = 0; a < 3; ++a) {
-        double t;
-        axis_cell(g, a, p[a], idx[a], &t);
-        float tf = (float)t;
+        float tf = (float)t[a];
         w[a][0] = 1.0f - tf;
         w[a][1] = tf;
     }
@@ -159,7 +206,7 @@ static void field_mix(const or_grid* g, const double p[3], float B[3])
         int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
         float wt = (w[0][dx] * w[1][dy]) * w[2][dz];
         for (int comp = 0; comp < 3; ++comp) {
-            float v = (float)grid_value(g, idx[0][dx], idx[1][dy], idx[2][dz], comp);
+            float v = (float)level_value(g, level, idx[0][dx], idx[1][dy], idx[2][dz], comp);
             if (c == 0)
                 B[comp] = wt * v;
             else

@@ -61,6 +61,21 @@ typedef struct {
     double b_x, r_x, h_x;
 } or_analytic;
 
+/* Refinement patch of a multi-resolution grid (section 4: multi-resolution
+ * grids give fast access to precomputed fields over a larger dynamic range).
+ * A patch is a non-periodic vertex grid [n0][n1][n2][3] of the base grid's
+ * element type with spacing base_spacing / refine; its vertex (0,0,0) sits on
+ * base vertex `offset`, and it lies inside one period of the base grid.  It
+ * repeats with the base grid's period.  Level selection: a position uses the
+ * last patch (in list order) whose cells contain it, else the base grid. */
+typedef struct {
+    const void* data;
+    int64_t n[3];
+    int64_t offset[3];      /* base-grid vertex index of the patch's vertex (0,0,0) */
+    int32_t refine;         /* base cells per patch cell along each axis: 2, 4, 8 or 16 */
+    int32_t pad_;
+} or_patch;
+
 typedef struct {
     const void* data;       /* [nx][ny][nz][3] tesla, C order */
     int32_t dtype;          /* OR_GRID_F32 / OR_GRID_F64 */
@@ -69,6 +84,9 @@ typedef struct {
     double spacing;         /* m */
     double origin[3];       /* m */
     const or_analytic* analytic;   /* non-NULL: this analytic field instead of the grid */
+    int32_t n_patches;      /* refinement patches (0: a single-resolution grid) */
+    int32_t pad2_;
+    const or_patch* patches;
 } or_grid;
 
 typedef struct {

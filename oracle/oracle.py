@@ -49,10 +49,16 @@ class Analytic(C.Structure):
         "b_disk", "r_disk", "h_disk", "b_halo", "r_halo", "h_halo", "b_x", "r_x", "h_x")]
 
 
+class Patch(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n", C.c_int64 * 3), ("offset", C.c_int64 * 3),
+                ("refine", C.c_int32), ("pad_", C.c_int32)]
+
+
 class Grid(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("pad_", C.c_int32),
                 ("n", C.c_int64 * 3), ("spacing", C.c_double), ("origin", C.c_double * 3),
-                ("analytic", _P(Analytic))]
+                ("analytic", _P(Analytic)), ("n_patches", C.c_int32), ("pad2_", C.c_int32),
+                ("patches", _P(Patch))]
 
 
 class Tables(C.Structure):
@@ -132,7 +138,10 @@ def _ptr(a):
 class GridRef:
     """Keeps the numpy array alive while the C struct points into it."""
 
-    def __init__(self, data, spacing, origin=(0.0, 0.0, 0.0)):
+    def __init__(self, data, spacing, origin=(0.0, 0.0, 0.0), patches=()):
+        """patches: refinement patches, each a dict with data ([n0][n1][n2][3] of
+        the base grid's dtype), offset (base vertex index of its first vertex)
+        and refine (base cells per patch cell)."""
         data = np.asarray(data)
         if data.dtype not in (np.float32, np.float64) or data.ndim != 4 or data.shape[3] != 3:
             raise ValueError("grid must be [nx][ny][nz][3] float32/float64")
@@ -144,6 +153,19 @@ class GridRef:
             self.s.n[a] = self.arr.shape[a]
             self.s.origin[a] = float(origin[a])
         self.s.spacing = float(spacing)
+        self.patch_arrs = [np.ascontiguousarray(q["data"], self.arr.dtype) for q in patches]
+        if patches:
+            self.ps = (Patch * len(patches))()
+            for k, q in enumerate(patches):
+                a = self.patch_arrs[k]
+                assert a.ndim == 4 and a.shape[3] == 3
+                self.ps[k].data = a.ctypes.data
+                for ax in range(3):
+                    self.ps[k].n[ax] = a.shape[ax]
+                    self.ps[k].offset[ax] = int(q["offset"][ax])
+                self.ps[k].refine = int(q["refine"])
+            self.s.n_patches = len(patches)
+            self.s.patches = C.cast(self.ps, _P(Patch))
 
 
 class AnalyticRef:
