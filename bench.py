@@ -63,6 +63,10 @@ def main():
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
     ap.add_argument("--nf-steps", type=int, default=1526,
                     help="training steps of 65536 points (1526 steps = 1e8 points)")
+    ap.add_argument("--no-outputs", action="store_true",
+                    help="skip the output-module variants (trajectory points, observables)")
+    ap.add_argument("--no-nested", action="store_true",
+                    help="skip the multi-resolution grid variant")
     ap.add_argument("--no-galactic", action="store_true",
                     help="skip the galactic backtracking variant (analytic field)")
     ap.add_argument("--gal-n", type=int, default=10_000_000)
@@ -124,9 +128,9 @@ def main():
         print(json.dumps({"variant": "nf", **nf}), flush=True)
         return
 
-    def context(precision):
+    def context(precision, **kw):
         prm = crp.params_for(w, precision, device=0, queue_capacity=2 * n,
-                             neutral_capacity=max(n, 1 << 20))
+                             neutral_capacity=max(n, 1 << 20), **kw)
         ctx = crp.Context(prm, stream)
         ctx.set_field_grid(grid, w.spacing_m)
         ctx.set_tables(tables)
@@ -270,6 +274,14 @@ def main():
             fp64_fin = crp.sort_finished(c64.read_finished())
         c64.close()
 
+    # ---- output modules: per-step trajectory points and observables ---------
+    if not args.no_outputs:
+        variants["outputs"] = outputs_variant(args, crp, w, n, context, inject, launch, value)
+
+    # ---- multi-resolution grid: a refined patch inside the 1024^3 grid -------
+    if not args.no_nested:
+        variants["nested"] = nested_variant(args, crp, I, torch, w, n, grid, tables, stream, inj)
+
     # ---- CPU oracle baseline and error of the precision form ----------------
     cpu = None
     err = None
@@ -368,6 +380,102 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# Bytes the observable reduction reads per record: the status of every record,
+# and energy, mass number, source energy and both directions of a record that
+# takes part.
+OBS_BYTES_STATUS = 4
+OBS_BYTES_SELECTED = 8 + 4 + 8 + 24 + 24
+TRAJ_POINT_BYTES = 3 * 8 + 8 + 8 + 4 + 4 + 4 + 4
+
+
+def outputs_variant(args, crp, w, n, context, inject, launch, headline):
+    """The headline batch with per-step trajectory output for the first 1e5
+    candidate ids, then the observable reduction over its finished records."""
+    traj_ids = min(n, 100_000)
+    ctx = context(crp.MIX, traj_every=1, traj_ids=traj_ids, traj_capacity=150_000_000)
+    ctx.set_launch(**launch)
+    inject(ctx)                          # untimed: builds this context's grid records
+    ctx.propagate(0)
+    ctx.discard_finished()
+    ctx.discard_trajectory()
+    ctx.reset_counters()
+    inject(ctx)
+    ctx.propagate(0)
+    ms, _ = ctx.last_timing()
+    cnt = ctx.counts()
+    rate = cnt["steps"] / (ms * 1e-3)
+    traj = {"ids_recorded": traj_ids, "every": 1, "points": cnt["traj_points"],
+            "dropped": cnt["traj_dropped"], "kernel_ms": ms, "steps_per_s_kernel": rate,
+            "point_bytes": TRAJ_POINT_BYTES}
+    log(f"[bench] with per-step output of {traj_ids} candidates: {cnt['traj_points']} points, "
+        f"kernel {ms:.1f} ms ({rate:.4e} steps/s by kernel time)")
+    edges = 10.0 ** np.linspace(16.0, 22.0, 25)
+    spec = dict(e_edges=edges, a_edges=np.array([1, 2, 5, 15, 57]), status_mask=0b11110,
+                sky_n=64, sky_sign=-1.0, e_ref=1e18, gamma=-1.5)
+    ctx.set_observables(spec)
+    ctx.observe()                        # warm
+    ctx.set_observables(spec)
+    oms = ctx.observe()
+    ob = ctx.read_observables()
+    nrec = cnt["finished_unread"]
+    nsel = int(ob["counts"].sum()) + ob["outside"]
+    obytes = OBS_BYTES_STATUS * nrec + OBS_BYTES_SELECTED * nsel
+    gbs = obytes / (oms * 1e-3) / 1e9
+    log(f"[bench] observables over {nrec} records: {oms:.3f} ms, {gbs:.0f} GB/s algorithmic")
+    ctx.close()
+    obs = {"records": nrec, "selected": nsel, "kernel_ms": oms,
+           "bins": int(ob["counts"].size), "sky_pixels": int(ob["sky"].shape[-1]),
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": obytes}}
+    return {"trajectory": traj, "observe": obs}
+
+
+def nested_variant(args, crp, I, torch, w, n, grid, tables, stream, inj):
+    """The 1e7 mixed-nuclei batch started at the centre of a 512^3 refinement
+    patch (4x finer: 2.5 kpc cells over a 1.28 Mpc cube) inside the 1024^3
+    grid, against the same batch on the plain grid, both from corner records
+    gathered by the whole wave."""
+    nside, refine, off = 512, 4, 448
+    dev = grid.device
+    t0 = time.time()
+    patch = I.turbulent_grid(nside, w.spacing_m / refine, 2.0, 64.0, w.brms_T, 31, np.float32,
+                             device=dev)
+    torch.cuda.synchronize()
+    centre = (off + nside / refine / 2) * w.spacing_m
+    pos = torch.full((n, 3), centre, dtype=torch.float64, device=dev)
+    d = [torch.as_tensor(a, device=dev) for a in
+         (inj.id.view(np.int32), inj.A, inj.Z, inj.E)] + \
+        [pos] + [torch.as_tensor(a, device=dev) for a in (inj.dir, inj.lmax)]
+    log(f"[bench] nested: patch {nside}^3 x{refine} generated in {time.time() - t0:.1f}s")
+    out = {"patch": f"{nside}^3 fp32, refine {refine} ({w.spacing_m / refine / I.KPC_M:g} kpc "
+                    f"cells), offset {off}", "workload": f"{w.name} started at the patch centre"}
+    for name, patches in (("nested", [dict(data=patch, offset=(off, off, off), refine=refine)]),
+                          ("plain", [])):
+        prm = crp.params_for(w, crp.MIX, device=0, queue_capacity=2 * n,
+                             neutral_capacity=max(n, 1 << 20))
+        ctx = crp.Context(prm, stream)
+        ctx.set_field_grid(grid, w.spacing_m)
+        ctx.set_tables(tables)
+        if patches:
+            ctx.set_field_patches(patches)
+        ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=crp.LAYOUT_CORNER)
+        ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
+                   on_device=True)
+        ctx.propagate(0)
+        ms, _ = ctx.last_timing()
+        cnt = ctx.counts()
+        ctx.close()
+        rate = cnt["steps"] / (ms * 1e-3)
+        gbs = cnt["attempts"] * GATHERS_PER_ATTEMPT * 8 * 3 * 4 / (ms * 1e-3) / 1e9
+        out[name] = {"steps_per_s": rate, "kernel_ms": ms, "steps": cnt["steps"],
+                     "attempts": cnt["attempts"], "algorithmic_GBps": gbs,
+                     "hbm_frac": gbs / HBM_PEAK_GBS}
+        log(f"[bench] {name}: {rate:.4e} steps/s, kernel {ms:.1f} ms, {gbs:.0f} GB/s algorithmic")
+    del patch, pos, d
+    torch.cuda.empty_cache()
+    return out
+
+
 # FP64 operations of one Cash-Karp attempt of the FP64 method with the analytic
 # field: 6 field evaluations x 44 (3 differences, 3 for r^2, 1 for z^2, 7 disk,
 # 2 + 8 halo, 1, 4 + 1 for D and D^2, 3 for q, 3 + 3 + 5 for B) plus the stages:
@@ -404,6 +512,8 @@ def galactic_variant(args, crp, I, torch, stream):
             wall = time.perf_counter() - t0
             ms, _ = ctx.last_timing()
             c = ctx.counts()
+            if prec == crp.FP64 and rep == 1:
+                out["lens"] = lens_measure(crp, torch, ctx)
             ctx.discard_finished()
         ctx.close()
         r = {"steps_per_s": c["steps"] / wall, "events_per_s": n / wall, "kernel_ms": ms,
@@ -430,6 +540,31 @@ def galactic_variant(args, crp, I, torch, stream):
         log(f"[bench] galactic backtracking oracle: {co['steps'] / t1:.3e} steps/s on {used} "
             f"threads")
     return out
+
+
+def lens_measure(crp, torch, ctx, sky_n=32, n_maps=16):
+    """Galactic lenses (section 4) from the backtracked events still unread in
+    ctx: build time, then the application to n_maps random border maps.  One
+    map application streams the matrix once: 12 bytes per entry (column and
+    value), the row pointers, the border map and the Earth map."""
+    edges = 10.0 ** np.linspace(16.5, 20.0, 8)
+    nnz, bms = ctx.lens_build(dict(r_edges=edges, sky_n=sky_n, status_mask=1 << crp.BOUNDARY))
+    nr, npix = len(edges) - 1, 6 * sky_n * sky_n
+    nrows = nr * npix
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(71)
+    x = torch.rand((n_maps, nr, npix), dtype=torch.float64, device="cuda:0", generator=g)
+    y = torch.empty_like(x)
+    ctx.lens_apply(x, y)                                # warm
+    _, ams = ctx.lens_apply(x, y)
+    per_map = 12 * nnz + 8 * (nrows + 1) + 8 * nrows + 8 * nrows
+    gbs = n_maps * per_map / (ams * 1e-3) / 1e9
+    log(f"[bench] lenses: {nr} rigidity bins x {npix} pixels, {nnz} entries, built in "
+        f"{bms:.2f} ms; {n_maps} maps applied in {ams:.3f} ms = {gbs:.0f} GB/s algorithmic")
+    return {"rigidity_bins": nr, "pixels": npix, "nnz": nnz, "build_ms": bms,
+            "maps": n_maps, "apply_ms": ams, "bytes_per_map": per_map,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS}}
 
 
 def paper_comparable(args, crp, I, torch, stream):
@@ -650,9 +785,10 @@ def summarize_pmc(d):
             c, k = r["Counter_Name"], r["Kernel_Name"]
             if c not in ("FETCH_SIZE", "WRITE_SIZE"):
                 continue
-            # the grid propagation kernel (the neural-field instantiation has
-            # layout 3 and is excluded)
-            grid_prop = "k_propagate" in k and ", 3," not in k
+            # the timed propagation kernel: the precision form on the FP32 grid
+            # (other instantiations run in the same process for the variant
+            # lines: FP64 grids, the analytic field, the neural field)
+            grid_prop = "k_propagate<1, float, 2," in k
             kind = "prop" if grid_prop else ("copy" if "copyBuffer" in k else None)
             if kind:
                 vals.setdefault((kind, c), []).append(float(r["Counter_Value"]))

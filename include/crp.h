@@ -81,6 +81,14 @@ typedef struct {
     double boundary_center[3];/* spherical boundary centre, m */
     double boundary_radius;   /* m; 0 disables it.  A candidate at or beyond the radius
                                  after a cycle stops with status CRP_BOUNDARY */
+    int32_t traj_every;       /* per-step trajectory output (section 3: output modules
+                                 can record a candidate after every step): a point is
+                                 recorded after the cycle of every traj_every-th
+                                 accepted step and after the cycle that ends the
+                                 candidate; 0 disables it (>= 0) */
+    uint32_t traj_ids;        /* only candidates with id < traj_ids are recorded */
+    int64_t traj_capacity;    /* max undrained trajectory points (> 0 if traj_every > 0);
+                                 points beyond it are dropped and counted */
 } crp_config;
 
 /* Analytic galactic field (section 4: the code offers analytic field models;
@@ -124,6 +132,44 @@ typedef struct {
     double *E, *x, *u;
 } crp_neutral_soa;
 
+/* Caller-allocated host arrays for trajectory points ([n] or [n][3]): the
+ * candidate key (id, lineage), n = its accepted steps so far, its mass number,
+ * trajectory length, energy and position after that step's cycle. */
+typedef struct {
+    uint32_t *id, *lineage, *n;
+    int32_t* A;
+    double *L, *E, *x;
+} crp_traj_soa;
+
+/* Observables of finished records (the reductions of the paper's section 5
+ * application: energy spectrum, mean deflection against energy, sky maps).
+ * A record with status s takes part if bit s of status_mask is set.  Its
+ * energy bin e has e_edges[e] <= E < e_edges[e + 1] and its mass group g has
+ * a_edges[g] <= A < a_edges[g + 1]; records outside either range (or with a
+ * zero direction when there is a sky map) are only counted in `outside`.
+ * Per (g, e) the library sums: the record count; the weight (E0 / e_ref)^gamma
+ * (E0 the source energy: gamma reweights the injected spectrum, FP64 sum in
+ * an unspecified order); the deflection, the angle between the initial and
+ * final directions a = u/|u|, b = u0/|u0|, 2 atan2(|a - b|, |a + b|), as
+ * floor(angle * 2^32) in 64-bit fixed point (order-independent); and, with
+ * sky_n > 0, a cube-map sky map of v = sky_sign * u: face 2m + (v_m < 0) for
+ * the axis m of largest |v_m| (the lowest on ties), on it s = v_p / |v_m| and
+ * t = v_q / |v_m| for the other two axes p < q, pixel
+ * (i, j) = (floor(((s + 1) / 2) sky_n), floor(((t + 1) / 2) sky_n)) clamped
+ * to sky_n - 1, index (face * sky_n + i) * sky_n + j. */
+typedef struct {
+    int32_t n_e;              /* energy bins, 1..256 */
+    int32_t n_groups;         /* mass groups, 1..16; n_e * n_groups <= 1024 */
+    const double* e_edges;    /* [n_e + 1] eV, strictly increasing (host) */
+    const int32_t* a_edges;   /* [n_groups + 1], strictly increasing (host) */
+    int32_t status_mask;      /* bit s: records with status s take part */
+    int32_t sky_n;            /* cube-map face resolution 0..512 (0: no sky map);
+                                 n_groups * n_e * 6 sky_n^2 <= 2^27 */
+    double sky_sign;          /* +1 or -1 (-1: the arrival direction -u) */
+    double e_ref;             /* > 0, eV */
+    double gamma;             /* finite */
+} crp_observables;
+
 /* Cumulative integer bookkeeping since crp_create (or crp_reset_counters). */
 typedef struct {
     int64_t finished, observed, max_traj, energy_floor;
@@ -137,6 +183,9 @@ typedef struct {
                                  attempts / lane_slots is the fraction of lanes
                                  that carried a candidate */
     int64_t boundary;         /* candidates stopped by the spherical boundary */
+    int64_t traj_points;      /* trajectory points recorded */
+    int64_t traj_dropped;     /* trajectory points dropped (capacity) */
+    int64_t traj_unread;      /* recorded points not yet read */
 } crp_counters;
 
 typedef struct crp_ctx crp_ctx;
@@ -159,6 +208,36 @@ void crp_destroy(crp_ctx* ctx);
 crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int32_t on_device,
                               int64_t nx, int64_t ny, int64_t nz, double spacing_m,
                               const double origin_m[3]);
+
+/* Refinement patch of a multi-resolution grid (section 4: multi-resolution
+ * grids give fast access to precomputed fields over a larger dynamic range).
+ * A patch is a non-periodic vertex grid [n0][n1][n2][3] of the base grid's
+ * element type with spacing spacing_m / refine; its vertex (0,0,0) sits on
+ * base vertex `offset`, and the whole patch lies inside one period of the
+ * base grid: offset[a] * refine + n[a] - 1 <= base_n[a] * refine.  It
+ * repeats with the base grid's period. */
+typedef struct {
+    const void* data;         /* [n0][n1][n2][3] tesla, C order, the base grid's dtype */
+    int64_t n[3];             /* vertices per axis, 2 .. 2^20 */
+    int64_t offset[3];        /* base-grid vertex index of the patch's vertex (0,0,0), >= 0 */
+    int32_t refine;           /* base cells per patch cell along each axis: 2, 4, 8 or 16 */
+    int32_t on_device;        /* 0: host data, copied; 1: device pointer used in place (the
+                                 caller keeps it alive while the patches are set) */
+} crp_grid_patch;
+
+/* Sets the refinement patches of the current field grid (replacing earlier
+ * ones; n = 0 removes them; crp_set_field_grid removes them too).  Level
+ * selection: a position p is located in the base grid (wrapped vertex index
+ * i0 and offset t in cell units, as for the plain grid); patch k sees it at
+ * r = ((i0 - offset) + t) * refine and holds it if 0 <= r < n - 1 on every
+ * axis; the last such patch in list order gives the field, by trilinear
+ * interpolation of its own vertices at r (same arithmetic as the base grid),
+ * else the base grid does.  With CRP_LAYOUT_CORNER (FP32 grids) every patch
+ * gets corner records too (128 bytes per patch vertex, built on first use) and
+ * the wave gathers each lane's record from whichever level it selected.
+ * 0 <= n <= 4.  Errors: CRP_EINVAL (limits above), CRP_ESTATE (no grid),
+ * CRP_ENOMEM. */
+crp_status crp_set_field_patches(crp_ctx* ctx, int32_t n, const crp_grid_patch* patches);
 
 /* Analytic field for CRP_FIELD_ANALYTIC (model above); copied.  Radii and
  * heights must be positive and every value finite.  Errors: CRP_EINVAL. */
@@ -205,6 +284,72 @@ crp_status crp_read_finished(crp_ctx* ctx, int64_t cap, const crp_finished_soa* 
 /* Same for neutral records, keyed by (id, lineage, m). */
 crp_status crp_read_neutral(crp_ctx* ctx, int64_t cap, const crp_neutral_soa* out,
                             int64_t* n_out);
+
+/* Copies up to cap trajectory points into out and removes them from the
+ * library; *n_out receives the count.  Order is unspecified: points are keyed
+ * by (id, lineage, n).  Returns CRP_EOVERFLOW (informational) if more remain. */
+crp_status crp_read_trajectory(crp_ctx* ctx, int64_t cap, const crp_traj_soa* out,
+                               int64_t* n_out);
+
+/* Sets the observable binning (copied) and clears the sums; the sums live in
+ * device memory owned by the context.  Errors: CRP_EINVAL (limits above),
+ * CRP_ENOMEM. */
+crp_status crp_set_observables(crp_ctx* ctx, const crp_observables* spec);
+
+/* Adds every unread finished record to the observable sums, on the context
+ * stream; the records stay unread.  kernel_ms (nullable) receives the
+ * reduction kernel's duration.  Errors: CRP_ESTATE (no crp_set_observables). */
+crp_status crp_observe(crp_ctx* ctx, double* kernel_ms);
+
+/* Copies the sums (host arrays, each nullable): counts, wsum and defl
+ * [n_groups][n_e]; sky [n_groups][n_e][6 sky_n^2]; *outside. */
+crp_status crp_read_observables(crp_ctx* ctx, uint64_t* counts, double* wsum, uint64_t* defl,
+                                uint64_t* sky, uint64_t* outside);
+
+/* Galactic lenses (section 4: the lensing technique maps the directions of
+ * cosmic rays at the border of the Galaxy to directions observed at Earth
+ * with one transformation matrix per energy range).  Built here from the
+ * unread finished records of a backtracking run (charge_sign = -1, a
+ * spherical boundary): a record with status s takes part if bit s of
+ * status_mask is set and its rigidity E0 / Z lies in a bin
+ * r_edges[r] <= E0 / Z < r_edges[r + 1].  Its Earth pixel i is the cube-map
+ * pixel (the map of crp_observables, sky_n x sky_n per face, Np = 6 sky_n^2)
+ * of its launch direction u0 (the arrival direction) and its border pixel j
+ * that of its final direction u (the direction it came from, seen at the
+ * border).  Lens r: L_r[i][j] = c_r(i, j) / sum_j' c_r(i, j') with c_r the
+ * number of such records; rows without records are zero. */
+typedef struct {
+    int32_t n_r;              /* rigidity bins, 1..256 */
+    int32_t sky_n;            /* cube-map face resolution, 1..512 */
+    const double* r_edges;    /* [n_r + 1] rigidity edges (eV per unit charge), strictly
+                                 increasing (host) */
+    int32_t status_mask;      /* normally 1 << CRP_BOUNDARY */
+    int32_t pad_;
+} crp_lens_spec;
+
+/* Builds the lens set from the unread finished records (they stay unread),
+ * replacing an earlier one; the lenses live in device memory owned by the
+ * context, as one CSR matrix of n_r * Np rows (row r * Np + i), Np columns,
+ * entries of a row in increasing column order, FP64 values.  *nnz receives
+ * the number of entries; kernel_ms (nullable) the device time of the build.
+ * Errors: CRP_EINVAL (spec; more than 2^31 - 1 records), CRP_ENOMEM,
+ * CRP_EDEVICE. */
+crp_status crp_lens_build(crp_ctx* ctx, const crp_lens_spec* spec, int64_t* nnz,
+                          double* kernel_ms);
+
+/* Copies the lens set to host arrays (each nullable): rowptr [n_r Np + 1],
+ * col [nnz], val [nnz], count [nnz] (records behind each entry).
+ * Errors: CRP_ESTATE (no lens built). */
+crp_status crp_lens_read(crp_ctx* ctx, int64_t* rowptr, int32_t* col, double* val,
+                         uint64_t* count);
+
+/* Applies the lenses to n_maps border maps: x [n_maps][n_r][Np] gives
+ * y [n_maps][n_r][Np], y[m][r][i] = sum_j L_r[i][j] x[m][r][j] (FP64; the
+ * order of the sum over j is unspecified).  Pointers are host (on_device = 0)
+ * or device memory; kernel_ms (nullable) receives the kernel's duration.
+ * Errors: CRP_ESTATE (no lens), CRP_EINVAL. */
+crp_status crp_lens_apply(crp_ctx* ctx, int32_t n_maps, const double* x, double* y,
+                          int32_t on_device, double* kernel_ms);
 
 /* Copies up to cap pending (interrupted) candidates as records with status
  * CRP_ACTIVE, without removing them. */

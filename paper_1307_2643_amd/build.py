@@ -11,7 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrp.so")
-SOURCES = ["crp_kernels.hip", "crp_runtime.hip", "crp_nf.hip"]
+SOURCES = ["crp_kernels.hip", "crp_runtime.hip", "crp_nf.hip", "crp_observe.hip",
+           "crp_lens.hip"]
 ARCH = os.environ.get("CRP_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

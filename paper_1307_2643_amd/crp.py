@@ -28,9 +28,12 @@ LAYOUT_LINEAR, LAYOUT_CORNER = 0, 1
 ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR, BOUNDARY = 0, 1, 2, 3, 4
 NF_NPARAM = 66435
 
-EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_field_analytic",
+EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_field_patches",
+           "crp_set_field_analytic",
            "crp_set_tables", "crp_inject",
-           "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_peek_pending",
+           "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_read_trajectory",
+           "crp_set_observables", "crp_observe", "crp_read_observables", "crp_lens_build",
+           "crp_lens_read", "crp_lens_apply", "crp_peek_pending",
            "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_set_launch",
            "crp_get_launch", "crp_tune", "crp_last_timing", "crp_gather_ceiling",
            "crp_snapshot", "crp_restore",
@@ -52,12 +55,19 @@ class Config(C.Structure):
                 ("obs_radius", C.c_double), ("seed", C.c_uint64),
                 ("queue_capacity", C.c_int64), ("neutral_capacity", C.c_int64),
                 ("charge_sign", C.c_int32), ("pad_", C.c_int32),
-                ("boundary_center", C.c_double * 3), ("boundary_radius", C.c_double)]
+                ("boundary_center", C.c_double * 3), ("boundary_radius", C.c_double),
+                ("traj_every", C.c_int32), ("traj_ids", C.c_uint32),
+                ("traj_capacity", C.c_int64)]
 
 
 class AnalyticField(C.Structure):
     _fields_ = [("center", C.c_double * 3)] + [(k, C.c_double) for k in (
         "b_disk", "r_disk", "h_disk", "b_halo", "r_halo", "h_halo", "b_x", "r_x", "h_x")]
+
+
+class GridPatch(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n", C.c_int64 * 3), ("offset", C.c_int64 * 3),
+                ("refine", C.c_int32), ("on_device", C.c_int32)]
 
 
 class Launch(C.Structure):
@@ -83,10 +93,28 @@ class NeutralSoA(C.Structure):
                 ("u", _P(C.c_double))]
 
 
+class TrajSoA(C.Structure):
+    _fields_ = [("id", _P(C.c_uint32)), ("lineage", _P(C.c_uint32)), ("n", _P(C.c_uint32)),
+                ("A", _P(C.c_int32)), ("L", _P(C.c_double)), ("E", _P(C.c_double)),
+                ("x", _P(C.c_double))]
+
+
+class Observables(C.Structure):
+    _fields_ = [("n_e", C.c_int32), ("n_groups", C.c_int32), ("e_edges", _P(C.c_double)),
+                ("a_edges", _P(C.c_int32)), ("status_mask", C.c_int32), ("sky_n", C.c_int32),
+                ("sky_sign", C.c_double), ("e_ref", C.c_double), ("gamma", C.c_double)]
+
+
+class LensSpec(C.Structure):
+    _fields_ = [("n_r", C.c_int32), ("sky_n", C.c_int32), ("r_edges", _P(C.c_double)),
+                ("status_mask", C.c_int32), ("pad_", C.c_int32)]
+
+
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts",
                 "rejects", "forced", "events", "null_events", "inter_pi", "inter_n",
                 "charged_sec", "neutral_sec", "queue_dropped", "neutral_dropped", "pending",
-                "finished_unread", "neutral_unread", "lane_slots", "boundary")
+                "finished_unread", "neutral_unread", "lane_slots", "boundary", "traj_points",
+                "traj_dropped", "traj_unread")
 
 
 class Counters(C.Structure):
@@ -118,11 +146,19 @@ def load():
         "crp_destroy": ([vp], None),
         "crp_set_field_grid": ([vp, vp, i32, i32, i64, i64, i64, dbl, vp], C.c_int),
         "crp_set_field_analytic": ([vp, _P(AnalyticField)], C.c_int),
+        "crp_set_field_patches": ([vp, i32, _P(GridPatch)], C.c_int),
         "crp_set_tables": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "crp_inject": ([vp, i64, vp, vp, vp, vp, vp, vp, vp, i32], C.c_int),
         "crp_propagate": ([vp, i64], C.c_int),
         "crp_read_finished": ([vp, i64, _P(FinishedSoA), _P(i64)], C.c_int),
         "crp_read_neutral": ([vp, i64, _P(NeutralSoA), _P(i64)], C.c_int),
+        "crp_read_trajectory": ([vp, i64, _P(TrajSoA), _P(i64)], C.c_int),
+        "crp_set_observables": ([vp, _P(Observables)], C.c_int),
+        "crp_observe": ([vp, _P(dbl)], C.c_int),
+        "crp_read_observables": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "crp_lens_build": ([vp, _P(LensSpec), _P(i64), _P(dbl)], C.c_int),
+        "crp_lens_read": ([vp, vp, vp, vp, vp], C.c_int),
+        "crp_lens_apply": ([vp, i32, vp, vp, i32, _P(dbl)], C.c_int),
         "crp_peek_pending": ([vp, i64, _P(FinishedSoA), _P(i64)], C.c_int),
         "crp_counts": ([vp, _P(Counters)], C.c_int),
         "crp_reset_counters": ([vp], C.c_int),
@@ -164,6 +200,8 @@ FIN_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "nsteps": n
               "u0": np.float64, "E0": np.float64}
 NEU_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "chan": np.int32,
               "E": np.float64, "x": np.float64, "u": np.float64}
+TRAJ_FIELDS = {"id": np.uint32, "lineage": np.uint32, "n": np.uint32, "A": np.int32,
+               "L": np.float64, "E": np.float64, "x": np.float64}
 VEC3 = ("x", "u", "u0")
 
 
@@ -199,6 +237,9 @@ class Params:
     pad_: int = 0
     boundary_center: tuple = (0.0, 0.0, 0.0)
     boundary_radius: float = 0.0
+    traj_every: int = 0
+    traj_ids: int = 0
+    traj_capacity: int = 0
 
 
 class Context:
@@ -265,6 +306,30 @@ class Context:
         self._check(self.L.crp_set_field_grid(self.h, _ptr(grid), dt, int(on_dev),
                                               grid.shape[0], grid.shape[1], grid.shape[2],
                                               float(spacing), org))
+
+    def set_field_patches(self, patches):
+        """Refinement patches of the grid: dicts with data ([n0][n1][n2][3] numpy
+        array, copied, or a contiguous torch device tensor, used in place and
+        kept alive here), offset (base vertex index) and refine."""
+        arr = (GridPatch * max(len(patches), 1))()
+        keep = []
+        for k, q in enumerate(patches):
+            d = q["data"]
+            on_dev = hasattr(d, "is_cuda") and d.is_cuda
+            if not on_dev:
+                d = np.ascontiguousarray(d)
+            else:
+                assert d.is_contiguous()
+            assert d.ndim == 4 and d.shape[3] == 3
+            keep.append(d)
+            arr[k].data = _ptr(d)
+            for a in range(3):
+                arr[k].n[a] = int(d.shape[a])
+                arr[k].offset[a] = int(q["offset"][a])
+            arr[k].refine = int(q["refine"])
+            arr[k].on_device = int(on_dev)
+        self._check(self.L.crp_set_field_patches(self.h, len(patches), arr))
+        self._patches_keep = [d for d in keep if hasattr(d, "is_cuda")]
 
     def set_field_analytic(self, model):
         """The analytic galactic field: a dict with center (3, m), b_disk, r_disk,
@@ -336,6 +401,88 @@ class Context:
         self._check(self.L.crp_read_neutral(self.h, cap, C.byref(s), C.byref(n)),
                     ok=(OK, EOVERFLOW))
         return {k: v[:n.value] for k, v in arrs.items()}
+
+    def read_trajectory(self, cap=None):
+        """Trajectory points (dict: id, lineage, n, A, L, E, x [n][3])."""
+        cap = self.counts()["traj_unread"] if cap is None else cap
+        arrs = _alloc(TRAJ_FIELDS, cap)
+        s = _fill(TrajSoA, arrs)
+        n = C.c_int64(0)
+        self._check(self.L.crp_read_trajectory(self.h, cap, C.byref(s), C.byref(n)),
+                    ok=(OK, EOVERFLOW))
+        return {k: v[:n.value] for k, v in arrs.items()}
+
+    def discard_trajectory(self):
+        n = C.c_int64(0)
+        self._check(self.L.crp_read_trajectory(self.h, 1 << 62, None, C.byref(n)),
+                    ok=(OK, EOVERFLOW))
+        return n.value
+
+    # -- observables ----------------------------------------------------------
+    def set_observables(self, spec):
+        """spec: dict with e_edges, a_edges, status_mask, sky_n, sky_sign, e_ref,
+        gamma (the fields of crp_observables); clears the sums."""
+        ee = np.ascontiguousarray(spec["e_edges"], np.float64)
+        ae = np.ascontiguousarray(spec["a_edges"], np.int32)
+        o = Observables(len(ee) - 1, len(ae) - 1, ee.ctypes.data_as(_P(C.c_double)),
+                        ae.ctypes.data_as(_P(C.c_int32)), int(spec["status_mask"]),
+                        int(spec["sky_n"]), float(spec["sky_sign"]), float(spec["e_ref"]),
+                        float(spec["gamma"]))
+        self._check(self.L.crp_set_observables(self.h, C.byref(o)))
+        self._obs_shape = (len(ae) - 1, len(ee) - 1, 6 * int(spec["sky_n"]) ** 2)
+
+    def observe(self):
+        """Adds the unread finished records to the sums; returns the kernel ms."""
+        ms = C.c_double(0)
+        self._check(self.L.crp_observe(self.h, C.byref(ms)))
+        return ms.value
+
+    def read_observables(self):
+        ng, ne, npix = self._obs_shape
+        out = dict(counts=np.zeros((ng, ne), np.uint64), wsum=np.zeros((ng, ne)),
+                   defl=np.zeros((ng, ne), np.uint64), sky=np.zeros((ng, ne, npix), np.uint64))
+        outside = np.zeros(1, np.uint64)
+        self._check(self.L.crp_read_observables(self.h, _ptr(out["counts"]), _ptr(out["wsum"]),
+                                                _ptr(out["defl"]), _ptr(out["sky"]),
+                                                _ptr(outside)))
+        out["outside"] = int(outside[0])
+        return out
+
+    # -- galactic lenses --------------------------------------------------------
+    def lens_build(self, spec):
+        """spec: dict with r_edges, sky_n, status_mask.  Returns (nnz, ms)."""
+        re_ = np.ascontiguousarray(spec["r_edges"], np.float64)
+        ls = LensSpec(len(re_) - 1, int(spec["sky_n"]), re_.ctypes.data_as(_P(C.c_double)),
+                      int(spec["status_mask"]), 0)
+        nnz = C.c_int64(0)
+        ms = C.c_double(0)
+        self._check(self.L.crp_lens_build(self.h, C.byref(ls), C.byref(nnz), C.byref(ms)))
+        self._lens_shape = (len(re_) - 1, 6 * int(spec["sky_n"]) ** 2, nnz.value)
+        return nnz.value, ms.value
+
+    def lens_read(self):
+        nr, npix, nnz = self._lens_shape
+        out = dict(rowptr=np.zeros(nr * npix + 1, np.int64), col=np.zeros(nnz, np.int32),
+                   val=np.zeros(nnz), count=np.zeros(nnz, np.uint64))
+        self._check(self.L.crp_lens_read(self.h, _ptr(out["rowptr"]), _ptr(out["col"]),
+                                         _ptr(out["val"]), _ptr(out["count"])))
+        out.update(npix=npix, n_r=nr)
+        return out
+
+    def lens_apply(self, x, y=None):
+        """x: [n_maps][n_r][Np] float64 numpy array (or a torch device tensor,
+        then y too).  Returns (y, kernel ms)."""
+        on_dev = hasattr(x, "is_cuda") and x.is_cuda
+        if on_dev:
+            import torch
+            y = torch.empty_like(x) if y is None else y
+        else:
+            x = np.ascontiguousarray(x, np.float64)
+            y = np.empty_like(x)
+        ms = C.c_double(0)
+        self._check(self.L.crp_lens_apply(self.h, int(x.shape[0]), _ptr(x), _ptr(y),
+                                          int(on_dev), C.byref(ms)))
+        return y, ms.value
 
     def peek_pending(self, cap=None):
         cap = self.counts()["pending"] if cap is None else cap
@@ -445,6 +592,11 @@ def params_for(workload, precision=FP64, **kw):
 def sort_finished(fin):
     order = np.lexsort((fin["lineage"], fin["id"]))
     return {k: v[order] for k, v in fin.items()}
+
+
+def sort_traj(tr):
+    order = np.lexsort((tr["n"], tr["lineage"], tr["id"]))
+    return {k: v[order] for k, v in tr.items()}
 
 
 def sort_neutral(neu):

@@ -219,6 +219,23 @@ struct Cell {
     double t[3];
 };
 
+// Refinement patch of a multi-resolution grid: a non-periodic vertex grid of
+// the base grid's element type, refine patch cells per base cell, vertex 0 on
+// base vertex `off`.
+constexpr int MAX_PATCHES = 4;
+struct PatchView {
+    const void* data;
+    const float* corner;    // corner records [n0][n1][n2][32] (FP32 patches), or null
+    int n[3];
+    int off[3];
+    int64_t stride[2];      // elements: n1*n2*3, n2*3
+    double refine;
+};
+struct NestView {
+    int np;
+    PatchView p[MAX_PATCHES];
+};
+
 __device__ inline int wrap_index(int i, int n, int mask)
 {
     if (mask >= 0)
@@ -348,6 +365,32 @@ __device__ inline void coop_consume(const float* stage, float v[8][3])
         v[k][1] = f[3 * k + 1];
         v[k][2] = f[3 * k + 2];
     }
+}
+
+// As coop_issue, for records given by a per-lane address (records of several
+// arrays, e.g. the levels of a multi-resolution grid).
+__device__ inline void coop_issue_rec(const float* rec, float* stage, bool need)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    float4* st = (float4*)stage;
+    const uint64_t needm = __ballot(need);
+    const uint64_t a = (uint64_t)(uintptr_t)rec;
+    const int lo = (int)(uint32_t)a, hi = (int)(uint32_t)(a >> 32);
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int idx = 64 * j + lane;            // 0..191
+            const int r = idx / 6, c = idx - 6 * r;   // record within the half, chunk
+            const int owner = 32 * half + r;
+            const uint64_t ra = ((uint64_t)(uint32_t)__shfl(hi, owner) << 32) |
+                                (uint64_t)(uint32_t)__shfl(lo, owner);
+            const float4* src = (const float4*)(uintptr_t)ra + c;
+            if ((needm >> owner) & 1ull)
+                __builtin_amdgcn_global_load_lds((const void*)src,
+                                                 (lds_void_ptr)(st + 192 * half + 64 * j), 16, 0,
+                                                 0);
+        }
 }
 
 __device__ inline void gather_corner_coop(const float* corner, uint32_t cell, float* stage,
@@ -480,6 +523,158 @@ struct AnalyticParams {
     double center[3];
     double b_disk, r_disk, b_halo, r_halo, b_x;
     double kd, ld, kh, lh, ih, kx, lx;
+};
+
+// Multi-resolution grid: the base grid plus up to MAX_PATCHES refinement
+// patches (P: the patch table, staged in LDS).  A position is located in the
+// base grid first; the last patch whose cells hold it, in the patch's own
+// cell units r = ((i0 - off) + t) * refine, supplies the cell instead.  Each
+// lane gathers its 8 corners from whichever level it selected.
+template <class GT, bool COOP = false>
+struct NestedField {
+    GridView g;
+    const PatchView* P = nullptr;
+    int np = 0;
+    float* stage = nullptr;   // COOP: the wave's LDS staging area
+    // COOP: the corner record of the cell that holds p on its level, and the
+    // offsets t within that cell
+    __device__ inline const float* record(const double p[3], double t[3]) const
+    {
+        const Cell c = locate(g, p);
+        const float* rec = g.corner + cell_index(g, c) * 32;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            t[a] = c.t[a];
+        for (int k = np - 1; k >= 0; --k) {
+            const PatchView& q = P[k];
+            double r[3];
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                r[a] = ((double)(c.i0[a] - q.off[a]) + c.t[a]) * q.refine;
+                in = in && r[a] >= 0.0 && r[a] < (double)(q.n[a] - 1);
+            }
+            if (in) {
+                int i[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double fl = floor(r[a]);
+                    i[a] = (int)fl;
+                    t[a] = r[a] - fl;
+                }
+                rec = q.corner + (((int64_t)i[0] * q.n[1] + i[1]) * q.n[2] + i[2]) * 32;
+                break;
+            }
+        }
+        return rec;
+    }
+    __device__ inline void corners(const double p[3], GT v[8][3], double t[3], bool need) const
+    {
+        const Cell c = locate(g, p);
+        const GT* src = (const GT*)g.data;
+        int64_t ox[2] = {(int64_t)c.i0[0] * g.stride[0], (int64_t)c.i1[0] * g.stride[0]};
+        int64_t oy[2] = {(int64_t)c.i0[1] * g.stride[1], (int64_t)c.i1[1] * g.stride[1]};
+        int64_t oz[2] = {(int64_t)c.i0[2] * 3, (int64_t)c.i1[2] * 3};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            t[a] = c.t[a];
+        for (int k = np - 1; k >= 0; --k) {
+            const PatchView& q = P[k];
+            double r[3];
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                r[a] = ((double)(c.i0[a] - q.off[a]) + c.t[a]) * q.refine;
+                in = in && r[a] >= 0.0 && r[a] < (double)(q.n[a] - 1);
+            }
+            if (in) {
+                int i[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double fl = floor(r[a]);
+                    i[a] = (int)fl;
+                    t[a] = r[a] - fl;
+                }
+                src = (const GT*)q.data;
+                ox[0] = (int64_t)i[0] * q.stride[0];
+                ox[1] = ox[0] + q.stride[0];
+                oy[0] = (int64_t)i[1] * q.stride[1];
+                oy[1] = oy[0] + q.stride[1];
+                oz[0] = (int64_t)i[2] * 3;
+                oz[1] = oz[0] + 3;
+                break;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (need) {
+                const GT* e = src + ox[k & 1] + oy[(k >> 1) & 1] + oz[(k >> 2) & 1];
+                v[k][0] = e[0];
+                v[k][1] = e[1];
+                v[k][2] = e[2];
+            } else {
+                v[k][0] = v[k][1] = v[k][2] = (GT)0;
+            }
+        }
+    }
+    __device__ inline void fp64(const double p[3], double B[3], bool need = true) const
+    {
+        double t[3];
+        if constexpr (COOP) {
+            float v[8][3];
+            coop_issue_rec(record(p, t), stage, need);
+            coop_consume(stage, v);
+            interp_fp64(t, v, B);
+        } else {
+            GT v[8][3];
+            corners(p, v, t, need);
+            interp_fp64(t, v, B);
+        }
+    }
+    __device__ inline void fp32(const double p[3], float B[3], bool need = true) const
+    {
+        double t[3];
+        if constexpr (COOP) {
+            float v[8][3];
+            coop_issue_rec(record(p, t), stage, need);
+            coop_consume(stage, v);
+            interp_fp32(t, v, B);
+        } else {
+            GT v[8][3];
+            corners(p, v, t, need);
+            float vf[8][3];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    vf[k][q] = (float)v[k][q];
+            interp_fp32(t, vf, B);
+        }
+    }
+    // Split evaluation (COOP only), as GridField's: prefetch() issues the
+    // record loads of B(p); *_prefetched(p) with the same p completes it.
+    __device__ inline void prefetch(const double p[3], bool need) const
+    {
+        static_assert(COOP, "split evaluation needs the cooperative gather");
+        double t[3];
+        coop_issue_rec(record(p, t), stage, need);
+    }
+    __device__ inline void fp32_prefetched(const double p[3], float B[3]) const
+    {
+        double t[3];
+        (void)record(p, t);
+        float v[8][3];
+        coop_consume(stage, v);
+        interp_fp32(t, v, B);
+    }
+    __device__ inline void fp64_prefetched(const double p[3], double B[3]) const
+    {
+        double t[3];
+        (void)record(p, t);
+        float v[8][3];
+        coop_consume(stage, v);
+        interp_fp64(t, v, B);
+    }
 };
 
 struct AnalyticFieldSrc {

@@ -36,6 +36,14 @@ struct NeutralSoA {
     int64_t cap;
 };
 
+// Per-step trajectory points (planar x).
+struct TrajSoA {
+    double *x, *L, *E;
+    uint32_t *id, *lineage, *n;
+    int32_t* A;
+    int64_t cap;
+};
+
 // Device counter block (all 64-bit, updated with device-scope atomics).
 struct DevCounters {
     unsigned long long head;                // claim cursor of slots written before the run
@@ -49,6 +57,8 @@ struct DevCounters {
     unsigned long long queue_dropped, neutral_dropped;
     unsigned long long lane_slots;          // 64 x wave iterations
     unsigned long long boundary;            // stopped by the spherical boundary
+    unsigned long long traj_n;              // trajectory-point append cursor (may pass the
+                                            // capacity: the excess was dropped)
     unsigned long long error;               // nonzero: a wave gave up waiting
 };
 
@@ -66,6 +76,8 @@ struct StepParams {
     int renorm;
     int charge_sign;             // +1 forward, -1 backtracking
     double bnd[3], bnd_r;        // spherical boundary (bnd_r = 0: none)
+    uint32_t traj_every;         // per-step output every k-th step (0: none)
+    uint32_t traj_ids;           // ... of candidates with id below this
 };
 
 
@@ -83,6 +95,7 @@ struct PropParams {
     QueueSoA park;
     FinishedSoA fin;
     NeutralSoA neu;
+    TrajSoA traj;
     DevCounters* cnt;
     GridView grid;
     TableParams tab;
@@ -93,6 +106,24 @@ struct PropParams {
     int refill;                  // idle lanes that trigger a claim (1..64)
     NFProp nf;                   // used by the neural-field instantiation only
     AnalyticParams ana;          // used by the analytic-field instantiation only
+    NestView nest;               // used by the multi-resolution instantiation only
+};
+
+// Observable reduction over finished records (definitions in crp.h).
+constexpr int OBS_MAX_BINS = 1024;      // n_groups * n_e
+constexpr int OBS_MAX_E = 256;
+constexpr int OBS_MAX_G = 16;
+struct ObsParams {
+    const double *E, *E0, *u, *u0;      // u, u0 planar [3][cap]
+    const int32_t *status, *A;
+    int64_t cap, n;
+    const double* e_edges;              // device [ne + 1]
+    const int32_t* a_edges;             // device [ng + 1]
+    int ne, ng, sky_n;
+    uint32_t status_mask;
+    double sky_sign, e_ref, gamma;
+    unsigned long long *counts, *defl, *sky, *outside;
+    double* wsum;
 };
 
 enum { MODE_FP64 = 0, MODE_MIX = 1 };

@@ -70,16 +70,34 @@ __device__ inline void add_count(unsigned long long* bc, int i, unsigned long lo
         atomicAdd(bc + i, v);
 }
 
+// Destination of each block counter in the device counter block.
+__device__ inline unsigned long long* count_dst(DevCounters* cnt, int i)
+{
+    switch (i) {
+    case WC_STEPS: return &cnt->steps;
+    case WC_ATTEMPTS: return &cnt->attempts;
+    case WC_REJECTS: return &cnt->rejects;
+    case WC_FORCED: return &cnt->forced;
+    case WC_EVENTS: return &cnt->events;
+    case WC_NULL: return &cnt->null_events;
+    case WC_PI: return &cnt->inter_pi;
+    case WC_N: return &cnt->inter_n;
+    case WC_FINISHED: return &cnt->finished;
+    case WC_OBSERVED: return &cnt->observed;
+    case WC_MAXTRAJ: return &cnt->max_traj;
+    case WC_EFLOOR: return &cnt->energy_floor;
+    case WC_QDROP: return &cnt->queue_dropped;
+    case WC_NDROP: return &cnt->neutral_dropped;
+    case WC_LANES: return &cnt->lane_slots;
+    default: return &cnt->boundary;
+    }
+}
+
 __device__ inline void flush_counts(DevCounters* cnt, const unsigned long long* bc)
 {
-    unsigned long long* dst[WC_COUNT] = {
-        &cnt->steps, &cnt->attempts, &cnt->rejects, &cnt->forced, &cnt->events,
-        &cnt->null_events, &cnt->inter_pi, &cnt->inter_n, &cnt->finished, &cnt->observed,
-        &cnt->max_traj, &cnt->energy_floor, &cnt->queue_dropped, &cnt->neutral_dropped,
-        &cnt->lane_slots, &cnt->boundary};
     const int i = (int)threadIdx.x;
     if (i < WC_COUNT && bc[i] != 0ull) {
-        atomicAdd(dst[i], bc[i]);
+        atomicAdd(count_dst(cnt, i), bc[i]);
         // every pion-like event emits one neutral secondary, every nucleon-loss
         // event one charged secondary
         if (i == WC_PI)
@@ -110,8 +128,9 @@ __device__ inline void claim_initial(DevCounters* cnt, unsigned long long tail0,
 // (acquire) before the append cursor; all three only grow and done never
 // exceeds the written slots, so equality means that at the last read every
 // written slot was done.  Slots past the queue capacity are never written.
+// `done` receives the finished + parked count that was read.
 __device__ inline bool run_drained(DevCounters* cnt, unsigned long long fin0,
-                                   unsigned long long cap)
+                                   unsigned long long cap, unsigned long long& done)
 {
     const unsigned long long f =
         __hip_atomic_load(&cnt->fin_n, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -120,13 +139,15 @@ __device__ inline bool run_drained(DevCounters* cnt, unsigned long long fin0,
     unsigned long long t = __hip_atomic_load(&cnt->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (t > cap)
         t = cap;
-    return (f - fin0) + p == t;
+    done = (f - fin0) + p;
+    return done == t;
 }
 
 // A wave with nothing to do sleeps in units of s_sleep 127 (~3.4 us), one
 // unit more per idle iteration up to IDLE_BACKOFF (its polls of the queue
-// must not load the memory system that busy waves use); after IDLE_SLEEP_LIMIT
-// units (about 28 s) without the run draining it records an error and leaves.
+// must not load the memory system that busy waves use).  If IDLE_SLEEP_LIMIT
+// units (about 28 s) pass with no candidate of the run finishing anywhere and
+// the run not drained, it records an error and leaves.
 constexpr uint32_t IDLE_BACKOFF = 16u;
 constexpr uint32_t IDLE_SLEEP_LIMIT = 1u << 23;
 
@@ -160,7 +181,9 @@ __device__ inline const T* opaque(const T* p)
 
 // Field source of a layout: 0 linear grid, 1 corner records (per lane),
 // 2 corner records gathered by the whole wave, 3 the neural field, 4 the
-// analytic galactic field.
+// analytic galactic field, 5 the multi-resolution grid (linear base grid and
+// refinement patches), 6 the multi-resolution grid from corner records
+// gathered by the whole wave.
 template <class GT, int LAYOUT>
 struct FieldOf {
     using T = GridField<GT, LAYOUT>;
@@ -173,6 +196,18 @@ template <class GT>
 struct FieldOf<GT, 4> {
     using T = AnalyticFieldSrc;
 };
+template <class GT>
+struct FieldOf<GT, 5> {
+    using T = NestedField<GT>;
+};
+template <class GT>
+struct FieldOf<GT, 6> {
+    using T = NestedField<GT, true>;
+};
+
+// Layouts whose field values are gathered by the whole wave together.
+template <int LAYOUT>
+constexpr bool wave_gather = LAYOUT == 2 || LAYOUT == 6;
 
 template <int MODE>
 struct DirType {
@@ -195,7 +230,10 @@ struct DirType<MODE_MIX> {
 #define CRP_WAVES_FP64 2
 #endif
 
-template <int MODE, class GT, int LAYOUT, int BS>
+// TRAJ: the variant with the per-step output module compiled in (a run without
+// trajectory output uses the variant without it, whose loop carries no trace
+// of it).
+template <int MODE, class GT, int LAYOUT, int BS, bool TRAJ>
 __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64))
     k_propagate(const PropParams* __restrict__ PP)
 {
@@ -206,7 +244,9 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     __shared__ LaneShared<BS> S;              // per-lane cold state
     __shared__ unsigned long long bc[WC_COUNT];   // block bookkeeping counters
     // LDS staging of the wave-cooperative corner gather (LAYOUT 2 only)
-    __shared__ float4 stage_mem[LAYOUT == 2 ? BS / 64 * COOP_STAGE_FLOAT4 : 1];
+    __shared__ float4 stage_mem[wave_gather<LAYOUT> ? BS / 64 * COOP_STAGE_FLOAT4 : 1];
+    // patch table of the multi-resolution grid (LAYOUT 5 only)
+    __shared__ PatchView nest_lds[LAYOUT == 5 || LAYOUT == 6 ? MAX_PATCHES : 1];
     const int t = (int)threadIdx.x;
     const int ntab = PP->tab.n;
     {
@@ -220,6 +260,10 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     }
     if (t < WC_COUNT)
         bc[t] = 0ull;
+    if constexpr (LAYOUT == 5 || LAYOUT == 6) {
+        if (t < PP->nest.np)
+            nest_lds[t] = PP->nest.p[t];
+    }
     __syncthreads();
     TableView T;
     T.e = lds;
@@ -239,6 +283,12 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         F.v = nf_view_lds(img, PP->nf.origin, PP->nf.inv_box, PP->nf.b_scale);
     } else if constexpr (LAYOUT == 4) {
         F.a = PP->ana;
+    } else if constexpr (LAYOUT == 5 || LAYOUT == 6) {
+        F.g = PP->grid;
+        F.P = nest_lds;
+        F.np = PP->nest.np;
+        if constexpr (LAYOUT == 6)
+            F.stage = (float*)(stage_mem + (t >> 6) * COOP_STAGE_FLOAT4);
     } else {
         F.g = PP->grid;
         F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * COOP_STAGE_FLOAT4 : 0));
@@ -268,7 +318,8 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
     // this wave's reservation of appended slots [rb, re): taken with one
     // atomicAdd, handed to idle lanes as their producers publish them
     unsigned long long rb = 0, re = 0;
-    uint32_t iter = 0, sleeps = 0, backoff = 0;
+    uint32_t sleeps = 0, backoff = 0;
+    unsigned long long seen_done = 0;   // progress of the run seen while idle
     const unsigned long long fin0 = PP->fin0;
 
     for (;;) {
@@ -342,10 +393,16 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             // secondaries that busy waves may still append
             if (!initial_left) {
                 bool drained = false;
+                unsigned long long done = 0;
                 if (lane == 0)
-                    drained = run_drained(cnt, fin0, qcap);
+                    drained = run_drained(cnt, fin0, qcap, done);
                 if (__shfl((int)drained, 0))
                     break;
+                done = __shfl(done, 0);
+                if (done != seen_done) {   // the run is progressing: keep waiting
+                    seen_done = done;
+                    sleeps = 0;
+                }
             }
             if (backoff < IDLE_BACKOFF)
                 ++backoff;
@@ -360,7 +417,6 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
             continue;
         }
         backoff = 0;
-        ++iter;
 
         // ---- start of a cycle: rates and step proposal -----------------------
         if (active && fresh) {
@@ -405,7 +461,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         }
 
         // ---- the first-stage field of this position may already be on its way
-        if constexpr (LAYOUT == 2) {
+        if constexpr (wave_gather<LAYOUT>) {
             if (__ballot(pref) != 0ull) {
                 BT bp[3];
                 if constexpr (MODE == MODE_FP64)
@@ -426,14 +482,14 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         uint32_t ev = 0u;
         int status = ST_ACTIVE;
         double dE = 0.0, Esec = 0.0;
-        bool neutral = false, spawn = false, park = false;
+        bool neutral = false, spawn = false, park = false, rec = false;
         // with the cooperative gather every lane of the wave takes part in the
         // attempt (idle lanes on a harmless cell); results are used only by
         // busy lanes
         double x5[3];
         UT u5[3];
         double err = 0.0;
-        if (active || LAYOUT == 2 || LAYOUT == 3) {
+        if (active || wave_gather<LAYOUT> || LAYOUT == 3) {
             if constexpr (MODE == MODE_FP64) {
                 const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
@@ -450,7 +506,7 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                     err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5, active, reuse, b1);
             }
         }
-        if constexpr (LAYOUT == 2) {
+        if constexpr (wave_gather<LAYOUT>) {
             // accepted lanes move to x5: start fetching B(x5) now, so that the
             // loads overlap the rest of the cycle
             const bool acc = active && (err / sp.tol <= 1.0 || h <= sp.hmin);
@@ -577,6 +633,14 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
                 } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
                     park = true;
                 }
+                // output module: every traj_every-th step and the last one
+                if constexpr (TRAJ) {
+                    // read here rather than kept in scalar registers all loop long
+                    const StepParams& spp = opaque(PP)->sp;
+                    const uint32_t every = spp.traj_every;
+                    if (every != 0u && S.id[t] < spp.traj_ids)
+                        rec = S.nsteps[t] % every == 0u || status != ST_ACTIVE;
+                }
                 fresh = true;
             } else {
                 reuse = true;             // same position: b1 holds its field
@@ -593,6 +657,31 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
         const bool fin = (ev & EV_FIN) != 0u;
 
         // ---- appends: one atomic per wave for each kind ----------------------
+        if constexpr (TRAJ) {
+            const uint64_t mk = __ballot(rec);
+            if (mk) {
+                unsigned long long base = 0;
+                if (lane == 0)
+                    base = atomicAdd(&cnt->traj_n, (unsigned long long)__popcll(mk));
+                base = __shfl(base, 0);
+                if (rec) {
+                    const TrajSoA& tq = opaque(PP)->traj;
+                    const unsigned long long i = base + (unsigned long long)lanes_below(mk);
+                    if (i < (unsigned long long)tq.cap) {
+                        const int64_t k = (int64_t)i;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            tq.x[a * tq.cap + k] = x[a];
+                        tq.L[k] = S.L[t];
+                        tq.E[k] = S.E[t];
+                        tq.id[k] = S.id[t];
+                        tq.lineage[k] = S.lineage[t];
+                        tq.n[k] = S.nsteps[t];
+                        tq.A[k] = unpack_A(S.azf[t]);
+                    }   // points past the capacity are counted by the host
+                }
+            }
+        }
         {
             const uint64_t mk = __ballot(neutral);
             if (mk) {
@@ -753,11 +842,19 @@ __global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_
 
 // Explicit instantiations: FP64 / mixed stage arithmetic x grid element type x
 // grid layout (corner records exist for FP32 grids only).
-#define CRP_INST(MODE, GT, LAYOUT)                                                   \
-    template __global__ void k_propagate<MODE, GT, LAYOUT, 128>(const PropParams*); \
-    template __global__ void k_propagate<MODE, GT, LAYOUT, 256>(const PropParams*);
+#define CRP_INST(MODE, GT, LAYOUT)                                                          \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 128, false>(const PropParams*); \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 256, false>(const PropParams*); \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 128, true>(const PropParams*);  \
+    template __global__ void k_propagate<MODE, GT, LAYOUT, 256, true>(const PropParams*);
 CRP_INST(MODE_FP64, double, 0)
 CRP_INST(MODE_FP64, double, 4)
+CRP_INST(MODE_FP64, double, 5)
+CRP_INST(MODE_FP64, float, 5)
+CRP_INST(MODE_MIX, double, 5)
+CRP_INST(MODE_MIX, float, 5)
+CRP_INST(MODE_MIX, float, 6)
+CRP_INST(MODE_FP64, float, 6)
 CRP_INST(MODE_MIX, double, 4)
 CRP_INST(MODE_FP64, float, 0)
 CRP_INST(MODE_FP64, float, 2)
@@ -766,7 +863,8 @@ CRP_INST(MODE_MIX, float, 0)
 CRP_INST(MODE_MIX, float, 2)
 #undef CRP_INST
 // neural field (precision form, one block of 256 per CU: the network fills LDS)
-template __global__ void k_propagate<MODE_MIX, float, 3, 256>(const PropParams*);
+template __global__ void k_propagate<MODE_MIX, float, 3, 256, false>(const PropParams*);
+template __global__ void k_propagate<MODE_MIX, float, 3, 256, true>(const PropParams*);
 
 // -------------------------------------------------------------------------
 // Injection: validation (first bad index) and slot initialisation.
@@ -853,6 +951,42 @@ __global__ void k_eval_field(GridView g, int64_t n, const double* pos, double* B
 }
 
 template __global__ void k_eval_field<double, 0>(GridView, int64_t, const double*, double*, int);
+
+// The multi-resolution grid at n positions (patch table staged in LDS).
+template <class GT>
+__global__ void k_eval_nested(GridView g, NestView nv, int64_t n, const double* pos, double* B,
+                              int mode)
+{
+    __shared__ PatchView P[MAX_PATCHES];
+    if ((int)threadIdx.x < nv.np)
+        P[threadIdx.x] = nv.p[threadIdx.x];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    NestedField<GT> F;
+    F.g = g;
+    F.P = P;
+    F.np = nv.np;
+    const double p[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    if (mode == MODE_FP64) {
+        double b[3];
+        F.fp64(p, b);
+        B[3 * i] = b[0];
+        B[3 * i + 1] = b[1];
+        B[3 * i + 2] = b[2];
+    } else {
+        float b[3];
+        F.fp32(p, b);
+        B[3 * i] = (double)b[0];
+        B[3 * i + 1] = (double)b[1];
+        B[3 * i + 2] = (double)b[2];
+    }
+}
+template __global__ void k_eval_nested<double>(GridView, NestView, int64_t, const double*, double*,
+                                               int);
+template __global__ void k_eval_nested<float>(GridView, NestView, int64_t, const double*, double*,
+                                              int);
 template __global__ void k_eval_field<float, 0>(GridView, int64_t, const double*, double*, int);
 template __global__ void k_eval_field<float, 1>(GridView, int64_t, const double*, double*, int);
 

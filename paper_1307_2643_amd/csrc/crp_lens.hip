@@ -1,0 +1,288 @@
+// Galactic lenses of libcrp for gfx950 (the lensing technique of the paper's
+// section 4: per-energy transformation matrices mapping directions at the
+// border of the Galaxy to directions observed at Earth; definitions in crp.h).
+//
+// Construction from the finished records of a backtracking run: one key per
+// record (rigidity bin, Earth pixel of u0, border pixel of u), a device radix
+// sort and run-length encoding give the distinct (row, column) entries with
+// their counts in CSR order; a binary search per row gives the row pointers
+// and an integer sum per row the normalisation.
+//
+// Application: a sparse matrix times border maps, one group of LPR lanes per
+// row (LPR chosen from the mean row length), the group's partial sums combined
+// by lane shuffles.  HBM-bound: the matrix is streamed once per map.
+#include <hipcub/hipcub.hpp>
+
+#include "crp_lens.hpp"
+
+namespace crp {
+
+// Cube-map pixel (as in crp.h for the observables), -1 for a zero vector.
+__device__ inline int64_t lens_pixel(double v0, double v1, double v2, int n)
+{
+    const double a0 = fabs(v0), a1 = fabs(v1), a2 = fabs(v2);
+    int m = 0;
+    double big = a0, vm = v0, vp = v1, vq = v2;
+    if (a1 > big) {
+        m = 1;
+        big = a1;
+        vm = v1;
+        vp = v0;
+        vq = v2;
+    }
+    if (a2 > big) {
+        m = 2;
+        big = a2;
+        vm = v2;
+        vp = v0;
+        vq = v1;
+    }
+    if (!(big > 0.0))
+        return -1;
+    const double s = vp / big, t = vq / big;
+    double fi = floor(((s + 1.0) * 0.5) * (double)n);
+    double fj = floor(((t + 1.0) * 0.5) * (double)n);
+    if (fi > (double)(n - 1))
+        fi = (double)(n - 1);
+    if (fj > (double)(n - 1))
+        fj = (double)(n - 1);
+    const int64_t face = 2 * m + (vm < 0.0 ? 1 : 0);
+    return (face * n + (int64_t)fi) * n + (int64_t)fj;
+}
+
+// Key (r Np + i) Np + j of every record, or LENS_NO_KEY if it takes no part.
+__global__ void k_lens_keys(LensKeyParams p, unsigned long long* keys)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.n)
+        return;
+    unsigned long long key = LENS_NO_KEY;
+    const int32_t st = p.status[k];
+    if (st >= 0 && st <= 31 && ((p.status_mask >> st) & 1u) != 0u) {
+        const double R = p.E0[k] / (double)p.Z[k];
+        int r = -1;
+        if (R >= p.r_edges[0] && R < p.r_edges[p.n_r]) {
+            int lo = 0, hi = p.n_r;   // r_edges[lo] <= R < r_edges[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (p.r_edges[mid] <= R)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            r = lo;
+        }
+        const int64_t cap = p.cap;
+        const int64_t i = lens_pixel(p.u0[k], p.u0[cap + k], p.u0[2 * cap + k], p.sky_n);
+        const int64_t j = lens_pixel(p.u[k], p.u[cap + k], p.u[2 * cap + k], p.sky_n);
+        if (r >= 0 && i >= 0 && j >= 0)
+            key = ((unsigned long long)(r * p.npix + i)) * (unsigned long long)p.npix +
+                  (unsigned long long)j;
+    }
+    keys[k] = key;
+}
+
+// Row pointers: the first entry whose key is at least row * Np (entries are
+// sorted); entries past nvalid hold the no-key marker.  Then each row's total
+// count and every entry's column and value.
+__global__ void k_lens_rows(const unsigned long long* ukeys, int64_t nvalid, int64_t nrows,
+                            int npix, int64_t* rowptr)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row > nrows)
+        return;
+    const unsigned long long target = (unsigned long long)row * (unsigned long long)npix;
+    int64_t lo = 0, hi = nvalid;   // first index with key >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ukeys[mid] < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    rowptr[row] = lo;
+}
+
+__global__ void k_lens_rowsum(const uint32_t* counts, const int64_t* rowptr, int64_t nrows,
+                              unsigned long long* tot)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= nrows)
+        return;
+    unsigned long long s = 0;
+    for (int64_t q = rowptr[row]; q < rowptr[row + 1]; ++q)
+        s += counts[q];
+    tot[row] = s;
+}
+
+__global__ void k_lens_values(const unsigned long long* ukeys, const uint32_t* counts,
+                              const unsigned long long* tot, int64_t nvalid, int npix,
+                              int32_t* col, double* val, unsigned long long* count)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nvalid)
+        return;
+    const unsigned long long key = ukeys[e];
+    const int64_t row = (int64_t)(key / (unsigned long long)npix);
+    col[e] = (int32_t)(key % (unsigned long long)npix);
+    val[e] = (double)counts[e] / (double)tot[row];
+    count[e] = counts[e];
+}
+
+// y[m][row] = sum over the row's entries of val * x[m][r Np + col], row = r Np + i.
+template <int LPR>
+__global__ void __launch_bounds__(256) k_lens_apply(LensApplyParams p)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const int sub = lane & (LPR - 1);
+    const int64_t group = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR;
+    const int64_t m = blockIdx.y;
+    const bool live = group < p.nrows;
+    const int64_t row = live ? group : 0;
+    const int64_t base = (row / p.npix) * p.npix;     // first column of this rigidity's block
+    const double* x = p.x + m * p.map_len + base;
+    double acc = 0.0;
+    if (live) {
+        const int64_t e1 = p.rowptr[row + 1];
+        for (int64_t e = p.rowptr[row] + sub; e < e1; e += LPR)
+            acc += p.val[e] * x[p.col[e]];
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1)
+        acc += __shfl_xor(acc, o, LPR);
+    if (live && sub == 0)
+        p.y[m * p.map_len + row] = acc;
+}
+
+template __global__ void k_lens_apply<4>(LensApplyParams);
+template __global__ void k_lens_apply<8>(LensApplyParams);
+template __global__ void k_lens_apply<16>(LensApplyParams);
+template __global__ void k_lens_apply<32>(LensApplyParams);
+template __global__ void k_lens_apply<64>(LensApplyParams);
+
+// ---- host side ---------------------------------------------------------------
+
+namespace {
+int blocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+}
+
+hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s)
+{
+    lens_free(L);
+    const int64_t n = kp.n;
+    L.nrows = nrows;
+    L.npix = kp.npix;
+    L.n_r = kp.n_r;
+    hipError_t e = hipSuccess;
+    unsigned long long *keys = nullptr, *sorted = nullptr, *ukeys = nullptr, *tot = nullptr;
+    uint32_t* counts = nullptr;
+    int64_t* nruns_d = nullptr;
+    void* tmp = nullptr;
+    size_t tmp_sort = 0, tmp_rle = 0;
+    auto done = [&](hipError_t r) {
+        for (void* q : {(void*)keys, (void*)sorted, (void*)ukeys, (void*)counts,
+                        (void*)nruns_d, tmp, (void*)tot})
+            if (q)
+                (void)hipFree(q);
+        if (r != hipSuccess)
+            lens_free(L);
+        return r;
+    };
+#define LCHK(x)                  \
+    do {                         \
+        e = (x);                 \
+        if (e != hipSuccess)     \
+            return done(e);      \
+    } while (0)
+    LCHK(hipMalloc(&L.rowptr, (size_t)(nrows + 1) * sizeof(int64_t)));
+    if (n == 0) {
+        LCHK(hipMemsetAsync(L.rowptr, 0, (size_t)(nrows + 1) * sizeof(int64_t), s));
+        LCHK(hipStreamSynchronize(s));
+        L.nnz = 0;
+        return done(hipSuccess);
+    }
+    LCHK(hipMalloc(&keys, n * sizeof(unsigned long long)));
+    LCHK(hipMalloc(&sorted, n * sizeof(unsigned long long)));
+    LCHK(hipMalloc(&ukeys, n * sizeof(unsigned long long)));
+    LCHK(hipMalloc(&counts, n * sizeof(uint32_t)));
+    LCHK(hipMalloc(&nruns_d, sizeof(int64_t)));
+    k_lens_keys<<<blocks(n, 256), 256, 0, s>>>(kp, keys);
+    LCHK(hipGetLastError());
+    const int nbits = 64;
+    LCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_sort, keys, sorted, (int)n, 0, nbits, s));
+    LCHK(hipcub::DeviceRunLengthEncode::Encode(nullptr, tmp_rle, sorted, ukeys, counts, nruns_d,
+                                               (int)n, s));
+    LCHK(hipMalloc(&tmp, std::max(tmp_sort, tmp_rle)));
+    LCHK(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_sort, keys, sorted, (int)n, 0, nbits, s));
+    LCHK(hipcub::DeviceRunLengthEncode::Encode(tmp, tmp_rle, sorted, ukeys, counts, nruns_d,
+                                               (int)n, s));
+    int64_t nruns = 0;
+    unsigned long long last = 0;
+    LCHK(hipMemcpyAsync(&nruns, nruns_d, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    LCHK(hipStreamSynchronize(s));
+    if (nruns > 0) {
+        LCHK(hipMemcpyAsync(&last, ukeys + nruns - 1, sizeof(last), hipMemcpyDeviceToHost, s));
+        LCHK(hipStreamSynchronize(s));
+    }
+    const int64_t nvalid = (nruns > 0 && last == LENS_NO_KEY) ? nruns - 1 : nruns;
+    L.nnz = nvalid;
+    k_lens_rows<<<blocks(nrows + 1, 256), 256, 0, s>>>(ukeys, nvalid, nrows, kp.npix, L.rowptr);
+    LCHK(hipGetLastError());
+    if (nvalid > 0) {
+        LCHK(hipMalloc(&L.col, nvalid * sizeof(int32_t)));
+        LCHK(hipMalloc(&L.val, nvalid * sizeof(double)));
+        LCHK(hipMalloc(&L.count, nvalid * sizeof(unsigned long long)));
+        LCHK(hipMalloc(&tot, nrows * sizeof(unsigned long long)));
+        k_lens_rowsum<<<blocks(nrows, 256), 256, 0, s>>>(counts, L.rowptr, nrows, tot);
+        LCHK(hipGetLastError());
+        k_lens_values<<<blocks(nvalid, 256), 256, 0, s>>>(ukeys, counts, tot, nvalid, kp.npix,
+                                                          L.col, L.val, L.count);
+        LCHK(hipGetLastError());
+    }
+    LCHK(hipStreamSynchronize(s));
+    // lanes per row: the power of two nearest above the mean filled-row length
+    L.lpr = 4;
+    if (nvalid > 0) {
+        const double mean = (double)nvalid / (double)std::min<int64_t>(nrows, nvalid);
+        while (L.lpr < 64 && L.lpr < mean)
+            L.lpr *= 2;
+    }
+#undef LCHK
+    return done(hipSuccess);
+}
+
+hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hipStream_t s)
+{
+    LensApplyParams p;
+    p.rowptr = L.rowptr;
+    p.col = L.col;
+    p.val = L.val;
+    p.x = x;
+    p.y = y;
+    p.nrows = L.nrows;
+    p.npix = L.npix;
+    p.map_len = L.nrows;
+    const dim3 grid((unsigned)((L.nrows * L.lpr + 255) / 256), (unsigned)n_maps);
+    switch (L.lpr) {
+    case 4: k_lens_apply<4><<<grid, 256, 0, s>>>(p); break;
+    case 8: k_lens_apply<8><<<grid, 256, 0, s>>>(p); break;
+    case 16: k_lens_apply<16><<<grid, 256, 0, s>>>(p); break;
+    case 32: k_lens_apply<32><<<grid, 256, 0, s>>>(p); break;
+    default: k_lens_apply<64><<<grid, 256, 0, s>>>(p); break;
+    }
+    return hipGetLastError();
+}
+
+void lens_free(Lens& L)
+{
+    for (void* q : {(void*)L.rowptr, (void*)L.col, (void*)L.val, (void*)L.count})
+        if (q)
+            (void)hipFree(q);
+    L.rowptr = nullptr;
+    L.col = nullptr;
+    L.val = nullptr;
+    L.count = nullptr;
+    L.nnz = 0;
+}
+
+}  // namespace crp

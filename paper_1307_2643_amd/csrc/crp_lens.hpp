@@ -1,0 +1,47 @@
+// Galactic lenses: device buffers and kernel parameters shared by the lens
+// kernels (crp_lens.hip) and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crp {
+
+constexpr unsigned long long LENS_NO_KEY = ~0ull;   // a record that takes no part
+
+// A lens set in CSR form: row r Np + i (rigidity bin r, Earth pixel i), columns
+// the border pixels j in increasing order.
+struct Lens {
+    int64_t* rowptr = nullptr;          // [nrows + 1]
+    int32_t* col = nullptr;             // [nnz]
+    double* val = nullptr;              // [nnz]
+    unsigned long long* count = nullptr;   // [nnz] records behind each entry
+    int64_t nrows = 0, nnz = 0;
+    int npix = 0, n_r = 0;
+    int lpr = 4;                        // lanes per row of the application kernel
+};
+
+struct LensKeyParams {
+    const double *E0, *u, *u0;          // finished records (u, u0 planar [3][cap])
+    const int32_t *status, *Z;
+    int64_t cap, n;
+    const double* r_edges;              // device [n_r + 1]
+    int n_r, sky_n, npix;
+    uint32_t status_mask;
+};
+
+struct LensApplyParams {
+    const int64_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    const double* x;                    // [n_maps][nrows]
+    double* y;                          // [n_maps][nrows]
+    int64_t nrows, map_len;
+    int64_t npix;
+};
+
+hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s);
+hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hipStream_t s);
+void lens_free(Lens& L);
+
+}  // namespace crp

@@ -1,0 +1,192 @@
+// Observable reduction of libcrp for gfx950: finished records -> energy
+// spectrum, reweighted spectrum, deflection sums and cube-map sky counts (the
+// observables of the paper's section 5 application; definitions in crp.h).
+//
+// One streaming pass over the structure-of-arrays columns of the finished
+// records: HBM-bound (status for every record, energy, mass, source energy
+// and the two directions for the records that take part).  Per-bin sums are
+// privatised in LDS per block and flushed once; sky counts go straight to
+// global atomics (the map is too large for LDS).
+#include "crp_internal.hpp"
+
+namespace crp {
+
+// Energy bin e with ed[e] <= E < ed[e + 1], else -1 (also for NaN).
+__device__ inline int obs_e_bin(const double* ed, int ne, double E)
+{
+    if (!(E >= ed[0]) || !(E < ed[ne]))
+        return -1;
+    int lo = 0, hi = ne;   // ed[lo] <= E < ed[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ed[mid] <= E)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int obs_a_bin(const int* ae, int ng, int A)
+{
+    if (A < ae[0] || A >= ae[ng])
+        return -1;
+    int g = 0;
+    while (A >= ae[g + 1])
+        ++g;
+    return g;
+}
+
+// |v| of a 3-vector with the sums in axis order.
+__device__ inline double obs_norm(double a, double b, double c)
+{
+    return sqrt((a * a + b * b) + c * c);
+}
+
+// Cube-map pixel of v (see crp.h), -1 for a zero (or NaN) vector.
+__device__ inline int64_t obs_cube_pixel(double v0, double v1, double v2, int n)
+{
+    const double a0 = fabs(v0), a1 = fabs(v1), a2 = fabs(v2);
+    int m = 0;
+    double big = a0, vm = v0, vp = v1, vq = v2;
+    if (a1 > big) {
+        m = 1;
+        big = a1;
+        vm = v1;
+        vp = v0;
+        vq = v2;
+    }
+    if (a2 > big) {
+        m = 2;
+        big = a2;
+        vm = v2;
+        vp = v0;
+        vq = v1;
+    }
+    if (!(big > 0.0))
+        return -1;
+    const double s = vp / big, t = vq / big;
+    double fi = floor(((s + 1.0) * 0.5) * (double)n);
+    double fj = floor(((t + 1.0) * 0.5) * (double)n);
+    if (fi > (double)(n - 1))
+        fi = (double)(n - 1);
+    if (fj > (double)(n - 1))
+        fj = (double)(n - 1);
+    const int64_t face = 2 * m + (vm < 0.0 ? 1 : 0);
+    return (face * n + (int64_t)fi) * n + (int64_t)fj;
+}
+
+// Records per thread per loop iteration: their loads are all issued before
+// any of them is reduced, so several records per lane are in flight.
+constexpr int OBS_BATCH = 4;
+
+// Dynamic LDS: energy edges [ne + 1] f64, then per bin: counts u64, deflection
+// u64, weights f64, then the mass edges [ng + 1] i32.
+__global__ void __launch_bounds__(256) k_observe(ObsParams p)
+{
+    extern __shared__ __attribute__((aligned(16))) double obs_lds[];
+    __shared__ unsigned long long outside;
+    const int t = (int)threadIdx.x;
+    const int ne = p.ne, ng = p.ng, nb = ne * ng;
+    double* ed = obs_lds;
+    unsigned long long* cnt = (unsigned long long*)(ed + ne + 1);
+    unsigned long long* dfl = cnt + nb;
+    double* ws = (double*)(dfl + nb);
+    int* ae = (int*)(ws + nb);
+    for (int i = t; i <= ne; i += 256)
+        ed[i] = p.e_edges[i];
+    if (t <= ng)
+        ae[t] = p.a_edges[t];
+    for (int i = t; i < nb; i += 256) {
+        cnt[i] = 0ull;
+        dfl[i] = 0ull;
+        ws[i] = 0.0;
+    }
+    if (t == 0)
+        outside = 0ull;
+    __syncthreads();
+
+    const int64_t npix = 6 * (int64_t)p.sky_n * (int64_t)p.sky_n;
+    const int64_t stride = (int64_t)gridDim.x * 256 * OBS_BATCH;
+    const int64_t cap = p.cap;
+    for (int64_t k0 = (int64_t)blockIdx.x * 256 * OBS_BATCH + t; k0 < p.n; k0 += stride) {
+        // phase 1: the loads of OBS_BATCH records (only for records that take part)
+        bool sel[OBS_BATCH];
+        double E[OBS_BATCH], E0[OBS_BATCH], u[OBS_BATCH][3], w[OBS_BATCH][3];
+        int A[OBS_BATCH];
+#pragma unroll
+        for (int j = 0; j < OBS_BATCH; ++j) {
+            const int64_t k = k0 + (int64_t)j * 256;
+            int32_t st = -1;
+            if (k < p.n)
+                st = p.status[k];
+            sel[j] = st >= 0 && st <= 31 && ((p.status_mask >> st) & 1u) != 0u;
+            E[j] = E0[j] = 0.0;
+            A[j] = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                u[j][a] = w[j][a] = 0.0;
+            if (sel[j]) {
+                E[j] = p.E[k];
+                A[j] = p.A[k];
+                E0[j] = p.E0[k];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    u[j][a] = p.u[a * cap + k];
+                    w[j][a] = p.u0[a * cap + k];
+                }
+            }
+        }
+        // phase 2: bins, deflection, weight, sums
+#pragma unroll
+        for (int j = 0; j < OBS_BATCH; ++j) {
+            if (!sel[j])
+                continue;
+            const int e = obs_e_bin(ed, ne, E[j]);
+            const int g = obs_a_bin(ae, ng, A[j]);
+            const double u0 = u[j][0], u1 = u[j][1], u2 = u[j][2];
+            int64_t pix = 0;
+            if (p.sky_n > 0)
+                pix = obs_cube_pixel(p.sky_sign * u0, p.sky_sign * u1, p.sky_sign * u2, p.sky_n);
+            if (e < 0 || g < 0 || pix < 0) {
+                atomicAdd(&outside, 1ull);
+                continue;
+            }
+            const int b = g * ne + e;
+            // deflection: angle between the unit initial and final directions
+            const double w0 = w[j][0], w1 = w[j][1], w2 = w[j][2];
+            const double nu = obs_norm(u0, u1, u2), nw = obs_norm(w0, w1, w2);
+            const double a0 = u0 / nu, a1 = u1 / nu, a2 = u2 / nu;
+            const double b0 = w0 / nw, b1 = w1 / nw, b2 = w2 / nw;
+            const double nd = obs_norm(a0 - b0, a1 - b1, a2 - b2);
+            const double ns = obs_norm(a0 + b0, a1 + b1, a2 + b2);
+            const double ang = 2.0 * atan2(nd, ns);
+            const unsigned long long fx = (unsigned long long)floor(ang * 4294967296.0);
+            const double wt = pow(E0[j] / p.e_ref, p.gamma);
+            atomicAdd(&cnt[b], 1ull);
+            atomicAdd(&dfl[b], fx);
+            atomicAdd(&ws[b], wt);
+            if (p.sky_n > 0)
+                atomicAdd(p.sky + (int64_t)b * npix + pix, 1ull);
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < nb; i += 256) {
+        if (cnt[i] != 0ull) {
+            atomicAdd(p.counts + i, cnt[i]);
+            atomicAdd(p.defl + i, dfl[i]);
+            atomicAdd(p.wsum + i, ws[i]);
+        }
+    }
+    if (t == 0 && outside != 0ull)
+        atomicAdd(p.outside, outside);
+}
+
+// Dynamic LDS bytes of k_observe for ne energy bins and ng mass groups.
+size_t observe_lds_bytes(int ne, int ng)
+{
+    const size_t nb = (size_t)ne * (size_t)ng;
+    return (size_t)(ne + 1) * 8 + nb * 24 + (size_t)(ng + 1) * 4;
+}
+
+}  // namespace crp

@@ -18,11 +18,12 @@
 
 #include "../../include/crp.h"
 #include "crp_internal.hpp"
+#include "crp_lens.hpp"
 #include "crp_nf.hpp"
 #include "crp_nf_device.hpp"
 
 namespace crp {
-template <int MODE, class GT, int LAYOUT, int BS>
+template <int MODE, class GT, int LAYOUT, int BS, bool TRAJ>
 __global__ void k_propagate(const PropParams* PP);
 template <class GT, int LAYOUT>
 __global__ void k_eval_field(GridView g, int64_t n, const double* pos, double* B, int mode);
@@ -36,6 +37,11 @@ __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id
 __global__ void k_corner_relayout(GridView g, float* out);
 __global__ void k_gather_ceiling(const float* corner, uint32_t ncell, int iters, float* sink);
 __global__ void k_eval_analytic(AnalyticParams a, int64_t n, const double* pos, double* B);
+__global__ void k_observe(ObsParams p);
+size_t observe_lds_bytes(int ne, int ng);
+template <class GT>
+__global__ void k_eval_nested(GridView g, NestView nv, int64_t n, const double* pos, double* B,
+                              int mode);
 }  // namespace crp
 
 using namespace crp;
@@ -56,6 +62,10 @@ struct crp_ctx {
     double spacing = 0.0;
     double origin[3] = {0, 0, 0};
     float* corner = nullptr;
+    // refinement patches of the grid (multi-resolution)
+    NestView nest{};
+    void* patch_owned[MAX_PATCHES] = {nullptr, nullptr, nullptr, nullptr};
+    float* patch_corner[MAX_PATCHES] = {nullptr, nullptr, nullptr, nullptr};
 
     // tables (device: e, tpi, tn, bp consecutive)
     bool has_tables = false;
@@ -72,12 +82,14 @@ struct crp_ctx {
     FinishedSoA fin;
     void* nmem = nullptr;
     NeutralSoA neu;
+    void* tmem = nullptr;                    // trajectory points (traj_capacity > 0)
+    TrajSoA traj{};
     DevCounters* cnt = nullptr;
     PropParams* d_params = nullptr;          // kernel parameter block (device)
     unsigned long long* scratch = nullptr;   // small device scratch (validation)
 
     int64_t pending = 0;
-    int64_t fin_unread = 0, neu_unread = 0;
+    int64_t fin_unread = 0, neu_unread = 0, traj_unread = 0;
     crp_counters totals;
 
     crp_launch launch;
@@ -86,6 +98,17 @@ struct crp_ctx {
     int64_t last_launches = 0;
 
     NeuralField* nf = nullptr;
+
+    // observable sums (crp_set_observables)
+    bool has_obs = false;
+    crp_observables obs{};
+    void* obs_mem = nullptr;
+    ObsParams obs_p{};
+    size_t obs_sky_n = 0;                    // sky entries
+
+    // galactic lenses (crp_lens_build)
+    Lens lens;
+    bool has_lens = false;
 };
 
 namespace {
@@ -187,6 +210,23 @@ size_t neutral_layout(char* base, int64_t cap, NeutralSoA* n)
     return c.off;
 }
 
+size_t traj_layout(char* base, int64_t cap, TrajSoA* t)
+{
+    Carver c{base};
+    TrajSoA r;
+    r.x = c.take<double>(3 * cap);
+    r.L = c.take<double>(cap);
+    r.E = c.take<double>(cap);
+    r.id = c.take<uint32_t>(cap);
+    r.lineage = c.take<uint32_t>(cap);
+    r.n = c.take<uint32_t>(cap);
+    r.A = c.take<int32_t>(cap);
+    r.cap = cap;
+    if (t)
+        *t = r;
+    return c.off;
+}
+
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 GridView make_view(const crp_ctx* ctx)
@@ -225,20 +265,25 @@ int resident_blocks(int bs, size_t lds)
     hipError_t e;
     if (bs == 128)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 128>, 128, lds);
+            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 128, false>, 128, lds);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 256>, 256, lds);
+            &nbpm, (const void*)k_propagate<MODE, GT, LAYOUT, 256, false>, 256, lds);
     return (e == hipSuccess && nbpm > 0) ? nbpm : 1;
 }
 
+// traj: the variant with the per-step output module (only when it records)
 template <int MODE, class GT, int LAYOUT>
-void launch_propagate(int nb, int bs, size_t lds, hipStream_t s, const PropParams* dp)
+void launch_propagate(int nb, int bs, size_t lds, hipStream_t s, const PropParams* dp, bool traj)
 {
-    if (bs == 128)
-        k_propagate<MODE, GT, LAYOUT, 128><<<nb, 128, lds, s>>>(dp);
+    if (bs == 128 && traj)
+        k_propagate<MODE, GT, LAYOUT, 128, true><<<nb, 128, lds, s>>>(dp);
+    else if (bs == 128)
+        k_propagate<MODE, GT, LAYOUT, 128, false><<<nb, 128, lds, s>>>(dp);
+    else if (traj)
+        k_propagate<MODE, GT, LAYOUT, 256, true><<<nb, 256, lds, s>>>(dp);
     else
-        k_propagate<MODE, GT, LAYOUT, 256><<<nb, 256, lds, s>>>(dp);
+        k_propagate<MODE, GT, LAYOUT, 256, false><<<nb, 256, lds, s>>>(dp);
 }
 
 // Copies [start, start+k) of a planar [3][cap] device array into host [k][3].
@@ -268,21 +313,59 @@ hipError_t copy_d2h(T* host, const T* dev, int64_t k, hipStream_t s)
     return hipMemcpyAsync(host, dev, k * sizeof(T), hipMemcpyDeviceToHost, s);
 }
 
+// Corner records of the base grid and of every refinement patch (built on
+// first use).  A patch's record of cell (i,j,k) holds its vertices i..i+1 etc.;
+// the records of its last vertex planes are built too (from wrapped indices)
+// but never read, since level selection keeps r < n - 1.
 crp_status ensure_corner(crp_ctx* ctx)
 {
-    if (ctx->corner)
-        return CRP_OK;
     if (ctx->grid_dtype != CRP_F32)
         return fail(ctx, CRP_EINVAL, "corner layout needs an FP32 grid");
-    const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
-    if (ncell >= (1ll << 32))
-        return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
-    HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
-    GridView g = make_view(ctx);
-    k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
-    HIPCHK(ctx, hipGetLastError());
+    if (!ctx->corner) {
+        const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
+        if (ncell >= (1ll << 32))
+            return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
+        HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
+        GridView g = make_view(ctx);
+        k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    for (int k = 0; k < ctx->nest.np; ++k) {
+        if (ctx->patch_corner[k])
+            continue;
+        PatchView& q = ctx->nest.p[k];
+        const int64_t ncell = (int64_t)q.n[0] * q.n[1] * q.n[2];
+        HIPCHK(ctx, hipMalloc((void**)&ctx->patch_corner[k], (size_t)ncell * 128));
+        GridView g{};
+        g.data = q.data;
+        for (int a = 0; a < 3; ++a) {
+            g.n[a] = q.n[a];
+            g.mask[a] = is_pow2(q.n[a]) ? q.n[a] - 1 : -1;
+        }
+        g.stride[0] = q.stride[0];
+        g.stride[1] = q.stride[1];
+        g.stride[2] = 3;
+        g.inv_spacing = 1.0;
+        g.dtype = 0;
+        k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->patch_corner[k]);
+        HIPCHK(ctx, hipGetLastError());
+        q.corner = ctx->patch_corner[k];
+    }
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return CRP_OK;
+}
+
+void free_patches(crp_ctx* ctx)
+{
+    for (int k = 0; k < MAX_PATCHES; ++k) {
+        if (ctx->patch_owned[k])
+            (void)hipFree(ctx->patch_owned[k]);
+        ctx->patch_owned[k] = nullptr;
+        if (ctx->patch_corner[k])
+            (void)hipFree(ctx->patch_corner[k]);
+        ctx->patch_corner[k] = nullptr;
+    }
+    ctx->nest = NestView{};
 }
 
 void free_corner(crp_ctx* ctx)
@@ -304,6 +387,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     init.head1 = (unsigned long long)ctx->pending;
     init.fin_n = (unsigned long long)ctx->fin_unread;
     init.neu_n = (unsigned long long)ctx->neu_unread;
+    init.traj_n = (unsigned long long)ctx->traj_unread;
     HIPCHK(ctx, hipMemcpyAsync(ctx->cnt, &init, sizeof init, hipMemcpyHostToDevice, ctx->stream));
 
     PropParams P;
@@ -311,6 +395,7 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.park = ctx->park;
     P.fin = ctx->fin;
     P.neu = ctx->neu;
+    P.traj = ctx->traj;
     P.cnt = ctx->cnt;
     P.grid = make_view(ctx);
     P.tab.e = ctx->tab;
@@ -336,7 +421,10 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     for (int a = 0; a < 3; ++a)
         P.sp.bnd[a] = c.boundary_center[a];
     P.sp.bnd_r = c.boundary_radius;
+    P.sp.traj_every = (uint32_t)c.traj_every;
+    P.sp.traj_ids = c.traj_ids;
     P.ana = ctx->ana;
+    P.nest = ctx->nest;
     P.max_cycles = max_cycles;
     P.tail0 = (unsigned long long)ctx->pending;
     P.fin0 = init.fin_n;
@@ -345,15 +433,19 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     P.refill = c.field_mode == CRP_FIELD_NEURAL ? 1 : ctx->launch.refill;
 
     const bool neural = c.field_mode == CRP_FIELD_NEURAL;
+    const bool traj = c.traj_every > 0;
     if (neural)
         nf_prop_params(ctx->nf, P.grid, &P.nf);
     const bool analytic = c.field_mode == CRP_FIELD_ANALYTIC;
+    // refinement patches: levels selected per lane
+    const bool nested = !neural && !analytic && ctx->nest.np > 0;
     const int layout = ctx->launch.layout;
     if (layout == CRP_LAYOUT_CORNER && !neural && !analytic) {
         crp_status st = ensure_corner(ctx);
         if (st != CRP_OK)
             return st;
         P.grid.corner = ctx->corner;
+        P.nest = ctx->nest;        // now with the patches' corner records
     }
     const int bs = ctx->launch.block;
     const size_t lds = lds_bytes(ctx->tab_n, bs);
@@ -361,7 +453,16 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     const bool f32 = ctx->grid_dtype == CRP_F32;
     int bpc = ctx->launch.blocks_per_cu;
     if (bpc == 0) {   // as many blocks as fit on a compute unit
-        if (analytic)
+        if (nested && f32 && layout == CRP_LAYOUT_CORNER)
+            bpc = mix ? resident_blocks<MODE_MIX, float, 6>(bs, lds)
+                      : resident_blocks<MODE_FP64, float, 6>(bs, lds);
+        else if (nested && f32)
+            bpc = mix ? resident_blocks<MODE_MIX, float, 5>(bs, lds)
+                      : resident_blocks<MODE_FP64, float, 5>(bs, lds);
+        else if (nested)
+            bpc = mix ? resident_blocks<MODE_MIX, double, 5>(bs, lds)
+                      : resident_blocks<MODE_FP64, double, 5>(bs, lds);
+        else if (analytic)
             bpc = mix ? resident_blocks<MODE_MIX, double, 4>(bs, lds)
                       : resident_blocks<MODE_FP64, double, 4>(bs, lds);
         else if (!mix && !f32)
@@ -389,30 +490,47 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
             return fail(ctx, CRP_EINVAL, "neural propagation: tables too large for LDS (n <= 200)");
         static bool attr_set = false;
         if (!attr_set) {
-            HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256>,
+            HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256, false>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)nl));
+            HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256, true>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)nl));
             attr_set = true;
         }
         HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-        k_propagate<MODE_MIX, float, 3, 256><<<ctx->num_cus, 256, nl, s>>>(dp);
+        if (traj)
+            k_propagate<MODE_MIX, float, 3, 256, true><<<ctx->num_cus, 256, nl, s>>>(dp);
+        else
+            k_propagate<MODE_MIX, float, 3, 256, false><<<ctx->num_cus, 256, nl, s>>>(dp);
     } else {
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    if (analytic && mix)
-        launch_propagate<MODE_MIX, double, 4>(nb, bs, lds, s, dp);
+    if (nested && f32 && layout == CRP_LAYOUT_CORNER && mix)
+        launch_propagate<MODE_MIX, float, 6>(nb, bs, lds, s, dp, traj);
+    else if (nested && f32 && layout == CRP_LAYOUT_CORNER)
+        launch_propagate<MODE_FP64, float, 6>(nb, bs, lds, s, dp, traj);
+    else if (nested && f32 && mix)
+        launch_propagate<MODE_MIX, float, 5>(nb, bs, lds, s, dp, traj);
+    else if (nested && f32)
+        launch_propagate<MODE_FP64, float, 5>(nb, bs, lds, s, dp, traj);
+    else if (nested && mix)
+        launch_propagate<MODE_MIX, double, 5>(nb, bs, lds, s, dp, traj);
+    else if (nested)
+        launch_propagate<MODE_FP64, double, 5>(nb, bs, lds, s, dp, traj);
+    else if (analytic && mix)
+        launch_propagate<MODE_MIX, double, 4>(nb, bs, lds, s, dp, traj);
     else if (analytic)
-        launch_propagate<MODE_FP64, double, 4>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_FP64, double, 4>(nb, bs, lds, s, dp, traj);
     else if (!mix && !f32)
-        launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp, traj);
     else if (!mix && layout == CRP_LAYOUT_CORNER)
-        launch_propagate<MODE_FP64, float, 2>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_FP64, float, 2>(nb, bs, lds, s, dp, traj);
     else if (!mix)
-        launch_propagate<MODE_FP64, float, 0>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_FP64, float, 0>(nb, bs, lds, s, dp, traj);
     else if (!f32)
-        launch_propagate<MODE_MIX, double, 0>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_MIX, double, 0>(nb, bs, lds, s, dp, traj);
     else if (layout == CRP_LAYOUT_CORNER)
-        launch_propagate<MODE_MIX, float, 2>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_MIX, float, 2>(nb, bs, lds, s, dp, traj);
     else
-        launch_propagate<MODE_MIX, float, 0>(nb, bs, lds, s, dp);
+        launch_propagate<MODE_MIX, float, 0>(nb, bs, lds, s, dp, traj);
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -434,6 +552,8 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
 {
     ctx->fin_unread = (int64_t)std::min<unsigned long long>(dc.fin_n, ctx->fin.cap);
     ctx->neu_unread = (int64_t)std::min<unsigned long long>(dc.neu_n, ctx->neu.cap);
+    const int64_t traj_before = ctx->traj_unread;
+    ctx->traj_unread = (int64_t)std::min<unsigned long long>(dc.traj_n, ctx->traj.cap);
     if (add_totals) {
         crp_counters& t = ctx->totals;
         t.finished += dc.finished;
@@ -454,6 +574,11 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
         t.neutral_dropped += dc.neutral_dropped;
         t.lane_slots += dc.lane_slots;
         t.boundary += dc.boundary;
+        t.traj_points += ctx->traj_unread - traj_before;
+        // the cursor started at the unread count (within the capacity) and
+        // counted every point; those past the capacity were dropped
+        if (dc.traj_n > (unsigned long long)ctx->traj.cap)
+            t.traj_dropped += (int64_t)(dc.traj_n - (unsigned long long)ctx->traj.cap);
     }
     ctx->pending = (int64_t)dc.park_n;
     if (dc.park_n > 0) {
@@ -484,6 +609,8 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
         !(c.tol > 0) || !(c.hmin > 0) || !(c.hmax >= c.hmin) || !(c.eps_loss > 0) ||
         !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !(c.obs_radius >= 0) ||
         c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40) ||
+        c.traj_every < 0 || c.traj_capacity < 0 || c.traj_capacity > (1ll << 40) ||
+        (c.traj_every > 0 && c.traj_capacity == 0) ||
         (c.field_mode == CRP_FIELD_NEURAL && c.precision != CRP_MIX))
         return CRP_EINVAL;
     crp_ctx* ctx = new (std::nothrow) crp_ctx();
@@ -536,6 +663,13 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
             return bail(CRP_ENOMEM, "neutral-record allocation", e);
         neutral_layout((char*)ctx->nmem, c.neutral_capacity, &ctx->neu);
     }
+    if (c.traj_capacity > 0) {
+        size_t bytes = traj_layout(nullptr, c.traj_capacity, nullptr);
+        e = hipMalloc(&ctx->tmem, bytes);
+        if (e != hipSuccess)
+            return bail(CRP_ENOMEM, "trajectory-point allocation", e);
+        traj_layout((char*)ctx->tmem, c.traj_capacity, &ctx->traj);
+    }
     e = hipMalloc((void**)&ctx->cnt, sizeof(DevCounters));
     if (e != hipSuccess)
         return bail(CRP_ENOMEM, "counter allocation", e);
@@ -564,7 +698,10 @@ void crp_destroy(crp_ctx* ctx)
     else
         (void)hipDeviceSynchronize();
     nf_destroy(ctx->nf);
-    for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, (void*)ctx->cnt,
+    free_patches(ctx);
+    lens_free(ctx->lens);
+    for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, ctx->tmem, ctx->obs_mem,
+                    (void*)ctx->cnt,
                     (void*)ctx->d_params,
                     (void*)ctx->scratch, ctx->grid_owned, (void*)ctx->tab, (void*)ctx->corner})
         if (p)
@@ -613,6 +750,7 @@ crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int
     if (ctx->grid_owned)
         (void)hipFree(ctx->grid_owned);
     free_corner(ctx);
+    free_patches(ctx);
     ctx->grid_owned = owned;
     ctx->grid = ptr;
     ctx->grid_dtype = dtype;
@@ -625,6 +763,65 @@ crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int
     ctx->has_grid = true;
     if (ctx->launch.layout == CRP_LAYOUT_CORNER && dtype != CRP_F32)
         ctx->launch.layout = CRP_LAYOUT_LINEAR;
+    return CRP_OK;
+}
+
+crp_status crp_set_field_patches(crp_ctx* ctx, int32_t n, const crp_grid_patch* patches)
+{
+    if (!ctx || n < 0 || n > MAX_PATCHES || (n > 0 && !patches))
+        return CRP_EINVAL;
+    if (!ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, "patches: set the base grid first");
+    const int64_t lim = 1ll << 20;
+    for (int k = 0; k < n; ++k) {
+        const crp_grid_patch& q = patches[k];
+        if (!q.data || !(q.refine == 2 || q.refine == 4 || q.refine == 8 || q.refine == 16))
+            return fail(ctx, CRP_EINVAL, "patches: null data or refine not in {2, 4, 8, 16}");
+        for (int a = 0; a < 3; ++a)
+            if (q.n[a] < 2 || q.n[a] > lim || q.offset[a] < 0 ||
+                q.offset[a] * q.refine + q.n[a] - 1 > ctx->gn[a] * q.refine)
+                return fail(ctx, CRP_EINVAL,
+                            "patches: each patch needs 2..2^20 vertices per axis and must lie "
+                            "inside one period of the base grid");
+        if (q.n[0] * q.n[1] * q.n[2] >= (1ll << 31) / 3)
+            return fail(ctx, CRP_EINVAL, "patches: at most 2^31/3 - 1 vertices per patch");
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    free_patches(ctx);
+    NestView nv{};
+    const size_t el = ctx->grid_dtype == CRP_F32 ? 4 : 8;
+    for (int k = 0; k < n; ++k) {
+        const crp_grid_patch& q = patches[k];
+        const size_t bytes = (size_t)q.n[0] * q.n[1] * q.n[2] * 3 * el;
+        const void* ptr = q.data;
+        if (!q.on_device) {
+            void* owned = nullptr;
+            hipError_t e = hipMalloc(&owned, bytes);
+            if (e == hipSuccess)
+                e = hipMemcpy(owned, q.data, bytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                if (owned)
+                    (void)hipFree(owned);
+                free_patches(ctx);
+                return fail(ctx, e == hipErrorOutOfMemory ? CRP_ENOMEM : CRP_EDEVICE,
+                            std::string("patch upload: ") + hipGetErrorString(e));
+            }
+            ctx->patch_owned[k] = owned;
+            ptr = owned;
+        }
+        PatchView& v = nv.p[k];
+        v.data = ptr;
+        for (int a = 0; a < 3; ++a) {
+            v.n[a] = (int)q.n[a];
+            v.off[a] = (int)q.offset[a];
+        }
+        v.stride[0] = q.n[1] * q.n[2] * 3;
+        v.stride[1] = q.n[2] * 3;
+        v.refine = (double)q.refine;
+    }
+    nv.np = n;
+    ctx->nest = nv;
     return CRP_OK;
 }
 
@@ -925,6 +1122,274 @@ crp_status crp_read_neutral(crp_ctx* ctx, int64_t cap, const crp_neutral_soa* ou
     return ctx->neu_unread > 0 ? CRP_EOVERFLOW : CRP_OK;
 }
 
+crp_status crp_read_trajectory(crp_ctx* ctx, int64_t cap, const crp_traj_soa* out,
+                               int64_t* n_out)
+{
+    if (!ctx || cap < 0 || !n_out)
+        return CRP_EINVAL;
+    const int64_t k = std::min(cap, ctx->traj_unread);
+    const int64_t s = ctx->traj_unread - k;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    if (out && k > 0) {
+        const TrajSoA& t = ctx->traj;
+        HIPCHK(ctx, copy_d2h(out->id, t.id + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->lineage, t.lineage + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->n, t.n + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->A, t.A + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->L, t.L + s, k, ctx->stream));
+        HIPCHK(ctx, copy_d2h(out->E, t.E + s, k, ctx->stream));
+        if (out->x)
+            HIPCHK(ctx, copy_planar(out->x, t.x, t.cap, s, k, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    ctx->traj_unread -= k;
+    *n_out = k;
+    return ctx->traj_unread > 0 ? CRP_EOVERFLOW : CRP_OK;
+}
+
+// ---- observables ----------------------------------------------------------
+crp_status crp_set_observables(crp_ctx* ctx, const crp_observables* sp)
+{
+    if (!ctx || !sp)
+        return CRP_EINVAL;
+    const crp_observables& o = *sp;
+    if (o.n_e < 1 || o.n_e > OBS_MAX_E || o.n_groups < 1 || o.n_groups > OBS_MAX_G ||
+        o.n_e * o.n_groups > OBS_MAX_BINS || !o.e_edges || !o.a_edges || o.sky_n < 0 ||
+        o.sky_n > 512 || !(o.sky_sign == 1.0 || o.sky_sign == -1.0) || !(o.e_ref > 0) ||
+        !std::isfinite(o.e_ref) || !std::isfinite(o.gamma))
+        return fail(ctx, CRP_EINVAL, "observables: bad bin counts, edges or parameters");
+    for (int i = 0; i <= o.n_e; ++i)
+        if (!std::isfinite(o.e_edges[i]) || (i > 0 && !(o.e_edges[i] > o.e_edges[i - 1])))
+            return fail(ctx, CRP_EINVAL, "observables: energy edges must increase strictly");
+    for (int i = 1; i <= o.n_groups; ++i)
+        if (!(o.a_edges[i] > o.a_edges[i - 1]))
+            return fail(ctx, CRP_EINVAL, "observables: mass edges must increase strictly");
+    const size_t nb = (size_t)o.n_e * (size_t)o.n_groups;
+    const size_t nsky = nb * 6 * (size_t)o.sky_n * (size_t)o.sky_n;
+    if (nsky > ((size_t)1 << 27))
+        return fail(ctx, CRP_EINVAL, "observables: sky map larger than 2^27 entries");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->obs_mem) {
+        (void)hipFree(ctx->obs_mem);
+        ctx->obs_mem = nullptr;
+        ctx->has_obs = false;
+    }
+    Carver c{nullptr};
+    c.take<double>(o.n_e + 1);
+    c.take<int32_t>(o.n_groups + 1);
+    c.take<unsigned long long>(nb);
+    c.take<unsigned long long>(nb);
+    c.take<double>(nb);
+    c.take<unsigned long long>(nsky);
+    c.take<unsigned long long>(1);
+    const size_t bytes = c.off;
+    HIPCHK(ctx, hipMalloc(&ctx->obs_mem, bytes));
+    Carver d{(char*)ctx->obs_mem};
+    ObsParams& p = ctx->obs_p;
+    p = ObsParams{};
+    double* ee = d.take<double>(o.n_e + 1);
+    int32_t* ae = d.take<int32_t>(o.n_groups + 1);
+    p.e_edges = ee;
+    p.a_edges = ae;
+    p.counts = d.take<unsigned long long>(nb);
+    p.defl = d.take<unsigned long long>(nb);
+    p.wsum = d.take<double>(nb);
+    p.sky = d.take<unsigned long long>(nsky);
+    p.outside = d.take<unsigned long long>(1);
+    p.ne = o.n_e;
+    p.ng = o.n_groups;
+    p.sky_n = o.sky_n;
+    p.status_mask = (uint32_t)o.status_mask;
+    p.sky_sign = o.sky_sign;
+    p.e_ref = o.e_ref;
+    p.gamma = o.gamma;
+    HIPCHK(ctx, hipMemsetAsync(ctx->obs_mem, 0, bytes, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ee, o.e_edges, (o.n_e + 1) * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ae, o.a_edges, (o.n_groups + 1) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->obs = o;
+    ctx->obs.e_edges = nullptr;   // the host arrays are not kept
+    ctx->obs.a_edges = nullptr;
+    ctx->obs_sky_n = nsky;
+    ctx->has_obs = true;
+    return CRP_OK;
+}
+
+crp_status crp_observe(crp_ctx* ctx, double* kernel_ms)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!ctx->has_obs)
+        return fail(ctx, CRP_ESTATE, "observe: call crp_set_observables first");
+    if (kernel_ms)
+        *kernel_ms = 0.0;
+    if (ctx->fin_unread == 0)
+        return CRP_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    ObsParams p = ctx->obs_p;
+    const FinishedSoA& f = ctx->fin;
+    p.E = f.E;
+    p.E0 = f.E0;
+    p.u = f.u;
+    p.u0 = f.u0;
+    p.status = f.status;
+    p.A = f.A;
+    p.cap = f.cap;
+    p.n = ctx->fin_unread;
+    // enough blocks for 8 waves per SIMD where the records allow; each block
+    // flushes its LDS bins once
+    const int64_t want = (p.n + 1023) / 1024;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 8));
+    const size_t lds = observe_lds_bytes(p.ne, p.ng);
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    k_observe<<<nb, 256, lds, ctx->stream>>>(p);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (kernel_ms)
+        *kernel_ms = ms;
+    return CRP_OK;
+}
+
+crp_status crp_read_observables(crp_ctx* ctx, uint64_t* counts, double* wsum, uint64_t* defl,
+                                uint64_t* sky, uint64_t* outside)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!ctx->has_obs)
+        return fail(ctx, CRP_ESTATE, "read_observables: call crp_set_observables first");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    const ObsParams& p = ctx->obs_p;
+    const int64_t nb = (int64_t)p.ne * p.ng;
+    HIPCHK(ctx, copy_d2h((unsigned long long*)counts, p.counts, nb, ctx->stream));
+    HIPCHK(ctx, copy_d2h(wsum, p.wsum, nb, ctx->stream));
+    HIPCHK(ctx, copy_d2h((unsigned long long*)defl, p.defl, nb, ctx->stream));
+    HIPCHK(ctx, copy_d2h((unsigned long long*)sky, p.sky, (int64_t)ctx->obs_sky_n, ctx->stream));
+    HIPCHK(ctx, copy_d2h((unsigned long long*)outside, p.outside, 1, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return CRP_OK;
+}
+
+// ---- galactic lenses --------------------------------------------------------
+crp_status crp_lens_build(crp_ctx* ctx, const crp_lens_spec* sp, int64_t* nnz, double* kernel_ms)
+{
+    if (!ctx || !sp || !nnz)
+        return CRP_EINVAL;
+    if (sp->n_r < 1 || sp->n_r > 256 || sp->sky_n < 1 || sp->sky_n > 512 || !sp->r_edges)
+        return fail(ctx, CRP_EINVAL, "lens: 1 <= n_r <= 256, 1 <= sky_n <= 512, edges needed");
+    for (int i = 0; i <= sp->n_r; ++i)
+        if (!std::isfinite(sp->r_edges[i]) || (i > 0 && !(sp->r_edges[i] > sp->r_edges[i - 1])))
+            return fail(ctx, CRP_EINVAL, "lens: rigidity edges must increase strictly");
+    if (ctx->fin_unread > (int64_t)INT32_MAX)
+        return fail(ctx, CRP_EINVAL, "lens: at most 2^31 - 1 records");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    double* edges = nullptr;
+    HIPCHK(ctx, hipMalloc((void**)&edges, (sp->n_r + 1) * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(edges, sp->r_edges, (sp->n_r + 1) * sizeof(double),
+                                  hipMemcpyHostToDevice, ctx->stream);
+    LensKeyParams kp;
+    const FinishedSoA& f = ctx->fin;
+    kp.E0 = f.E0;
+    kp.u = f.u;
+    kp.u0 = f.u0;
+    kp.status = f.status;
+    kp.Z = f.Z;
+    kp.cap = f.cap;
+    kp.n = ctx->fin_unread;
+    kp.r_edges = edges;
+    kp.n_r = sp->n_r;
+    kp.sky_n = sp->sky_n;
+    kp.npix = 6 * sp->sky_n * sp->sky_n;
+    kp.status_mask = (uint32_t)sp->status_mask;
+    ctx->has_lens = false;
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = lens_build(ctx->lens, kp, (int64_t)kp.n_r * kp.npix, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(ctx->ev1);
+    float ms = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    (void)hipFree(edges);
+    if (e != hipSuccess)
+        return fail(ctx, e == hipErrorOutOfMemory ? CRP_ENOMEM : CRP_EDEVICE,
+                    std::string("lens build: ") + hipGetErrorString(e));
+    ctx->has_lens = true;
+    *nnz = ctx->lens.nnz;
+    if (kernel_ms)
+        *kernel_ms = ms;
+    return CRP_OK;
+}
+
+crp_status crp_lens_read(crp_ctx* ctx, int64_t* rowptr, int32_t* col, double* val,
+                         uint64_t* count)
+{
+    if (!ctx)
+        return CRP_EINVAL;
+    if (!ctx->has_lens)
+        return fail(ctx, CRP_ESTATE, "lens_read: no lens built");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    const Lens& L = ctx->lens;
+    HIPCHK(ctx, copy_d2h(rowptr, L.rowptr, L.nrows + 1, ctx->stream));
+    HIPCHK(ctx, copy_d2h(col, L.col, L.nnz, ctx->stream));
+    HIPCHK(ctx, copy_d2h(val, L.val, L.nnz, ctx->stream));
+    HIPCHK(ctx, copy_d2h((unsigned long long*)count, L.count, L.nnz, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return CRP_OK;
+}
+
+crp_status crp_lens_apply(crp_ctx* ctx, int32_t n_maps, const double* x, double* y,
+                          int32_t on_device, double* kernel_ms)
+{
+    if (!ctx || n_maps < 0 || n_maps > 65535 || (n_maps > 0 && (!x || !y)))
+        return CRP_EINVAL;
+    if (!ctx->has_lens)
+        return fail(ctx, CRP_ESTATE, "lens_apply: no lens built");
+    if (kernel_ms)
+        *kernel_ms = 0.0;
+    if (n_maps == 0)
+        return CRP_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    const Lens& L = ctx->lens;
+    const size_t bytes = (size_t)n_maps * (size_t)L.nrows * sizeof(double);
+    const double* dx = x;
+    double* dy = y;
+    void* stage = nullptr;
+    if (!on_device) {
+        HIPCHK(ctx, hipMalloc(&stage, 2 * bytes));
+        dx = (const double*)stage;
+        dy = (double*)((char*)stage + bytes);
+        HIPCHK(ctx, hipMemcpyAsync((void*)dx, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+    }
+    hipError_t e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = lens_apply(L, n_maps, dx, dy, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev1, ctx->stream);
+    if (e == hipSuccess && !on_device)
+        e = hipMemcpyAsync(y, dy, bytes, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    float ms = 0.f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
+    if (stage)
+        (void)hipFree(stage);
+    if (e != hipSuccess)
+        return fail(ctx, CRP_EDEVICE, std::string("lens apply: ") + hipGetErrorString(e));
+    if (kernel_ms)
+        *kernel_ms = ms;
+    return CRP_OK;
+}
+
 crp_status crp_peek_pending(crp_ctx* ctx, int64_t cap, const crp_finished_soa* out,
                             int64_t* n_out)
 {
@@ -967,6 +1432,7 @@ crp_status crp_counts(crp_ctx* ctx, crp_counters* out)
     out->pending = ctx->pending;
     out->finished_unread = ctx->fin_unread;
     out->neutral_unread = ctx->neu_unread;
+    out->traj_unread = ctx->traj_unread;
     return CRP_OK;
 }
 
@@ -1017,7 +1483,13 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
     } else {
         GridView g = make_view(ctx);
         const int md = mode == CRP_MIX ? MODE_MIX : MODE_FP64;
-        if (ctx->grid_dtype == CRP_F64)
+        if (ctx->nest.np > 0 && ctx->grid_dtype == CRP_F64)
+            k_eval_nested<double><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n,
+                                                                               dpos, dB, md);
+        else if (ctx->nest.np > 0)
+            k_eval_nested<float><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n,
+                                                                              dpos, dB, md);
+        else if (ctx->grid_dtype == CRP_F64)
             k_eval_field<double, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
         else if (ctx->launch.layout == CRP_LAYOUT_CORNER && ctx->corner)
             k_eval_field<float, 1><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
@@ -1133,7 +1605,7 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
         }
     }
     const crp_launch orig = ctx->launch;
-    const int64_t fin0 = ctx->fin_unread, neu0 = ctx->neu_unread;
+    const int64_t fin0 = ctx->fin_unread, neu0 = ctx->neu_unread, traj0 = ctx->traj_unread;
     std::vector<crp_launch> cands;
     const bool corner_ok = ctx->grid_dtype == CRP_F32;
     for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
@@ -1161,6 +1633,7 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
             ctx->pending = np;
             ctx->fin_unread = fin0;
             ctx->neu_unread = neu0;
+            ctx->traj_unread = traj0;
             ctx->launch = l;
             DevCounters dc;
             st = run_kernel(ctx, max_cycles, &dc);
@@ -1187,6 +1660,7 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     ctx->pending = np;
     ctx->fin_unread = fin0;
     ctx->neu_unread = neu0;
+    ctx->traj_unread = traj0;
     if (st != CRP_OK) {
         ctx->launch = orig;
         return st;
@@ -1215,10 +1689,10 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
 
 // ---- checkpoint -----------------------------------------------------------
 namespace {
-const uint64_t kMagic = 0x31504b43505243ull;  // "CRPCKP1"
+const uint64_t kMagic = 0x32504b43505243ull;  // "CRPCKP2"
 struct SnapHeader {
     uint64_t magic;
-    int64_t pending, fin_unread, neu_unread;
+    int64_t pending, fin_unread, neu_unread, traj_unread;
     int32_t precision, pad;
     crp_counters totals;
 };
@@ -1261,6 +1735,7 @@ crp_status crp_snapshot(crp_ctx* ctx, void** blob, size_t* bytes)
     h.pending = ctx->pending;
     h.fin_unread = ctx->fin_unread;
     h.neu_unread = ctx->neu_unread;
+    h.traj_unread = ctx->traj_unread;
     h.precision = ctx->cfg.precision;
     h.totals = ctx->totals;
     std::memcpy(b.data(), &h, sizeof h);
@@ -1301,6 +1776,15 @@ crp_status crp_snapshot(crp_ctx* ctx, void** blob, size_t* bytes)
     for (uint32_t* p : {n.id, n.lineage, n.m})
         put(b, p, nn, s);
     put(b, n.chan, nn, s);
+    const TrajSoA& tr = ctx->traj;
+    const int64_t nt = ctx->traj_unread;
+    for (int a = 0; a < 3; ++a)
+        put(b, tr.x + a * tr.cap, nt, s);
+    for (double* p : {tr.L, tr.E})
+        put(b, p, nt, s);
+    for (uint32_t* p : {tr.id, tr.lineage, tr.n})
+        put(b, p, nt, s);
+    put(b, tr.A, nt, s);
     void* mem = std::malloc(b.size());
     if (!mem)
         return fail(ctx, CRP_ENOMEM, "snapshot: host allocation failed");
@@ -1318,7 +1802,8 @@ crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes)
     std::memcpy(&h, blob, sizeof h);
     if (h.magic != kMagic || h.precision != ctx->cfg.precision)
         return fail(ctx, CRP_EINVAL, "restore: not a snapshot of this version / precision");
-    if (h.pending > ctx->q.cap || h.fin_unread > ctx->fin.cap || h.neu_unread > ctx->neu.cap)
+    if (h.pending > ctx->q.cap || h.fin_unread > ctx->fin.cap || h.neu_unread > ctx->neu.cap ||
+        h.traj_unread > ctx->traj.cap || h.traj_unread < 0)
         return fail(ctx, CRP_EINVAL, "restore: snapshot exceeds this context's capacity");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     hipStream_t s = ctx->stream;
@@ -1361,11 +1846,21 @@ crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes)
     for (uint32_t* d : {n.id, n.lineage, n.m})
         ok = ok && get(p, end, d, nn, s);
     ok = ok && get(p, end, n.chan, nn, s);
+    const TrajSoA& tr = ctx->traj;
+    const int64_t nt = h.traj_unread;
+    for (int a = 0; a < 3; ++a)
+        ok = ok && get(p, end, tr.x + a * tr.cap, nt, s);
+    for (double* d : {tr.L, tr.E})
+        ok = ok && get(p, end, d, nt, s);
+    for (uint32_t* d : {tr.id, tr.lineage, tr.n})
+        ok = ok && get(p, end, d, nt, s);
+    ok = ok && get(p, end, tr.A, nt, s);
     if (!ok || p != end)
         return fail(ctx, CRP_EINVAL, "restore: truncated or oversized snapshot");
     ctx->pending = h.pending;
     ctx->fin_unread = h.fin_unread;
     ctx->neu_unread = h.neu_unread;
+    ctx->traj_unread = h.traj_unread;
     ctx->totals = h.totals;
     return CRP_OK;
 }

@@ -57,7 +57,11 @@ def _c_struct_size(decl, name):
                                           ("crp_finished_soa", "FinishedSoA"),
                                           ("crp_neutral_soa", "NeutralSoA"),
                                           ("crp_counters", "Counters"),
-                                          ("crp_analytic_field", "AnalyticField")])
+                                          ("crp_analytic_field", "AnalyticField"),
+                                          ("crp_traj_soa", "TrajSoA"),
+                                          ("crp_observables", "Observables"),
+                                          ("crp_grid_patch", "GridPatch"),
+                                          ("crp_lens_spec", "LensSpec")])
 def test_binding_struct_sizes_match_header(cname, pyname):
     from paper_1307_2643_amd import crp
     assert C.sizeof(getattr(crp, pyname)) == _c_struct_size(HEADER, cname)

@@ -1,0 +1,119 @@
+"""GPU parity of the galactic lenses (section 4: PARSEC-style transformation
+matrices per energy range), through the C-ABI: construction from the records
+of a backtracking run on the GPU against the oracle's construction from its
+own run of the same events (bitwise: integer counts and one FP64 division per
+entry), and the application to border maps against the oracle's sparse
+product (FP64, the order of the sums differs: within (row length + 2) ulp of
+the sum of |terms|)."""
+import numpy as np
+import pytest
+
+import crp_inputs as I
+from oracle import lens as LN
+from parity_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+W = I.W_GALBACK
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_1307_2643_amd import crp
+    crp.load()
+    return crp
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+    oracle.lib()
+    return oracle
+
+
+def backtrack_gpu(P, inj, model=None, precision=0):
+    prm = P.params_for(W, precision, queue_capacity=1 << 16, neutral_capacity=1 << 10)
+    ctx = P.Context(prm)
+    ctx.set_field_analytic(model or I.GALACTIC_FIELD)
+    ctx.set_tables(W.make_tables())
+    ctx.inject(inj)
+    assert ctx.propagate()
+    return ctx
+
+
+@pytest.fixture(scope="module")
+def events(O):
+    inj = W.make_injection(6000)
+    fo, _, _, _ = O.propagate(O.config_for(W), O.AnalyticRef(I.GALACTIC_FIELD),
+                              O.TablesRef(W.make_tables()), inj, nthreads=0)
+    return inj, fo
+
+
+def compare_lens(Lg, Lo, what):
+    assert np.array_equal(Lg["rowptr"], Lo["rowptr"]), what
+    assert np.array_equal(Lg["col"], Lo["col"]), what
+    assert np.array_equal(Lg["count"].astype(np.int64), Lo["count"]), what
+    assert np.array_equal(Lg["val"], Lo["val"]), what
+    say(f"{what}: {len(Lo['col'])} entries bitwise identical")
+
+
+def check_apply(P, ctx, Lo, seed, n_maps=3):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, 1.0, (n_maps, Lo["n_r"], Lo["npix"]))
+    y, ms = ctx.lens_apply(x)
+    ref = LN.apply(Lo, x)
+    # bound of a sum in any order: (terms + 2) ulp of sum |terms| (x >= 0, val > 0)
+    nrow = np.diff(Lo["rowptr"]).reshape(Lo["n_r"], Lo["npix"])
+    tol = (nrow + 2) * 2.0 ** -52 * ref
+    assert np.all(np.abs(y - ref) <= tol + 1e-300)
+    import torch
+    xd = torch.as_tensor(x, device="cuda:0")
+    yd, _ = ctx.lens_apply(xd)
+    assert np.array_equal(yd.cpu().numpy(), y)
+    return ms
+
+
+@pytest.mark.parametrize("sky_n", [2, 8, 24], ids=["long-rows", "mid", "short-rows"])
+def test_lens_build_and_apply_parity(P, O, events, sky_n):
+    inj, fo = events
+    sp = LN.spec(10.0 ** np.linspace(16.5, 20.0, 6), sky_n=sky_n)
+    ctx = backtrack_gpu(P, inj)
+    say(f"lens sky_n={sky_n}")
+    nnz, ms = ctx.lens_build(sp)
+    Lg = ctx.lens_read()
+    assert ctx.counts()["finished_unread"] == len(fo["id"])     # records stay unread
+    Lo = LN.build(sp, fo)
+    assert nnz == len(Lo["col"])
+    compare_lens(Lg, Lo, f"lens sky_n={sky_n}")
+    check_apply(P, ctx, Lo, sky_n)
+    ctx.close()
+
+
+def test_field_free_identity_and_edge_cases(P, O):
+    inj = W.make_injection(1000)
+    zero = {k: (0.0 if k.startswith("b_") else v) for k, v in I.GALACTIC_FIELD.items()}
+    prm = P.params_for(W, P.FP64, queue_capacity=1 << 14, neutral_capacity=1 << 10,
+                       renormalize=0)
+    ctx = P.Context(prm)
+    with pytest.raises(P.CrpError):
+        ctx.lens_read()                                        # nothing built yet
+    ctx.set_field_analytic(zero)
+    ctx.set_tables(W.make_tables())
+    ctx.inject(inj)
+    assert ctx.propagate()
+    sp = LN.spec([1e16, 1e21], sky_n=5)
+    say("lens identity")
+    nnz, _ = ctx.lens_build(sp)
+    L = ctx.lens_read()
+    rows = np.repeat(np.arange(len(L["rowptr"]) - 1), np.diff(L["rowptr"]))
+    assert np.all(L["col"] == rows % L["npix"]) and np.all(L["val"] == 1.0)
+    # a range no record falls in: an empty lens, maps to zero
+    nnz, _ = ctx.lens_build(LN.spec([1e25, 1e26], sky_n=3))
+    assert nnz == 0
+    y, _ = ctx.lens_apply(np.ones((2, 1, 54)))
+    assert np.all(y == 0.0)
+    for bad in (LN.spec([1e18, 1e18], sky_n=2), LN.spec([1e18, 1e19], sky_n=0),
+                LN.spec([1e18, 1e19], sky_n=600)):
+        with pytest.raises(P.CrpError):
+            ctx.lens_build(bad)
+    ctx.close()

@@ -144,3 +144,55 @@ def test_full_batch_sampled_parity(P, O, big, precision):
     same = compare_records(fg, fo, f"1024^3 sample p{precision}")
     assert same.all()
     compare_neutral(_select(neu, ids), no, f"1024^3 sample neutral p{precision}")
+
+
+def test_full_batch_trajectory_and_observables(P, O, big):
+    """The full batch with per-step output for the first 200 candidate ids and
+    the observable reduction over all of its finished records: the points of
+    those candidates (and of their secondaries) against the oracle run on them
+    alone; the reduction against properties that hold at any size."""
+    from oracle import observables as OB
+    n = W.n_candidates
+    ids = 200
+    prm = P.params_for(W, P.MIX, device=0, queue_capacity=2 * n,
+                       neutral_capacity=max(n, 1 << 20), traj_every=1, traj_ids=ids,
+                       traj_capacity=1 << 24)
+    ctx = P.Context(prm)
+    ctx.set_field_grid(big["grid"], W.spacing_m)
+    ctx.set_tables(big["tables"])
+    if big["launch"]:
+        ctx.set_launch(**big["launch"])
+    say(f"full batch with trajectory output of ids < {ids}, launch={ctx.get_launch()}")
+    _inject(ctx, big["d_inj"])
+    assert ctx.propagate(0)
+    sp = OB.spec(10.0 ** np.linspace(15.0, 22.0, 29), a_edges=(1, 2, 5, 15, 57),
+                 status_mask=0b11110, sky_n=32, sky_sign=-1.0, e_ref=1e18, gamma=-1.5)
+    ctx.set_observables(sp)
+    ctx.observe()
+    ob = ctx.read_observables()
+    cnt = ctx.counts()
+    tg = ctx.read_trajectory()
+    ctx.close()
+    assert cnt["traj_dropped"] == 0 and cnt["traj_points"] == len(tg["id"])
+    # observables: every finished record lands in one bin or in `outside`
+    assert int(ob["counts"].sum()) + ob["outside"] == cnt["finished"]
+    assert np.array_equal(ob["sky"].sum(axis=2), ob["counts"])
+    c = ob["counts"].astype(np.float64)
+    nz = c > 0
+    mean = ob["defl"][nz].astype(np.float64) / OB.DEFL_SCALE / c[nz]
+    assert np.all(mean >= 0) and np.all(mean <= np.pi)
+    assert np.all(ob["wsum"][nz] > 0) and np.all(ob["wsum"][~nz] == 0)
+    # trajectory points of the first candidates, bitwise against the oracle
+    sub = big["inj"].subset(np.arange(ids))
+    G = O.GridRef(big["host"], W.spacing_m)
+    T = O.TablesRef(big["tables"])
+    cfg = O.config_for(W, precision=O.MIX, traj_every=1, traj_ids=ids)
+    _, _, _, to = O.propagate_traj(cfg, G, T, sub, 1 << 24,
+                                   nthreads=len(os.sched_getaffinity(0)))
+    tg = P.sort_traj(tg)
+    to = O.sort_traj(to)
+    assert len(tg["id"]) == len(to["id"])
+    for k in to:
+        assert np.array_equal(tg[k], to[k]), k
+    say(f"{len(to['id'])} trajectory points of {ids} candidates bitwise identical; "
+        f"{int(ob['counts'].sum())} records observed in {int(nz.sum())} bins")
