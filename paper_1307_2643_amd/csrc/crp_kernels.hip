@@ -229,12 +229,22 @@ struct DirType<MODE_MIX> {
 #ifndef CRP_WAVES_FP64
 #define CRP_WAVES_FP64 2
 #endif
+// The analytic field has no memory traffic to overlap: its waves hide the
+// latency of FP64 arithmetic instead.
+#ifndef CRP_WAVES_ANALYTIC
+#define CRP_WAVES_ANALYTIC 2
+#endif
+
+template <int MODE, int LAYOUT>
+constexpr int min_waves = LAYOUT == 3   ? 1
+                          : LAYOUT == 4 ? CRP_WAVES_ANALYTIC
+                                        : (MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64);
 
 // TRAJ: the variant with the per-step output module compiled in (a run without
 // trajectory output uses the variant without it, whose loop carries no trace
 // of it).
 template <int MODE, class GT, int LAYOUT, int BS, bool TRAJ>
-__global__ void __launch_bounds__(BS, LAYOUT == 3 ? 1 : (MODE == MODE_MIX ? CRP_WAVES_MIX : CRP_WAVES_FP64))
+__global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
     k_propagate(const PropParams* __restrict__ PP)
 {
     using UT = typename DirType<MODE>::T;   // direction storage: FP64 or FP32

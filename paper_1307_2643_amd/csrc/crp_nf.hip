@@ -431,6 +431,7 @@ struct NeuralField {
     double* loss = nullptr;
     int num_cus = 256;
     bool loaded = false;
+    bool lds_attr_set = false;
 };
 
 static void nf_free_train(NeuralField* nf)
@@ -501,11 +502,11 @@ static NFGeom nf_geom(const NeuralField* nf, const GridView& g)
     return G;
 }
 
-static bool nf_lds_attr_set = false;
-
-static hipError_t nf_set_lds_attr()
+// The dynamic-LDS limit is a per-device function attribute: set once per
+// network object (bound to the device current at its creation).
+static hipError_t nf_set_lds_attr(NeuralField* nf)
 {
-    if (nf_lds_attr_set)
+    if (nf->lds_attr_set)
         return hipSuccess;
     const int bytes = (int)NF_LDS_BYTES;
     hipError_t e = hipFuncSetAttribute((const void*)k_nf_eval,
@@ -516,7 +517,7 @@ static hipError_t nf_set_lds_attr()
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_nf_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 bytes);
-    nf_lds_attr_set = e == hipSuccess;
+    nf->lds_attr_set = e == hipSuccess;
     return e;
 }
 
@@ -545,7 +546,7 @@ crp_status nf_load(NeuralField* nf, const int32_t* freq, const float* params, do
     if (e == hipSuccess)
         e = nf_pack(nf);
     if (e == hipSuccess)
-        e = nf_set_lds_attr();
+        e = nf_set_lds_attr(nf);
     if (e == hipSuccess)
         e = hipStreamSynchronize(nf->stream);
     if (e != hipSuccess) {

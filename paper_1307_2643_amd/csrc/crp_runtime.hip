@@ -98,6 +98,7 @@ struct crp_ctx {
     int64_t last_launches = 0;
 
     NeuralField* nf = nullptr;
+    bool nf_attr_set = false;
 
     // observable sums (crp_set_observables)
     bool has_obs = false;
@@ -488,13 +489,14 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         // the network, the tables and the per-lane state share the CU's LDS
         if (nl + (size_t)256 * (7 * 8 + 7 * 4) + 256 > (size_t)160 * 1024)
             return fail(ctx, CRP_EINVAL, "neural propagation: tables too large for LDS (n <= 200)");
-        static bool attr_set = false;
-        if (!attr_set) {
+        // the dynamic-LDS limit is a per-device function attribute: set it
+        // once per context (each context is bound to one device)
+        if (!ctx->nf_attr_set) {
             HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256, false>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)nl));
             HIPCHK(ctx, hipFuncSetAttribute((const void*)k_propagate<MODE_MIX, float, 3, 256, true>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)nl));
-            attr_set = true;
+            ctx->nf_attr_set = true;
         }
         HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
         if (traj)

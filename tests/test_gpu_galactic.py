@@ -88,3 +88,27 @@ def test_forward_tracking_and_launch_shapes(P, O):
         assert np.array_equal(results[0][0][k], results[1][0][k])
     for k in CNT_KEYS:
         assert results[0][1][k] == results[1][1][k]
+
+
+def test_backtracking_trajectory_points(P, O):
+    """Per-step output of backtracked paths through the analytic field: the
+    points of the first 40 events, every third step and the last, bitwise."""
+    inj = W.make_injection(500)
+    ctx = make(P, P.FP64, traj_every=3, traj_ids=40, traj_capacity=1 << 20)
+    say("galactic trajectory points")
+    ctx.inject(inj)
+    assert ctx.propagate()
+    tg = P.sort_traj(ctx.read_trajectory())
+    cg = ctx.counts()
+    ctx.close()
+    cfg = O.config_for(W, traj_every=3, traj_ids=40)
+    _, _, _, to = O.propagate_traj(cfg, O.AnalyticRef(I.GALACTIC_FIELD),
+                                   O.TablesRef(W.make_tables()), inj, 1 << 20)
+    to = O.sort_traj(to)
+    assert cg["traj_points"] == len(to["id"]) > 1000
+    for k in to:
+        assert np.array_equal(tg[k], to[k]), k
+    # every path ends on or beyond the 20 kpc sphere or at its length limit
+    last = np.r_[np.nonzero(np.diff(tg["id"].astype(np.int64)))[0], len(tg["id"]) - 1]
+    r = np.linalg.norm(tg["x"][last], axis=1)
+    assert np.all((r >= W.boundary_radius_m) | (tg["L"][last] >= W.lmax_m * (1 - 1e-12)))

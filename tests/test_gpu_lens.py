@@ -117,3 +117,51 @@ def test_field_free_identity_and_edge_cases(P, O):
         with pytest.raises(P.CrpError):
             ctx.lens_build(bad)
     ctx.close()
+
+
+def test_full_size_lens_properties(P, O):
+    """The bench's lens set: 1e7 backtracked events (the full galactic batch),
+    7 rigidity bins x 6144 pixels.  Checked by properties that hold at any
+    size, and the first 2000 events' lens against the oracle's."""
+    import torch
+    n = 10_000_000
+    inj = W.make_injection(n)
+    prm = P.params_for(W, P.FP64, queue_capacity=2 * n, neutral_capacity=1 << 10)
+    ctx = P.Context(prm)
+    ctx.set_field_analytic(I.GALACTIC_FIELD)
+    ctx.set_tables(W.make_tables())
+    dev = [torch.as_tensor(a, device="cuda:0") for a in
+           (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+    say("full-size lens: backtracking 1e7 events")
+    ctx.inject(id=dev[0], A=dev[1], Z=dev[2], E=dev[3], pos=dev[4], dir=dev[5], lmax=dev[6],
+               on_device=True)
+    assert ctx.propagate()
+    cnt = ctx.counts()
+    edges = 10.0 ** np.linspace(16.5, 20.0, 8)
+    sp = LN.spec(edges, sky_n=32)
+    nnz, ms = ctx.lens_build(sp)
+    L = ctx.lens_read()
+    say(f"lens: {nnz} entries in {ms:.2f} ms")
+    R = inj.E / inj.Z
+    in_range = (R >= edges[0]) & (R < edges[-1])
+    # every boundary event in range is counted once (events that reach the length
+    # limit instead are not in the lens)
+    assert int(L["count"].sum()) <= int(in_range.sum())
+    assert int(L["count"].sum()) >= int(in_range.sum()) - cnt["max_traj"]
+    rowlen = np.diff(L["rowptr"])
+    rows = np.repeat(np.arange(len(rowlen)), rowlen)
+    assert np.all(np.diff(L["col"])[np.diff(rows) == 0] > 0)          # sorted columns
+    sums = np.bincount(rows, weights=L["val"], minlength=len(rowlen))
+    assert np.all(np.abs(sums[rowlen > 0] - 1.0) <= 4e-16 * rowlen[rowlen > 0])
+    y, _ = ctx.lens_apply(np.ones((1, 7, L["npix"])))
+    assert np.allclose(y.ravel()[rowlen > 0], 1.0, rtol=1e-13) and np.all(y.ravel()[rowlen == 0] == 0)
+    ctx.close()
+    # the first 2000 events alone: the same lens as the oracle's from its own run
+    sub = inj.subset(np.arange(2000))
+    c2 = backtrack_gpu(P, sub)
+    c2.lens_build(sp)
+    Lg = c2.lens_read()
+    c2.close()
+    fo, _, _, _ = O.propagate(O.config_for(W), O.AnalyticRef(I.GALACTIC_FIELD),
+                              O.TablesRef(W.make_tables()), sub, nthreads=0)
+    compare_lens(Lg, LN.build(sp, fo), "first 2000 events")

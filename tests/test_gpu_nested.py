@@ -152,3 +152,25 @@ def test_nested_launch_shapes_device_patches_and_errors(P, O, fields):
     assert np.array_equal(ctx.eval_field(pos, 0),
                           O.eval_field(O.GridRef(b, W.spacing_m), pos, O.FP64))
     ctx.close()
+
+
+def test_nested_trajectory_points(P, O, fields):
+    """Per-step output on the multi-resolution grid from corner records."""
+    base, patches = fields
+    b, ps, G = _grid_pair(O, base, patches, np.float32)
+    inj = W.make_injection(300)
+    ctx = make_ctx(P, W, b, W.make_tables(), P.MIX, traj_every=2, traj_ids=1 << 30,
+                   traj_capacity=1 << 20)
+    ctx.set_field_patches(ps)
+    ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=P.LAYOUT_CORNER)
+    say("nested trajectory points")
+    ctx.inject(inj)
+    assert ctx.propagate()
+    tg = P.sort_traj(ctx.read_trajectory())
+    ctx.close()
+    cfg = O.config_for(W, precision=O.MIX, traj_every=2, traj_ids=1 << 30)
+    _, _, _, to = O.propagate_traj(cfg, G, O.TablesRef(W.make_tables()), inj, 1 << 20)
+    to = O.sort_traj(to)
+    assert len(tg["id"]) == len(to["id"])
+    for k in to:
+        assert np.array_equal(tg[k], to[k]), k

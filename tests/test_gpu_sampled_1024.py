@@ -196,3 +196,44 @@ def test_full_batch_trajectory_and_observables(P, O, big):
         assert np.array_equal(tg[k], to[k]), k
     say(f"{len(to['id'])} trajectory points of {ids} candidates bitwise identical; "
         f"{int(ob['counts'].sum())} records observed in {int(nz.sum())} bins")
+
+
+def test_full_batch_multiresolution_sampled_parity(P, O, big):
+    """The bench's multi-resolution case: the 1e7 batch started at the centre
+    of a 512^3 refine-4 patch inside the 1024^3 grid, corner records for both
+    levels, against the oracle on 200 sampled candidates with all their
+    secondaries."""
+    import torch
+    n = W.n_candidates
+    nside, refine, off = 512, 4, 448
+    say("generating the 512^3 patch on the GPU")
+    patch = I.turbulent_grid(nside, W.spacing_m / refine, 2.0, 64.0, W.brms_T, 31, np.float32,
+                             device="cuda:0")
+    torch.cuda.synchronize()
+    centre = (off + nside / refine / 2) * W.spacing_m
+    inj = big["inj"]
+    pos = np.full((n, 3), centre)
+    d = big["d_inj"]
+    ctx = _context(P, big, P.MIX)
+    ctx.set_field_patches([dict(data=patch, offset=(off, off, off), refine=refine)])
+    ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=P.LAYOUT_CORNER)
+    dpos = torch.as_tensor(pos, device="cuda:0")
+    say("full batch from the patch centre")
+    ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=dpos, dir=d[5], lmax=d[6], on_device=True)
+    assert ctx.propagate(0)
+    fin = ctx.read_finished()
+    cnt = ctx.counts()
+    ctx.close()
+    host_patch = patch.cpu().numpy()
+    del patch, dpos
+    torch.cuda.empty_cache()
+    assert cnt["finished"] == len(fin["id"]) == n + cnt["charged_sec"]
+    ids = np.random.default_rng(4343).choice(n, 200, replace=False)
+    sub = I.Injection(inj.id[ids], inj.A[ids], inj.Z[ids], inj.E[ids], pos[ids], inj.dir[ids],
+                      inj.lmax[ids])
+    G = O.GridRef(big["host"], W.spacing_m,
+                  patches=[dict(data=host_patch, offset=(off, off, off), refine=refine)])
+    fo, _, _, _ = O.propagate(O.config_for(W, precision=O.MIX), G, O.TablesRef(big["tables"]),
+                              sub, nthreads=len(os.sched_getaffinity(0)))
+    same = compare_records(_select(fin, ids), fo, "multi-resolution 1024^3 sample")
+    assert same.all()
