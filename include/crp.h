@@ -395,8 +395,10 @@ crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches);
  * or iters < 1. */
 crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s);
 
-/* Checkpoint: pending candidates, undrained records and counters.  The blob
- * is allocated by the library and released with crp_free. */
+/* Checkpoint: pending candidates, undrained finished / neutral records,
+ * unread trajectory points and counters (not the observable sums or lenses,
+ * which are rebuilt from records).  The blob is allocated by the library and
+ * released with crp_free; a blob of an earlier layout is rejected. */
 crp_status crp_snapshot(crp_ctx* ctx, void** blob, size_t* bytes);
 crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes);
 void crp_free(void* p);

@@ -438,6 +438,8 @@ class Context:
         return ms.value
 
     def read_observables(self):
+        if getattr(self, "_obs_shape", None) is None:      # the library reports the state
+            self._check(self.L.crp_read_observables(self.h, None, None, None, None, None))
         ng, ne, npix = self._obs_shape
         out = dict(counts=np.zeros((ng, ne), np.uint64), wsum=np.zeros((ng, ne)),
                    defl=np.zeros((ng, ne), np.uint64), sky=np.zeros((ng, ne, npix), np.uint64))
@@ -461,6 +463,8 @@ class Context:
         return nnz.value, ms.value
 
     def lens_read(self):
+        if getattr(self, "_lens_shape", None) is None:     # the library reports the state
+            self._check(self.L.crp_lens_read(self.h, None, None, None, None))
         nr, npix, nnz = self._lens_shape
         out = dict(rowptr=np.zeros(nr * npix + 1, np.int64), col=np.zeros(nnz, np.int32),
                    val=np.zeros(nnz), count=np.zeros(nnz, np.uint64))

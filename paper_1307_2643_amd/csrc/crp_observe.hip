@@ -162,7 +162,8 @@ __global__ void __launch_bounds__(256) k_observe(ObsParams p)
             const double ns = obs_norm(a0 + b0, a1 + b1, a2 + b2);
             const double ang = 2.0 * atan2(nd, ns);
             const unsigned long long fx = (unsigned long long)floor(ang * 4294967296.0);
-            const double wt = pow(E0[j] / p.e_ref, p.gamma);
+            // x^0 = 1 for every x: no power function for an unweighted spectrum
+            const double wt = p.gamma == 0.0 ? 1.0 : pow(E0[j] / p.e_ref, p.gamma);
             atomicAdd(&cnt[b], 1ull);
             atomicAdd(&dfl[b], fx);
             atomicAdd(&ws[b], wt);
