@@ -477,10 +477,12 @@ def nested_variant(args, crp, I, torch, w, n, grid, tables, stream, inj):
 
 
 # FP64 operations of one Cash-Karp attempt of the FP64 method with the analytic
-# field: 6 field evaluations x 44 (3 differences, 3 for r^2, 1 for z^2, 7 disk,
-# 2 + 8 halo, 1, 4 + 1 for D and D^2, 3 for q, 3 + 3 + 5 for B) plus the stages:
-# 6 x 12 derivative, 210 stage sums, 54 fifth-order sum, 34 error estimate.
-ANALYTIC_FLOP_PER_ATTEMPT = 6 * 44 + 6 * 12 + 210 + 54 + 34
+# field: 6 field evaluations x 47 (3 differences, 3 for r^2, 1 for z^2, 6 for the
+# disk denominator X, 2 + 5 for the halo denominator Y, 7 for g including its
+# division, 4 for D, 1 + 1 for 1/D and its square, 3 for q, 3 + 3 + 5 for B)
+# plus the stages: 6 x 12 derivative, 210 stage sums, 54 fifth-order sum, 34
+# error estimate.
+ANALYTIC_FLOP_PER_ATTEMPT = 6 * 47 + 6 * 12 + 210 + 54 + 34
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 

@@ -86,8 +86,10 @@ static void axis_cell(const or_grid* g, int a, double p, int64_t idx[2], double*
 
 /* Analytic galactic field (model in crp_oracle.h), FP64 in the order written:
  * derived constants first, then the toroidal factor g with B_t = g (-y, x, 0),
- * then the X-field B_x = x q, B_y = y q, B_z = b_x / D - b_x r^2 / (r_x^2 D^2)
- * with q = b_x z / (h_x^2 D^2). */
+ * g = b_disk / X + b_halo (z/h_halo) / Y over the common denominator X Y
+ * (X, Y the disk and halo denominators), then the X-field with one reciprocal
+ * iD = 1/D: B_x = x q, B_y = y q, B_z = b_x iD - b_x (r^2/r_x^2) iD^2,
+ * q = b_x (z/h_x^2) iD^2.  Two divisions per evaluation. */
 static void field_analytic(const or_analytic* a, const double p[3], double B[3])
 {
     double kd = 1.0 / (a->r_disk * a->r_disk), ld = 1.0 / (a->h_disk * a->h_disk);
@@ -97,16 +99,17 @@ static void field_analytic(const or_analytic* a, const double p[3], double B[3])
     double dx = p[0] - a->center[0], dy = p[1] - a->center[1], dz = p[2] - a->center[2];
     double r2 = dx * dx + dy * dy;
     double z2 = dz * dz;
-    double gd = a->b_disk / ((a->r_disk * (1.0 + r2 * kd)) * (1.0 + z2 * ld));
+    double X = (a->r_disk * (1.0 + r2 * kd)) * (1.0 + z2 * ld);
     double wh = 1.0 + z2 * lh;
-    double gh = (a->b_halo * (dz * ih)) / ((a->r_halo * (1.0 + r2 * kh)) * (wh * wh));
-    double g = gd + gh;
+    double Y = (a->r_halo * (1.0 + r2 * kh)) * (wh * wh);
+    double g = (a->b_disk * Y + (a->b_halo * (dz * ih)) * X) / (X * Y);
     double D = (1.0 + r2 * kx) + z2 * lx;
-    double D2 = D * D;
-    double q = (a->b_x * (dz * lx)) / D2;
+    double iD = 1.0 / D;
+    double iD2 = iD * iD;
+    double q = (a->b_x * (dz * lx)) * iD2;
     B[0] = (-g) * dy + dx * q;
     B[1] = g * dx + dy * q;
-    B[2] = a->b_x / D - (a->b_x * (r2 * kx)) / D2;
+    B[2] = a->b_x * iD - (a->b_x * (r2 * kx)) * iD2;
 }
 
 /* Multi-resolution grid: the cell that holds position p.  The base cell

@@ -685,16 +685,19 @@ struct AnalyticFieldSrc {
         const double dx = p[0] - a.center[0], dy = p[1] - a.center[1], dz = p[2] - a.center[2];
         const double r2 = dx * dx + dy * dy;
         const double z2 = dz * dz;
-        const double gd = a.b_disk / ((a.r_disk * (1.0 + r2 * a.kd)) * (1.0 + z2 * a.ld));
+        // two divisions: g over the common denominator of its disk and halo
+        // parts, and one reciprocal of D for the X-field
+        const double X = (a.r_disk * (1.0 + r2 * a.kd)) * (1.0 + z2 * a.ld);
         const double wh = 1.0 + z2 * a.lh;
-        const double gh = (a.b_halo * (dz * a.ih)) / ((a.r_halo * (1.0 + r2 * a.kh)) * (wh * wh));
-        const double g = gd + gh;
+        const double Y = (a.r_halo * (1.0 + r2 * a.kh)) * (wh * wh);
+        const double g = (a.b_disk * Y + (a.b_halo * (dz * a.ih)) * X) / (X * Y);
         const double D = (1.0 + r2 * a.kx) + z2 * a.lx;
-        const double D2 = D * D;
-        const double q = (a.b_x * (dz * a.lx)) / D2;
+        const double iD = 1.0 / D;
+        const double iD2 = iD * iD;
+        const double q = (a.b_x * (dz * a.lx)) * iD2;
         B[0] = (-g) * dy + dx * q;
         B[1] = g * dx + dy * q;
-        B[2] = a.b_x / D - (a.b_x * (r2 * a.kx)) / D2;
+        B[2] = a.b_x * iD - (a.b_x * (r2 * a.kx)) * iD2;
     }
     __device__ inline void fp32(const double p[3], float B[3], bool need = true) const
     {
