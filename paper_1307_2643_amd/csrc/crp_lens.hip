@@ -9,8 +9,9 @@
 // and an integer sum per row the normalisation.
 //
 // Application: a sparse matrix times border maps, one group of LPR lanes per
-// row (LPR chosen from the mean row length), the group's partial sums combined
-// by lane shuffles.  HBM-bound: the matrix is streamed once per map.
+// row (LPR chosen from the mean row length), four maps per pass, the group's
+// partial sums combined by lane shuffles.  HBM-bound: the matrix is streamed
+// once per four maps.
 #include <hipcub/hipcub.hpp>
 
 #include "crp_lens.hpp"
@@ -129,29 +130,48 @@ __global__ void k_lens_values(const unsigned long long* ukeys, const uint32_t* c
     count[e] = counts[e];
 }
 
-// y[m][row] = sum over the row's entries of val * x[m][r Np + col], row = r Np + i.
+// y[m][row] = sum over the row's entries of val * x[m][r Np + col], row = r Np + i,
+// for LENS_MAPS maps m0, m0 + 1, ... at once (blockIdx.y = m0 / LENS_MAPS): the
+// row's columns and values are read once for all of them.  Every map's sum
+// has the same order whatever the number of maps applied together.
+constexpr int LENS_MAPS = 4;
+
 template <int LPR>
 __global__ void __launch_bounds__(256) k_lens_apply(LensApplyParams p)
 {
     const int lane = (int)(threadIdx.x & 63u);
     const int sub = lane & (LPR - 1);
     const int64_t group = ((int64_t)blockIdx.x * 256 + threadIdx.x) / LPR;
-    const int64_t m = blockIdx.y;
+    const int64_t m0 = (int64_t)blockIdx.y * LENS_MAPS;
+    const int nm = (int)(p.n_maps - m0 < LENS_MAPS ? p.n_maps - m0 : LENS_MAPS);
     const bool live = group < p.nrows;
     const int64_t row = live ? group : 0;
     const int64_t base = (row / p.npix) * p.npix;     // first column of this rigidity's block
-    const double* x = p.x + m * p.map_len + base;
-    double acc = 0.0;
+    const double* x = p.x + m0 * p.map_len + base;
+    double acc[LENS_MAPS] = {0.0, 0.0, 0.0, 0.0};
     if (live) {
         const int64_t e1 = p.rowptr[row + 1];
-        for (int64_t e = p.rowptr[row] + sub; e < e1; e += LPR)
-            acc += p.val[e] * x[p.col[e]];
+        for (int64_t e = p.rowptr[row] + sub; e < e1; e += LPR) {
+            const double v = p.val[e];
+            const int64_t c = p.col[e];
+#pragma unroll
+            for (int k = 0; k < LENS_MAPS; ++k)
+                if (k < nm)
+                    acc[k] += v * x[k * p.map_len + c];
+        }
     }
 #pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1)
-        acc += __shfl_xor(acc, o, LPR);
-    if (live && sub == 0)
-        p.y[m * p.map_len + row] = acc;
+    for (int k = 0; k < LENS_MAPS; ++k) {
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1)
+            acc[k] += __shfl_xor(acc[k], o, LPR);
+    }
+    if (live && sub == 0) {
+#pragma unroll
+        for (int k = 0; k < LENS_MAPS; ++k)
+            if (k < nm)
+                p.y[(m0 + k) * p.map_len + row] = acc[k];
+    }
 }
 
 template __global__ void k_lens_apply<4>(LensApplyParams);
@@ -262,7 +282,9 @@ hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hip
     p.nrows = L.nrows;
     p.npix = L.npix;
     p.map_len = L.nrows;
-    const dim3 grid((unsigned)((L.nrows * L.lpr + 255) / 256), (unsigned)n_maps);
+    p.n_maps = n_maps;
+    const dim3 grid((unsigned)((L.nrows * L.lpr + 255) / 256),
+                    (unsigned)((n_maps + LENS_MAPS - 1) / LENS_MAPS));
     switch (L.lpr) {
     case 4: k_lens_apply<4><<<grid, 256, 0, s>>>(p); break;
     case 8: k_lens_apply<8><<<grid, 256, 0, s>>>(p); break;

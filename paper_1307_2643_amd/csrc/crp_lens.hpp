@@ -38,6 +38,7 @@ struct LensApplyParams {
     double* y;                          // [n_maps][nrows]
     int64_t nrows, map_len;
     int64_t npix;
+    int64_t n_maps;
 };
 
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s);
