@@ -423,7 +423,23 @@ def outputs_variant(args, crp, w, n, context, inject, launch, headline):
     gbs = obytes / (oms * 1e-3) / 1e9
     log(f"[bench] observables over {nrec} records: {oms:.3f} ms, {gbs:.0f} GB/s algorithmic")
     ctx.close()
-    obs = {"records": nrec, "selected": nsel, "kernel_ms": oms,
+    oracle = None
+    if not args.no_cpu:
+        # the oracle's reduction on a bounded synthetic sample of records
+        from oracle import observables as OB
+        m = 1_000_000
+        rng = np.random.default_rng(72)
+        recs = dict(status=rng.integers(1, 5, m).astype(np.int32),
+                    A=rng.choice([1, 4, 14, 56], m).astype(np.int32),
+                    E=10.0 ** rng.uniform(16.0, 22.0, m), E0=10.0 ** rng.uniform(18.0, 21.0, m),
+                    u=rng.standard_normal((m, 3)), u0=rng.standard_normal((m, 3)))
+        sp = dict(spec, e_edges=np.asarray(edges), a_edges=np.asarray(spec["a_edges"]))
+        t0 = time.perf_counter()
+        OB.observe(sp, recs)
+        t1 = time.perf_counter() - t0
+        oracle = {"records_per_s": m / t1, "cores": 1, "sample": f"{m} synthetic records"}
+        log(f"[bench] observables oracle: {m / t1:.3e} records/s (one core)")
+    obs = {"records": nrec, "selected": nsel, "kernel_ms": oms, "oracle": oracle,
            "bins": int(ob["counts"].size), "sky_pixels": int(ob["sky"].shape[-1]),
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": obytes}}
@@ -471,6 +487,23 @@ def nested_variant(args, crp, I, torch, w, n, grid, tables, stream, inj):
                      "attempts": cnt["attempts"], "algorithmic_GBps": gbs,
                      "hbm_frac": gbs / HBM_PEAK_GBS}
         log(f"[bench] {name}: {rate:.4e} steps/s, kernel {ms:.1f} ms, {gbs:.0f} GB/s algorithmic")
+    if not args.no_cpu:
+        # the oracle on the first candidates of the same batch, both levels on the host
+        from oracle import oracle as O
+        m = 64
+        G = O.GridRef(grid.cpu().numpy(), w.spacing_m,
+                      patches=[dict(data=patch.cpu().numpy(), offset=(off, off, off),
+                                    refine=refine)])
+        sub = I.Injection(inj.id[:m], inj.A[:m], inj.Z[:m], inj.E[:m],
+                          np.full((m, 3), centre), inj.dir[:m], inj.lmax[:m])
+        t1 = time.perf_counter()
+        _, _, co, used = O.propagate(O.config_for(w, precision=O.MIX), G, O.TablesRef(tables),
+                                     sub, nthreads=len(os.sched_getaffinity(0)))
+        tc = time.perf_counter() - t1
+        out["oracle"] = {"steps_per_s": co["steps"] / tc, "cores": used,
+                         "sample": f"first {m} candidates of the batch, precision form"}
+        log(f"[bench] nested oracle: {co['steps'] / tc:.3e} steps/s on {used} threads")
+        del G
     del patch, pos, d
     torch.cuda.empty_cache()
     return out
@@ -533,14 +566,30 @@ def galactic_variant(args, crp, I, torch, stream):
         from oracle import oracle as O
         m = 20000
         t0 = time.perf_counter()
-        _, _, co, used = O.propagate(O.config_for(w), O.AnalyticRef(I.GALACTIC_FIELD),
-                                     O.TablesRef(w.make_tables()), inj.subset(slice(0, m)),
-                                     nthreads=len(os.sched_getaffinity(0)))
+        fo, _, co, used = O.propagate(O.config_for(w), O.AnalyticRef(I.GALACTIC_FIELD),
+                                      O.TablesRef(w.make_tables()), inj.subset(slice(0, m)),
+                                      nthreads=len(os.sched_getaffinity(0)))
         t1 = time.perf_counter() - t0
         out["oracle"] = {"steps_per_s": co["steps"] / t1, "cores": used,
                          "sample": f"first {m} events, FP64"}
         log(f"[bench] galactic backtracking oracle: {co['steps'] / t1:.3e} steps/s on {used} "
             f"threads")
+        if "lens" in out:
+            # the oracle's lens construction and application on its own records
+            from oracle import lens as LN
+            sp = LN.spec(10.0 ** np.linspace(16.5, 20.0, 8), sky_n=32)
+            t0 = time.perf_counter()
+            L = LN.build(sp, fo)
+            tb = time.perf_counter() - t0
+            x = np.random.default_rng(71).uniform(0.0, 1.0, (16, 7, 6144))
+            t0 = time.perf_counter()
+            LN.apply(L, x)
+            ta = time.perf_counter() - t0
+            out["lens"]["oracle"] = {"build_records_per_s": len(fo["id"]) / tb,
+                                     "apply_entries_per_s": 16 * len(L["col"]) / ta,
+                                     "cores": 1, "sample": f"the oracle's {m} events"}
+            log(f"[bench] lens oracle: build {len(fo['id']) / tb:.3e} records/s, apply "
+                f"{16 * len(L['col']) / ta:.3e} entries/s (one core)")
     return out
 
 
