@@ -14,6 +14,12 @@
  * Everything the paper leaves open (integrator, interpolation, controller,
  * tables, random stream) follows the readings listed with each function.
  *
+ * Parity unpinned: the synthetic interaction channels (which nucleon leaves,
+ * the pion-like energy fraction, the secondary's inherited state) and the
+ * species scaling of the per-nucleon rates have no physical values to match;
+ * the tests check them only for internal consistency (bookkeeping invariants,
+ * branching fractions, energy accounting).
+ *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no -ffast-math,
  * no FMA contraction) so every FP64 operation is one correctly rounded IEEE
  * operation in the order written.
