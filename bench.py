@@ -763,7 +763,7 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
     train_s = time.perf_counter() - t0
     log(f"[bench] NF trained on {args.nf_steps * 65536:.3g} points in {train_s:.1f}s, "
         f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
-    # field error on held-out points (the grid path is the judge)
+    # field error on held-out points (the grid path is the reference)
     box = wd.grid_n * wd.spacing_m
     pos = I.uniform_points(1_000_000, box, 507)
     Bn = cnf.eval_field(pos, crp.EVAL_NEURAL)
