@@ -79,6 +79,16 @@ def _sample_ids(n):
     return np.unique(np.concatenate([ids, np.arange(4), np.arange(n - 4, n)]))
 
 
+def _digest(P, fin):
+    """SHA-256 of every field of the records in (id, lineage) order."""
+    import hashlib
+    f = P.sort_finished(fin)
+    h = hashlib.sha256()
+    for k in sorted(f):
+        h.update(np.ascontiguousarray(f[k]).tobytes())
+    return h.hexdigest()
+
+
 def _select(rec, ids):
     keep = np.isin(rec["id"], ids)
     return {k: v[keep] for k, v in rec.items()}
@@ -131,6 +141,8 @@ def test_full_batch_sampled_parity(P, O, big, precision):
     ctx.close()
     say(f"gpu: {len(fin['id'])} finished, {len(neu['id'])} neutral, {cnt['steps']} steps")
     _check_whole_batch(P, fin, neu, cnt, n)
+    big[f"digest{precision}"] = (_digest(P, fin), {k: cnt[k] for k in
+                                                   ("steps", "attempts", "finished", "events")})
 
     ids = _sample_ids(n)
     sub = big["inj"].subset(ids)
@@ -237,3 +249,31 @@ def test_full_batch_multiresolution_sampled_parity(P, O, big):
                               sub, nthreads=len(os.sched_getaffinity(0)))
     same = compare_records(_select(fin, ids), fo, "multi-resolution 1024^3 sample")
     assert same.all()
+
+
+def test_batch_split_invariance_full_size(P, big):
+    """The same 1e7 candidates injected and propagated as 10 batches of 1e6 in
+    one context give bitwise the same records as the single 1e7 launch (each
+    candidate's history depends only on its own inputs and random stream)."""
+    if "digest1" not in big:
+        pytest.skip("needs the full-batch precision-form run of this module")
+    n = W.n_candidates
+    ctx = _context(P, big, P.MIX)
+    if big["launch"]:
+        ctx.set_launch(**big["launch"])
+    d = big["d_inj"]
+    parts = []
+    for b in range(10):
+        s = slice(b * n // 10, (b + 1) * n // 10)
+        say(f"batch {b}: candidates {s.start}..{s.stop}")
+        ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
+                   lmax=d[6][s], on_device=True)
+        assert ctx.propagate(0)
+        parts.append(ctx.read_finished())
+    cnt = ctx.counts()
+    ctx.close()
+    fin = {k: np.concatenate([p[k] for p in parts]) for k in parts[0]}
+    digest, ref_cnt = big["digest1"]
+    for k, v in ref_cnt.items():
+        assert cnt[k] == v, k
+    assert _digest(P, fin) == digest
