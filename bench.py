@@ -229,7 +229,7 @@ def main():
             f"algorithmic ({rec_s * 128 / 1e9:.0f} GB/s in 128-byte lines)")
 
     # ---- sample for the stated error: MIX (GPU) vs FP64 oracle --------------
-    nsample = 0 if args.no_sample else min(n, 2000)
+    nsample = 0 if args.no_sample else min(n, 10_000)   # the 1e4-candidate error subset
     horizon = 16
     if nsample:
         ctx.reset_counters()
