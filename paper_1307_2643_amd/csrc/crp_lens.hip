@@ -51,13 +51,14 @@ __device__ inline int64_t lens_pixel(double v0, double v1, double v2, int n)
     return (face * n + (int64_t)fi) * n + (int64_t)fj;
 }
 
-// Key (r Np + i) Np + j of every record, or LENS_NO_KEY if it takes no part.
+// Key (r Np + i) Np + j of every record, or no_key (one past the largest) if
+// it takes no part, so that the sort needs only the key's significant bits.
 __global__ void k_lens_keys(LensKeyParams p, unsigned long long* keys)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= p.n)
         return;
-    unsigned long long key = LENS_NO_KEY;
+    unsigned long long key = p.no_key;
     const int32_t st = p.status[k];
     if (st >= 0 && st <= 31 && ((p.status_mask >> st) & 1u) != 0u) {
         const double R = p.E0[k] / (double)p.Z[k];
@@ -84,7 +85,7 @@ __global__ void k_lens_keys(LensKeyParams p, unsigned long long* keys)
 }
 
 // Row pointers: the first entry whose key is at least row * Np (entries are
-// sorted); entries past nvalid hold the no-key marker.  Then each row's total
+// sorted); an entry past nvalid holds the no-key marker.  Then each row's total
 // count and every entry's column and value.
 __global__ void k_lens_rows(const unsigned long long* ukeys, int64_t nvalid, int64_t nrows,
                             int npix, int64_t* rowptr)
@@ -186,6 +187,42 @@ namespace {
 int blocks(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 }
 
+// Carves the construction buffers out of the lens's grow-only scratch.
+static hipError_t lens_scratch(Lens& L, int64_t n, size_t tmp_bytes, int64_t nrows,
+                               unsigned long long** keys, unsigned long long** sorted,
+                               unsigned long long** ukeys, uint32_t** counts, int64_t** nruns,
+                               unsigned long long** tot, void** tmp)
+{
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_keys = up(n * sizeof(unsigned long long));
+    const size_t b_counts = up(n * sizeof(uint32_t));
+    const size_t b_nruns = up(sizeof(int64_t));
+    const size_t b_tot = up(nrows * sizeof(unsigned long long));
+    const size_t need = 3 * b_keys + b_counts + b_nruns + b_tot + up(tmp_bytes);
+    if (need > L.scratch_bytes) {
+        lens_free_scratch(L);
+        hipError_t e = hipMalloc(&L.scratch, need);
+        if (e != hipSuccess)
+            return e;
+        L.scratch_bytes = need;
+    }
+    char* p = (char*)L.scratch;
+    *keys = (unsigned long long*)p;
+    p += b_keys;
+    *sorted = (unsigned long long*)p;
+    p += b_keys;
+    *ukeys = (unsigned long long*)p;
+    p += b_keys;
+    *counts = (uint32_t*)p;
+    p += b_counts;
+    *nruns = (int64_t*)p;
+    p += b_nruns;
+    *tot = (unsigned long long*)p;
+    p += b_tot;
+    *tmp = (void*)p;
+    return hipSuccess;
+}
+
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s)
 {
     lens_free(L);
@@ -194,16 +231,7 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
     L.npix = kp.npix;
     L.n_r = kp.n_r;
     hipError_t e = hipSuccess;
-    unsigned long long *keys = nullptr, *sorted = nullptr, *ukeys = nullptr, *tot = nullptr;
-    uint32_t* counts = nullptr;
-    int64_t* nruns_d = nullptr;
-    void* tmp = nullptr;
-    size_t tmp_sort = 0, tmp_rle = 0;
     auto done = [&](hipError_t r) {
-        for (void* q : {(void*)keys, (void*)sorted, (void*)ukeys, (void*)counts,
-                        (void*)nruns_d, tmp, (void*)tot})
-            if (q)
-                (void)hipFree(q);
         if (r != hipSuccess)
             lens_free(L);
         return r;
@@ -221,18 +249,25 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
         L.nnz = 0;
         return done(hipSuccess);
     }
-    LCHK(hipMalloc(&keys, n * sizeof(unsigned long long)));
-    LCHK(hipMalloc(&sorted, n * sizeof(unsigned long long)));
-    LCHK(hipMalloc(&ukeys, n * sizeof(unsigned long long)));
-    LCHK(hipMalloc(&counts, n * sizeof(uint32_t)));
-    LCHK(hipMalloc(&nruns_d, sizeof(int64_t)));
+    // the sort needs the bits of the largest key (no_key) only
+    int nbits = 1;
+    while (nbits < 64 && (kp.no_key >> nbits) != 0ull)
+        ++nbits;
+    size_t tmp_sort = 0, tmp_rle = 0;
+    LCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_sort, (unsigned long long*)nullptr,
+                                           (unsigned long long*)nullptr, (int)n, 0, nbits, s));
+    LCHK(hipcub::DeviceRunLengthEncode::Encode(nullptr, tmp_rle, (unsigned long long*)nullptr,
+                                               (unsigned long long*)nullptr, (uint32_t*)nullptr,
+                                               (int64_t*)nullptr, (int)n, s));
+    size_t tmp_bytes = std::max(tmp_sort, tmp_rle);
+    unsigned long long *keys, *sorted, *ukeys, *tot;
+    uint32_t* counts;
+    int64_t* nruns_d;
+    void* tmp;
+    LCHK(lens_scratch(L, n, tmp_bytes, nrows, &keys, &sorted, &ukeys, &counts, &nruns_d, &tot,
+                      &tmp));
     k_lens_keys<<<blocks(n, 256), 256, 0, s>>>(kp, keys);
     LCHK(hipGetLastError());
-    const int nbits = 64;
-    LCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_sort, keys, sorted, (int)n, 0, nbits, s));
-    LCHK(hipcub::DeviceRunLengthEncode::Encode(nullptr, tmp_rle, sorted, ukeys, counts, nruns_d,
-                                               (int)n, s));
-    LCHK(hipMalloc(&tmp, std::max(tmp_sort, tmp_rle)));
     LCHK(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_sort, keys, sorted, (int)n, 0, nbits, s));
     LCHK(hipcub::DeviceRunLengthEncode::Encode(tmp, tmp_rle, sorted, ukeys, counts, nruns_d,
                                                (int)n, s));
@@ -244,7 +279,7 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
         LCHK(hipMemcpyAsync(&last, ukeys + nruns - 1, sizeof(last), hipMemcpyDeviceToHost, s));
         LCHK(hipStreamSynchronize(s));
     }
-    const int64_t nvalid = (nruns > 0 && last == LENS_NO_KEY) ? nruns - 1 : nruns;
+    const int64_t nvalid = (nruns > 0 && last == kp.no_key) ? nruns - 1 : nruns;
     L.nnz = nvalid;
     k_lens_rows<<<blocks(nrows + 1, 256), 256, 0, s>>>(ukeys, nvalid, nrows, kp.npix, L.rowptr);
     LCHK(hipGetLastError());
@@ -252,7 +287,6 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
         LCHK(hipMalloc(&L.col, nvalid * sizeof(int32_t)));
         LCHK(hipMalloc(&L.val, nvalid * sizeof(double)));
         LCHK(hipMalloc(&L.count, nvalid * sizeof(unsigned long long)));
-        LCHK(hipMalloc(&tot, nrows * sizeof(unsigned long long)));
         k_lens_rowsum<<<blocks(nrows, 256), 256, 0, s>>>(counts, L.rowptr, nrows, tot);
         LCHK(hipGetLastError());
         k_lens_values<<<blocks(nvalid, 256), 256, 0, s>>>(ukeys, counts, tot, nvalid, kp.npix,
@@ -293,6 +327,14 @@ hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hip
     default: k_lens_apply<64><<<grid, 256, 0, s>>>(p); break;
     }
     return hipGetLastError();
+}
+
+void lens_free_scratch(Lens& L)
+{
+    if (L.scratch)
+        (void)hipFree(L.scratch);
+    L.scratch = nullptr;
+    L.scratch_bytes = 0;
 }
 
 void lens_free(Lens& L)

@@ -7,8 +7,6 @@
 
 namespace crp {
 
-constexpr unsigned long long LENS_NO_KEY = ~0ull;   // a record that takes no part
-
 // A lens set in CSR form: row r Np + i (rigidity bin r, Earth pixel i), columns
 // the border pixels j in increasing order.
 struct Lens {
@@ -19,6 +17,9 @@ struct Lens {
     int64_t nrows = 0, nnz = 0;
     int npix = 0, n_r = 0;
     int lpr = 4;                        // lanes per row of the application kernel
+    // construction scratch, kept (grow-only) between builds
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
 };
 
 struct LensKeyParams {
@@ -28,6 +29,7 @@ struct LensKeyParams {
     const double* r_edges;              // device [n_r + 1]
     int n_r, sky_n, npix;
     uint32_t status_mask;
+    unsigned long long no_key;          // n_r Np Np: the key of a record that takes no part
 };
 
 struct LensApplyParams {
@@ -43,6 +45,7 @@ struct LensApplyParams {
 
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s);
 hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hipStream_t s);
-void lens_free(Lens& L);
+void lens_free(Lens& L);           // the matrix (the scratch stays)
+void lens_free_scratch(Lens& L);
 
 }  // namespace crp

@@ -702,6 +702,7 @@ void crp_destroy(crp_ctx* ctx)
     nf_destroy(ctx->nf);
     free_patches(ctx);
     lens_free(ctx->lens);
+    lens_free_scratch(ctx->lens);
     for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, ctx->tmem, ctx->obs_mem,
                     (void*)ctx->cnt,
                     (void*)ctx->d_params,
@@ -1308,6 +1309,8 @@ crp_status crp_lens_build(crp_ctx* ctx, const crp_lens_spec* sp, int64_t* nnz, d
     kp.sky_n = sp->sky_n;
     kp.npix = 6 * sp->sky_n * sp->sky_n;
     kp.status_mask = (uint32_t)sp->status_mask;
+    kp.no_key = (unsigned long long)kp.n_r * (unsigned long long)kp.npix *
+                (unsigned long long)kp.npix;
     ctx->has_lens = false;
     if (e == hipSuccess)
         e = hipEventRecord(ctx->ev0, ctx->stream);
