@@ -223,9 +223,25 @@ static hipError_t lens_scratch(Lens& L, int64_t n, size_t tmp_bytes, int64_t nro
     return hipSuccess;
 }
 
+// Grows a matrix buffer to at least n elements (contents not kept).
+template <class T>
+static hipError_t lens_grow(T** p, int64_t n, int64_t& cap)
+{
+    if (n <= cap && *p)
+        return hipSuccess;
+    if (*p)
+        (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    hipError_t e = hipMalloc((void**)p, (size_t)std::max<int64_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess)
+        cap = n;
+    return e;
+}
+
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s)
 {
-    lens_free(L);
+    L.nnz = 0;
     const int64_t n = kp.n;
     L.nrows = nrows;
     L.npix = kp.npix;
@@ -242,7 +258,11 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
         if (e != hipSuccess)     \
             return done(e);      \
     } while (0)
-    LCHK(hipMalloc(&L.rowptr, (size_t)(nrows + 1) * sizeof(int64_t)));
+    {
+        int64_t cap = L.cap_rows;
+        LCHK(lens_grow(&L.rowptr, nrows + 1, cap));
+        L.cap_rows = cap;
+    }
     if (n == 0) {
         LCHK(hipMemsetAsync(L.rowptr, 0, (size_t)(nrows + 1) * sizeof(int64_t), s));
         LCHK(hipStreamSynchronize(s));
@@ -284,9 +304,14 @@ hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream
     k_lens_rows<<<blocks(nrows + 1, 256), 256, 0, s>>>(ukeys, nvalid, nrows, kp.npix, L.rowptr);
     LCHK(hipGetLastError());
     if (nvalid > 0) {
-        LCHK(hipMalloc(&L.col, nvalid * sizeof(int32_t)));
-        LCHK(hipMalloc(&L.val, nvalid * sizeof(double)));
-        LCHK(hipMalloc(&L.count, nvalid * sizeof(unsigned long long)));
+        if (nvalid > L.cap_nnz || !L.col || !L.val || !L.count) {
+            int64_t c1 = 0, c2 = 0, c3 = 0;   // zero capacities: reallocate all three
+            L.cap_nnz = 0;
+            LCHK(lens_grow(&L.col, nvalid, c1));
+            LCHK(lens_grow(&L.val, nvalid, c2));
+            LCHK(lens_grow(&L.count, nvalid, c3));
+            L.cap_nnz = nvalid;
+        }
         k_lens_rowsum<<<blocks(nrows, 256), 256, 0, s>>>(counts, L.rowptr, nrows, tot);
         LCHK(hipGetLastError());
         k_lens_values<<<blocks(nvalid, 256), 256, 0, s>>>(ukeys, counts, tot, nvalid, kp.npix,
@@ -347,6 +372,8 @@ void lens_free(Lens& L)
     L.val = nullptr;
     L.count = nullptr;
     L.nnz = 0;
+    L.cap_rows = 0;
+    L.cap_nnz = 0;
 }
 
 }  // namespace crp

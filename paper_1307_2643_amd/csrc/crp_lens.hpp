@@ -17,9 +17,11 @@ struct Lens {
     int64_t nrows = 0, nnz = 0;
     int npix = 0, n_r = 0;
     int lpr = 4;                        // lanes per row of the application kernel
-    // construction scratch, kept (grow-only) between builds
+    // construction scratch, kept (grow-only) between builds, and the matrix
+    // buffers' capacities (also grow-only)
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    int64_t cap_rows = 0, cap_nnz = 0;
 };
 
 struct LensKeyParams {
@@ -45,7 +47,7 @@ struct LensApplyParams {
 
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s);
 hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hipStream_t s);
-void lens_free(Lens& L);           // the matrix (the scratch stays)
+void lens_free(Lens& L);           // the matrix buffers
 void lens_free_scratch(Lens& L);
 
 }  // namespace crp

@@ -165,3 +165,22 @@ def test_full_size_lens_properties(P, O):
     fo, _, _, _ = O.propagate(O.config_for(W), O.AnalyticRef(I.GALACTIC_FIELD),
                               O.TablesRef(W.make_tables()), sub, nthreads=0)
     compare_lens(Lg, LN.build(sp, fo), "first 2000 events")
+
+
+def test_rebuilds_in_one_context(P, O, events):
+    """Builds of growing, empty and shrinking lens sets in one context (the
+    construction scratch and matrix buffers are reused) each equal the
+    oracle's."""
+    inj, fo = events
+    ctx = backtrack_gpu(P, inj)
+    edges = 10.0 ** np.linspace(16.5, 20.0, 6)
+    for sky_n, e in ((2, edges), (24, edges), (3, [1e25, 1e26]), (8, edges), (24, edges[:3])):
+        sp = LN.spec(e, sky_n=sky_n)
+        say(f"rebuild sky_n={sky_n} bins={len(e) - 1}")
+        nnz, _ = ctx.lens_build(sp)
+        Lo = LN.build(sp, fo)
+        assert nnz == len(Lo["col"])
+        compare_lens(ctx.lens_read(), Lo, f"rebuild sky_n={sky_n}")
+        if nnz:
+            check_apply(P, ctx, Lo, sky_n + 100, n_maps=5)
+    ctx.close()
