@@ -756,9 +756,7 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
     cnf = crp.Context(nprm, stream)
     cnf.set_field_grid(grid, wd.spacing_m)
     cnf.set_tables(tables)
-    from oracle import nf_oracle as NO      # parameter flattening only
-    ws, bs = I.nf_init_weights(509)
-    cnf.nf_init(I.nf_frequencies(seed=505), NO.flatten(ws, bs).astype(np.float32), wd.brms_T)
+    cnf.nf_init(I.nf_frequencies(seed=505), I.nf_init_flat(509), wd.brms_T)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = cnf.nf_train(args.nf_steps, 65536, 1e-3, 1e-5, 506)

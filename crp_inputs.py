@@ -412,6 +412,17 @@ def nf_init_weights(seed=509, width=128, depth=4, nout=3, nin=128):
     return ws, bs
 
 
+def nf_init_flat(seed=509):
+    """The same initial parameters as one flat FP32 vector in the library's
+    order W1, b1, ..., W4, b4, W5, b5 (each W row-major [out][in])."""
+    ws, bs = nf_init_weights(seed)
+    parts = []
+    for W, b in zip(ws, bs):
+        parts.append(np.asarray(W, np.float32).ravel())
+        parts.append(np.asarray(b, np.float32).ravel())
+    return np.concatenate(parts)
+
+
 def uniform_points(n, box_m, seed, origin=(0.0, 0.0, 0.0)):
     """Uniform sample positions in one period of the field box, metres."""
     rng = np.random.default_rng(seed)

@@ -277,3 +277,52 @@ def test_batch_split_invariance_full_size(P, big):
     for k, v in ref_cnt.items():
         assert cnt[k] == v, k
     assert _digest(P, fin) == digest
+
+
+def test_neural_field_full_size(P, big):
+    """The learned form at full size: the network trained on 1e8 points of the
+    1024^3 grid by the library's own kernels, its RMS field error against the
+    grid on held-out points, and the deflection-angle distribution of 2e5
+    distance-workload candidates propagated with it against the grid run (the
+    grid path is the reference).  The network replaces a 12.9 GB field with
+    132,870 bytes of bf16 weights."""
+    wd = I.W_DIST1024
+    m = 200_000
+    prm = P.params_for(wd, P.MIX, device=0, field_mode=P.FIELD_NEURAL, queue_capacity=2 * m,
+                       neutral_capacity=1 << 20)
+    ctx = P.Context(prm)
+    ctx.set_field_grid(big["grid"], wd.spacing_m)
+    ctx.set_tables(big["tables"])
+    ctx.nf_init(I.nf_frequencies(seed=505), I.nf_init_flat(509), wd.brms_T)
+    say("training the network on 1e8 points")
+    losses = ctx.nf_train(1526, 65536, 1e-3, 1e-5, 506)
+    assert np.all(np.isfinite(losses)) and losses[-1] < 0.1 * losses[0]
+    pos = I.uniform_points(200_000, wd.grid_n * wd.spacing_m, 507)
+    Bn = ctx.eval_field(pos, P.EVAL_NEURAL)
+    Bg = ctx.eval_field(pos, P.MIX)
+    rms = float(np.sqrt(((Bn - Bg) ** 2).sum(1).mean()) / wd.brms_T)
+    inj = I.inject_distances(m, 508)
+    ctx.inject(inj)
+    say("propagating 2e5 candidates with the network")
+    assert ctx.propagate(0)
+    fn = ctx.read_finished()
+    ctx.close()
+    gprm = P.params_for(wd, P.MIX, device=0, queue_capacity=2 * m, neutral_capacity=1 << 20)
+    cg = P.Context(gprm)
+    cg.set_field_grid(big["grid"], wd.spacing_m)
+    cg.set_tables(big["tables"])
+    cg.inject(inj)
+    assert cg.propagate(0)
+    fg = cg.read_finished()
+    cg.close()
+
+    def hist(f):
+        th = np.degrees(np.arccos(np.clip((f["u"] * f["u0"]).sum(1), -1, 1)))
+        return np.histogram(th, bins=36, range=(0, 180))[0] / len(th)
+
+    dist = float(0.5 * np.abs(hist(fn) - hist(fg)).sum())
+    say(f"network: RMS field error {rms:.3f} of B_rms, deflection histogram distance {dist:.4f}")
+    # measured 0.27: 64 Fourier features do not represent the band to 1%; a regression guard
+    assert rms < 0.35
+    assert dist <= 0.02
+    assert len(fn["id"]) >= m and len(fg["id"]) >= m

@@ -107,3 +107,12 @@ def test_normalized_position_wraps():
     p = np.array([[-1.0, 0.0, 10.5], [3.0, 7.0, -0.25]])
     xh = N.normalized_position(p, (2, 2, 2), 2.0)
     assert np.allclose(xh, [[0.75, 0.0, 0.625], [0.75, 0.75, 0.9375]])
+
+
+def test_flat_initial_parameters_follow_the_oracle_layout():
+    """The input module's flat initial vector (used by the benchmark) is the
+    oracle's flattening of the same weights."""
+    import crp_inputs as I
+    from oracle import nf_oracle as NO
+    ws, bs = I.nf_init_weights(509)
+    assert np.array_equal(I.nf_init_flat(509), NO.flatten(ws, bs).astype(np.float32))
