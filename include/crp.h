@@ -17,6 +17,11 @@
  *      after each cycle.
  * Secondaries: a nucleon-loss event spawns a charged proton candidate that is
  * propagated in the same run; a pion-like event emits a neutral record.
+ * Field sources: the periodic grid (optionally with refinement patches: a
+ * multi-resolution grid), an analytic galactic field for backtracking
+ * (section 4), or a learned neural field.  Outputs: finished and neutral
+ * records, per-step trajectory points, observable sums (spectra, deflection,
+ * sky maps) and galactic lenses built from backtracked records (section 4).
  *
  * Units at this ABI: metres, eV, tesla; rates in 1/m.
  * Threading: one context per host thread; calls on one context must not
