@@ -194,6 +194,45 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def _is_dev(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _shape_ok(got, want, what):
+    if len(got) != len(want) or any(w is not None and g != w for g, w in zip(got, want)):
+        exp = tuple("*" if w is None else w for w in want)
+        raise ValueError(f"{what}: shape {tuple(got)}, expected {exp}")
+
+
+def _host(a, dtype, shape, what):
+    """`a` as a C-contiguous host array of `dtype` whose shape matches `shape`
+    (None matches any extent).  The library reads exactly the sizes it is
+    given, so every shape is checked here before a pointer is passed."""
+    if hasattr(a, "is_cuda"):
+        raise ValueError(f"{what}: a host array is expected here, got a torch tensor")
+    a = np.ascontiguousarray(a, dtype)
+    _shape_ok(a.shape, shape, what)
+    return a
+
+
+def _dev(a, dtype, shape, what, device):
+    """`a` checked as a contiguous torch tensor on GPU `device` of `dtype`
+    (uint32 data may come as int32 tensors) with a shape matching `shape`."""
+    if not _is_dev(a):
+        raise ValueError(f"{what}: a torch tensor on the GPU is expected here")
+    import torch
+    ok = {np.float64: (torch.float64,), np.float32: (torch.float32,),
+          np.int32: (torch.int32,), np.uint32: (torch.int32, torch.uint32)}[dtype]
+    if a.dtype not in ok:
+        raise ValueError(f"{what}: dtype {a.dtype}, expected {ok[0]}")
+    if not a.is_contiguous():
+        raise ValueError(f"{what}: the tensor must be contiguous")
+    if a.device.index != device:
+        raise ValueError(f"{what}: tensor on {a.device}, the context uses cuda:{device}")
+    _shape_ok(tuple(a.shape), shape, what)
+    return a
+
+
 FIN_FIELDS = {"id": np.uint32, "lineage": np.uint32, "m": np.uint32, "nsteps": np.uint32,
               "nrej": np.uint32, "status": np.int32, "A": np.int32, "Z": np.int32,
               "E": np.float64, "x": np.float64, "u": np.float64, "L": np.float64,
@@ -292,35 +331,38 @@ class Context:
     def set_field_grid(self, grid, spacing, origin=(0.0, 0.0, 0.0)):
         """grid: [nx][ny][nz][3] float32/float64 numpy array (copied) or a
         contiguous torch device tensor (used in place; kept alive here)."""
-        on_dev = hasattr(grid, "is_cuda") and grid.is_cuda
+        on_dev = _is_dev(grid)
         if on_dev:
             import torch
-            assert grid.is_contiguous() and grid.dim() == 4 and grid.shape[3] == 3
             dt = F32 if grid.dtype == torch.float32 else F64
+            _dev(grid, np.float32 if dt == F32 else np.float64, (None, None, None, 3), "grid",
+                 self.params.device)
             self._keep = [grid]
         else:
-            grid = np.ascontiguousarray(grid)
-            assert grid.ndim == 4 and grid.shape[3] == 3
-            dt = F32 if grid.dtype == np.float32 else F64
+            dt = F32 if np.asarray(grid).dtype == np.float32 else F64
+            grid = _host(grid, np.float32 if dt == F32 else np.float64, (None, None, None, 3),
+                         "grid")
         org = (C.c_double * 3)(*[float(v) for v in origin])
         self._check(self.L.crp_set_field_grid(self.h, _ptr(grid), dt, int(on_dev),
                                               grid.shape[0], grid.shape[1], grid.shape[2],
                                               float(spacing), org))
+        self._grid_dtype = np.float32 if dt == F32 else np.float64
 
     def set_field_patches(self, patches):
         """Refinement patches of the grid: dicts with data ([n0][n1][n2][3] numpy
         array, copied, or a contiguous torch device tensor, used in place and
-        kept alive here), offset (base vertex index) and refine."""
+        kept alive here), offset (base vertex index) and refine.  Patch values
+        have the base grid's type (host arrays are converted to it)."""
+        gdt = getattr(self, "_grid_dtype", np.float64)
         arr = (GridPatch * max(len(patches), 1))()
         keep = []
         for k, q in enumerate(patches):
             d = q["data"]
-            on_dev = hasattr(d, "is_cuda") and d.is_cuda
-            if not on_dev:
-                d = np.ascontiguousarray(d)
+            on_dev = _is_dev(d)
+            if on_dev:
+                d = _dev(d, gdt, (None, None, None, 3), f"patch {k}", self.params.device)
             else:
-                assert d.is_contiguous()
-            assert d.ndim == 4 and d.shape[3] == 3
+                d = _host(d, gdt, (None, None, None, 3), f"patch {k}")
             keep.append(d)
             arr[k].data = _ptr(d)
             for a in range(3):
@@ -342,7 +384,8 @@ class Context:
         self._check(self.L.crp_set_field_analytic(self.h, C.byref(f)))
 
     def set_tables(self, tables):
-        arrs = [np.ascontiguousarray(a, np.float64) for a in
+        n = len(tables.e_nodes)
+        arrs = [_host(a, np.float64, (n,), "tables") for a in
                 (tables.e_nodes, tables.t_pi, tables.t_n, tables.beta_p)]
         self._check(self.L.crp_set_tables(self.h, len(arrs[0]), *[_ptr(a) for a in arrs]))
 
@@ -350,14 +393,14 @@ class Context:
                lmax=None, on_device=False):
         if inj is not None:
             id, A, Z, E, pos, dir, lmax = inj.id, inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax
+        n = int(len(id))
+        spec = ((id, np.uint32, (n,), "id"), (A, np.int32, (n,), "A"), (Z, np.int32, (n,), "Z"),
+                (E, np.float64, (n,), "E"), (pos, np.float64, (n, 3), "pos"),
+                (dir, np.float64, (n, 3), "dir"), (lmax, np.float64, (n,), "lmax"))
         if on_device:
-            arrs = [id, A, Z, E, pos, dir, lmax]
+            arrs = [_dev(a, dt, sh, w, self.params.device) for a, dt, sh, w in spec]
         else:
-            arrs = [np.ascontiguousarray(id, np.uint32), np.ascontiguousarray(A, np.int32),
-                    np.ascontiguousarray(Z, np.int32), np.ascontiguousarray(E, np.float64),
-                    np.ascontiguousarray(pos, np.float64), np.ascontiguousarray(dir, np.float64),
-                    np.ascontiguousarray(lmax, np.float64)]
-        n = int(arrs[0].shape[0])
+            arrs = [_host(a, dt, sh, w) for a, dt, sh, w in spec]
         self._check(self.L.crp_inject(self.h, n, *[_ptr(a) for a in arrs], int(on_device)))
 
     # -- the hot path ---------------------------------------------------------
@@ -476,12 +519,18 @@ class Context:
     def lens_apply(self, x, y=None):
         """x: [n_maps][n_r][Np] float64 numpy array (or a torch device tensor,
         then y too).  Returns (y, kernel ms)."""
-        on_dev = hasattr(x, "is_cuda") and x.is_cuda
+        if getattr(self, "_lens_shape", None) is None:
+            self._check(self.L.crp_lens_apply(self.h, 0, None, None, 0, None))
+        nr, npix, _ = self._lens_shape
+        shape = (None, nr, npix)
+        on_dev = _is_dev(x)
         if on_dev:
             import torch
+            x = _dev(x, np.float64, shape, "x", self.params.device)
             y = torch.empty_like(x) if y is None else y
+            _dev(y, np.float64, tuple(x.shape), "y", self.params.device)
         else:
-            x = np.ascontiguousarray(x, np.float64)
+            x = _host(x, np.float64, shape, "x")
             y = np.empty_like(x)
         ms = C.c_double(0)
         self._check(self.L.crp_lens_apply(self.h, int(x.shape[0]), _ptr(x), _ptr(y),
@@ -497,12 +546,13 @@ class Context:
         return {k: v[:n.value] for k, v in arrs.items()}
 
     def eval_field(self, pos, mode=FP64):
-        on_dev = hasattr(pos, "is_cuda") and pos.is_cuda
+        on_dev = _is_dev(pos)
         if on_dev:
             import torch
+            pos = _dev(pos, np.float64, (None, 3), "pos", self.params.device)
             out = torch.empty_like(pos)
         else:
-            pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
+            pos = _host(np.asarray(pos, np.float64).reshape(-1, 3), np.float64, (None, 3), "pos")
             out = np.empty_like(pos)
         self._check(self.L.crp_eval_field(self.h, pos.shape[0], _ptr(pos), _ptr(out), mode,
                                           int(on_dev)))
@@ -553,9 +603,8 @@ class Context:
 
     # -- neural field ---------------------------------------------------------
     def nf_init(self, freq, params, b_scale):
-        f = np.ascontiguousarray(freq, np.int32)
-        p = np.ascontiguousarray(params, np.float32)
-        assert f.shape == (64, 3) and p.shape == (NF_NPARAM,)
+        f = _host(freq, np.int32, (64, 3), "freq")
+        p = _host(params, np.float32, (NF_NPARAM,), "params")
         self._check(self.L.crp_nf_init(self.h, _ptr(f), _ptr(p), float(b_scale)))
 
     def nf_get_params(self):
@@ -564,8 +613,9 @@ class Context:
         return p
 
     def nf_loss_grad(self, pos, target):
-        pos = np.ascontiguousarray(pos, np.float64).reshape(-1, 3)
-        t = np.ascontiguousarray(target, np.float32).reshape(-1, 3)
+        pos = _host(np.asarray(pos, np.float64).reshape(-1, 3), np.float64, (None, 3), "pos")
+        t = _host(np.asarray(target, np.float32).reshape(-1, 3), np.float32,
+                  (pos.shape[0], 3), "target")
         out = np.empty(t.shape, np.float32)
         g = np.empty(NF_NPARAM, np.float32)
         loss = C.c_double(0)

@@ -1368,13 +1368,15 @@ crp_status crp_lens_apply(crp_ctx* ctx, int32_t n_maps, const double* x, double*
     const double* dx = x;
     double* dy = y;
     void* stage = nullptr;
+    hipError_t e = hipSuccess;
     if (!on_device) {
         HIPCHK(ctx, hipMalloc(&stage, 2 * bytes));
         dx = (const double*)stage;
         dy = (double*)((char*)stage + bytes);
-        HIPCHK(ctx, hipMemcpyAsync((void*)dx, x, bytes, hipMemcpyHostToDevice, ctx->stream));
+        e = hipMemcpyAsync((void*)dx, x, bytes, hipMemcpyHostToDevice, ctx->stream);
     }
-    hipError_t e = hipEventRecord(ctx->ev0, ctx->stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->ev0, ctx->stream);
     if (e == hipSuccess)
         e = lens_apply(L, n_maps, dx, dy, ctx->stream);
     if (e == hipSuccess)
@@ -1472,10 +1474,13 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
         HIPCHK(ctx, hipMalloc(&stage, (size_t)n * 48));
         dpos = (const double*)stage;
         dB = (double*)stage + 3 * n;
-        HIPCHK(ctx, hipMemcpyAsync((void*)dpos, pos, n * 24, hipMemcpyHostToDevice, ctx->stream));
     }
-    hipError_t e = hipSuccess;
-    if (analytic) {
+    hipError_t e = on_device ? hipSuccess
+                             : hipMemcpyAsync((void*)dpos, pos, n * 24, hipMemcpyHostToDevice,
+                                              ctx->stream);
+    if (e != hipSuccess) {
+        // the copy failed: nothing launched; the staging buffer is freed below
+    } else if (analytic) {
         k_eval_analytic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->ana, n, dpos, dB);
         e = hipGetLastError();
     } else if (neural) {
@@ -1553,6 +1558,8 @@ crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s
         return CRP_EINVAL;
     if (!ctx->has_grid)
         return fail(ctx, CRP_ESTATE, "gather_ceiling: set the grid first");
+    if (ctx->gn[0] * ctx->gn[1] * ctx->gn[2] > (int64_t)UINT32_MAX)
+        return fail(ctx, CRP_EINVAL, "gather_ceiling: at most 2^32 - 1 cells");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     crp_status st = ensure_corner(ctx);
     if (st != CRP_OK)
