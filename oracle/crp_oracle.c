@@ -76,15 +76,29 @@ static double grid_value(const or_grid* g, int64_t i, int64_t j, int64_t k, int 
     return (double)((const float*)g->data)[off];
 }
 
+/* floor(f) reduced modulo n into [0, n), exactly for every finite f: through
+ * 64-bit integers where they hold the value, else through fmod (exact); a
+ * non-finite offset takes cell 0 (its t is NaN). */
+static int64_t wrap_cell(double fl, int64_t n)
+{
+    if (fabs(fl) < 0x1p62) {
+        int64_t i = (int64_t)fl;
+        return ((i % n) + n) % n;
+    }
+    double r = fmod(fl, (double)n);
+    if (r < 0.0)
+        r += (double)n;
+    return r == r ? (int64_t)r : 0;
+}
+
 /* Cell index pair and fractional offset along one axis (FP64 in all modes). */
 static void axis_cell(const or_grid* g, int a, double p, int64_t idx[2], double* t)
 {
     double inv = 1.0 / g->spacing;
     double f = (p - g->origin[a]) * inv;
     double fl = floor(f);
-    int64_t i = (int64_t)fl;
     int64_t n = g->n[a];
-    int64_t i0 = ((i % n) + n) % n;
+    int64_t i0 = wrap_cell(fl, n);
     idx[0] = i0;
     idx[1] = (i0 + 1) % n;
     *t = f - fl;

@@ -633,3 +633,31 @@ def test_small_workload_matches_stored_summary(oracle_lib):
     fin = O.sort_finished(fin)
     assert int(fin["nsteps"].sum()) == ref["fp64"]["nsteps_sum"]
     assert np.allclose(fin["x"][:4], np.array(ref["fp64"]["first"]["x"]), rtol=1e-12, atol=0)
+
+
+def test_periodic_cell_of_far_positions(oracle_lib):
+    """Positions far beyond the box (as a forced step with a huge error
+    estimate can produce) still select the cell floor(x / d) mod N.  At
+    |x / d| >= 2^52 every double is an integer, so the field there is the value
+    of one vertex, whose index Python's exact integers give; the offsets span
+    both sides of 2^31, 2^62 and 2^63."""
+    O = oracle_lib
+    rng = np.random.default_rng(41)
+    n = (6, 7, 5)
+    g = rng.standard_normal(n + (3,))
+    G = O.GridRef(g, 1.0)
+    vals = [2.0 ** 31 - 1, 2.0 ** 31, 2.0 ** 52 + 2, 2.0 ** 62 - 2 ** 10, 2.0 ** 62,
+            2.0 ** 62 + 2 ** 11, 2.0 ** 63, 2.0 ** 64 + 2 ** 12, 3.0 * 2.0 ** 70, 1e300]
+    vals = vals + [-v for v in vals]
+    p = np.array([[vals[k], vals[(k + 3) % len(vals)], vals[(k + 7) % len(vals)]]
+                  for k in range(len(vals))])
+    got = O.eval_field(G, p)
+    for k in range(len(p)):
+        idx = [int(p[k, a]) % n[a] for a in range(3)]      # Python: exact, non-negative
+        if all(abs(p[k, a]) >= 2.0 ** 52 for a in range(3)):
+            assert np.array_equal(got[k], g[idx[0], idx[1], idx[2]]), k
+    # below 2^52 the offset is fractional only for the 2^31 +- values, which are
+    # integers too: every point here sits on a vertex
+    for k in range(len(p)):
+        idx = [int(p[k, a]) % n[a] for a in range(3)]
+        assert np.array_equal(got[k], g[idx[0], idx[1], idx[2]]), k
