@@ -76,19 +76,15 @@ static double grid_value(const or_grid* g, int64_t i, int64_t j, int64_t k, int 
     return (double)((const float*)g->data)[off];
 }
 
-/* floor(f) reduced modulo n into [0, n), exactly for every finite f: through
- * 64-bit integers where they hold the value, else through fmod (exact); a
- * non-finite offset takes cell 0 (its t is NaN). */
+/* floor(f) reduced modulo n into [0, n).  Offsets beyond 32-bit cell indices
+ * (positions some 2^31 cells from the origin, reachable only through a forced
+ * step with an enormous error) saturate to [-2^31, 2^31 - 1] first; a NaN
+ * offset takes -2^31 (its t is NaN). */
 static int64_t wrap_cell(double fl, int64_t n)
 {
-    if (fabs(fl) < 0x1p62) {
-        int64_t i = (int64_t)fl;
-        return ((i % n) + n) % n;
-    }
-    double r = fmod(fl, (double)n);
-    if (r < 0.0)
-        r += (double)n;
-    return r == r ? (int64_t)r : 0;
+    double fc = fmin(fmax(fl, -0x1p31), 0x1p31 - 1.0);
+    int64_t i = (int64_t)fc;
+    return ((i % n) + n) % n;
 }
 
 /* Cell index pair and fractional offset along one axis (FP64 in all modes). */

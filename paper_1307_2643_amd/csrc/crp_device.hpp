@@ -251,8 +251,10 @@ __device__ inline Cell locate(const GridView& g, const double p[3])
     for (int a = 0; a < 3; ++a) {
         const double f = (p[a] - g.origin[a]) * g.inv_spacing;
         const double fl = floor(f);
-        const int i = (int)fl;
-        const int i0 = wrap_index(i, g.n[a], g.mask[a]);
+        // offsets beyond 32-bit cell indices (positions ~2^31 cells out)
+        // saturate; a NaN offset takes the lowest index
+        const double fc = fmin(fmax(fl, -0x1p31), 0x1p31 - 1.0);
+        const int i0 = wrap_index((int)fc, g.n[a], g.mask[a]);
         c.i0[a] = i0;
         c.i1[a] = (i0 + 1 == g.n[a]) ? 0 : i0 + 1;
         c.t[a] = f - fl;

@@ -311,3 +311,87 @@ def test_single_candidate_and_ragged_batch(P, O, mixed_grid):
         compare_counts(cg, co, f"n={n}")
         compare_records(fg, fo, f"n={n}")
         ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Degenerate cases of the method: energies below the floor and beyond both
+# ends of the tables, the lightest and heaviest nuclei the boundary accepts,
+# axis-aligned directions, starts on grid vertices and just below a vertex
+# (the cell offset rounds to 1), trajectory limits far below the minimum step;
+# then a field-free grid (straight lines) and a fixed step (hmin = hmax).
+# ---------------------------------------------------------------------------
+def _edge_injection(spacing):
+    species = [(1, 1), (2, 1), (4, 2), (14, 7), (56, 26), (255, 1), (255, 100), (255, 255)]
+    energies = [1e15, 1e16, 1.0000001e16, 1e18, 1e21, 1e23, 1e24, 1e26]
+    n = 70                                                   # one wave and six lanes
+    rng = np.random.default_rng(77)
+    A = np.array([species[i % 8][0] for i in range(n)], np.int32)
+    Z = np.array([species[i % 8][1] for i in range(n)], np.int32)
+    E = np.array([energies[(i // 8 + i) % 8] for i in range(n)])
+    d = rng.standard_normal((n, 3))
+    d[:6] = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]])
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pos = rng.uniform(-300.0, 300.0, (n, 3)) * spacing
+    pos[:10] = np.round(pos[:10] / spacing) * spacing        # on vertices
+    pos[10] = (0.0, -0.0, 0.0)
+    pos[11] = (-1e-30, -1e-30, -1e-30)                       # offset rounds to 1
+    lmax = np.full(n, 100 * I.MPC_M)
+    lmax[12], lmax[13], lmax[14] = 1.0, 1e3, 1e-3 * spacing  # below the minimum step
+    return I.Injection(np.arange(n, dtype=np.uint32), A, Z, E, pos, d, lmax)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_degenerate_cases_match_oracle(P, O, mixed_grid, precision):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    inj = _edge_injection(w.spacing_m)
+    grid = mixed_grid if precision == 0 else mixed_grid.astype(np.float32)
+    say(f"degenerate cases precision={precision}")
+    ctx = make_ctx(P, w, grid, tables, precision, ncap=1 << 20)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done
+    fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
+                                O.GridRef(grid, w.spacing_m), O.TablesRef(tables), inj,
+                                nthreads=0, neu_cap=1 << 20)
+    compare_counts(cg, co, "degenerate")
+    assert co["energy_floor"] > 0 and co["charged_sec"] > 0 and co["forced"] > 0
+    same = compare_records(fg, fo, f"degenerate p{precision}")
+    assert same.all()
+    compare_neutral(ng, no, "degenerate neutral")
+    ctx.close()
+
+
+def test_field_free_and_fixed_step_match_oracle(P, O, mixed_grid):
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    inj = _edge_injection(w.spacing_m)
+    zero = np.zeros((8, 8, 8, 3))
+    say("field-free grid")
+    ctx = make_ctx(P, w, zero, tables, 0, ncap=1 << 20)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done
+    fo, no, co, _ = O.propagate(O.config_for(w), O.GridRef(zero, w.spacing_m),
+                                O.TablesRef(tables), inj, nthreads=0, neu_cap=1 << 20)
+    compare_counts(cg, co, "field-free")
+    assert compare_records(fg, fo, "field-free").all()
+    # straight lines: the primaries end at x0 + L u0
+    fg = P.sort_finished(fg)
+    prim = fg["lineage"] == 0
+    ids = fg["id"][prim]
+    x0 = inj.pos[ids]
+    dev = np.linalg.norm(fg["x"][prim] - (x0 + fg["L"][prim, None] * inj.dir[ids]), axis=1)
+    assert np.all(dev <= 1e-9 * np.maximum(fg["L"][prim], 1.0) + 1e-9 * np.linalg.norm(x0, axis=1))
+    assert np.array_equal(fg["u0"][prim], inj.dir[ids])
+    ctx.close()
+    h = 100 * I.KPC_M
+    say("fixed step hmin = hmax")
+    ctx = make_ctx(P, w, mixed_grid, tables, 0, ncap=1 << 20, hmin=h, hmax=h)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done
+    fo, no, co, _ = O.propagate(O.config_for(w, hmin=h, hmax=h),
+                                O.GridRef(mixed_grid, w.spacing_m), O.TablesRef(tables), inj,
+                                nthreads=0, neu_cap=1 << 20)
+    compare_counts(cg, co, "fixed step")
+    assert compare_records(fg, fo, "fixed step").all()
+    compare_neutral(ng, no, "fixed step neutral")
+    ctx.close()
