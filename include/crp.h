@@ -396,8 +396,8 @@ crp_status crp_last_timing(crp_ctx* ctx, double* kernel_ms, int64_t* launches);
  * context's corner records (built on first use, as for CRP_LAYOUT_CORNER),
  * `iters` random records per lane with the context's blocks per CU (block
  * 128).  records_per_s: gathered records per second, the practical ceiling of
- * the field evaluation.  CRP_ESTATE without a grid, CRP_EINVAL for an FP64 grid
- * or iters < 1. */
+ * the field evaluation.  CRP_ESTATE without a grid, CRP_EINVAL for an FP64 grid,
+ * a grid of more than 2^32 - 1 cells or iters < 1. */
 crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s);
 
 /* Checkpoint: pending candidates, undrained finished / neutral records,
