@@ -609,8 +609,12 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
         !std::isfinite(c.boundary_center[0]) || !std::isfinite(c.boundary_center[1]) ||
         !std::isfinite(c.boundary_center[2]) ||
         !(c.tol > 0) || !(c.hmin > 0) || !(c.hmax >= c.hmin) || !(c.eps_loss > 0) ||
-        !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !(c.obs_radius >= 0) ||
+        !std::isfinite(c.tol) || !std::isfinite(c.hmax) || !std::isfinite(c.eps_loss) ||
+        !(c.kappa_pi >= 0 && c.kappa_pi < 1) || !(c.e_floor >= 0) || !std::isfinite(c.e_floor) ||
+        !(c.obs_radius >= 0) || !std::isfinite(c.obs_radius) || !std::isfinite(c.obs_center[0]) ||
+        !std::isfinite(c.obs_center[1]) || !std::isfinite(c.obs_center[2]) ||
         c.queue_capacity <= 0 || c.neutral_capacity <= 0 || c.queue_capacity > (1ll << 40) ||
+        c.neutral_capacity > (1ll << 40) ||
         c.traj_every < 0 || c.traj_capacity < 0 || c.traj_capacity > (1ll << 40) ||
         (c.traj_every > 0 && c.traj_capacity == 0) ||
         (c.field_mode == CRP_FIELD_NEURAL && c.precision != CRP_MIX))

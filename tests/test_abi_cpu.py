@@ -73,3 +73,41 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(crp, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         crp.load()
+
+
+def test_create_rejects_bad_configs_before_any_device_call():
+    """crp_create validates the configuration on the host: every bad field is
+    CRP_EINVAL without touching a device (a good one reaches the device, which
+    this container lacks: CRP_EDEVICE, or a context where there is a GPU)."""
+    import math
+    from paper_1307_2643_amd import crp
+    lib = crp.load()
+
+    def status(**kw):
+        p = crp.Params()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        c = crp.Config()
+        for k, _ in crp.Config._fields_:
+            v = getattr(p, k)
+            if k in ("obs_center", "boundary_center"):
+                for a in range(3):
+                    getattr(c, k)[a] = float(v[a])
+            else:
+                setattr(c, k, v)
+        h = C.c_void_p()
+        st = lib.crp_create(C.byref(c), None, C.byref(h))
+        if h.value:
+            lib.crp_destroy(h)
+        return st
+
+    bad = [dict(precision=2), dict(field_mode=7), dict(charge_sign=2), dict(tol=0.0),
+           dict(tol=math.inf), dict(hmin=0.0), dict(hmax=1.0), dict(hmax=math.inf),
+           dict(eps_loss=math.nan), dict(kappa_pi=1.0), dict(e_floor=math.inf),
+           dict(obs_radius=-1.0), dict(obs_center=(0.0, math.nan, 0.0)),
+           dict(boundary_radius=math.inf), dict(queue_capacity=0),
+           dict(neutral_capacity=(1 << 40) + 1), dict(traj_every=1, traj_capacity=0),
+           dict(field_mode=crp.FIELD_NEURAL, precision=crp.FP64)]
+    for kw in bad:
+        assert status(**kw) == -1, kw
+    assert status() in (0, -2)
