@@ -122,7 +122,9 @@ __device__ __attribute__((always_inline)) inline void nf_embed(const float* freq
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             const int jj = 16 * m + 8 * g + j;
-            const float ang = (freq[3 * jj] * x0 + freq[3 * jj + 1] * x1) + freq[3 * jj + 2] * x2;
+            // fused: the phases only feed bf16 features
+            const float ang = __builtin_fmaf(
+                freq[3 * jj + 2], x2, __builtin_fmaf(freq[3 * jj + 1], x1, freq[3 * jj] * x0));
             act[m][j] = (__bf16)__builtin_amdgcn_cosf(ang);       // cos 2 pi ang
             act[m + 4][j] = (__bf16)__builtin_amdgcn_sinf(ang);   // sin 2 pi ang
         }
@@ -141,7 +143,15 @@ __device__ __attribute__((always_inline)) inline void nf_layer(const __bf16* wim
     const int rr = lane & 31;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        floatx16 acc0 = {}, acc1 = {};
+        // the accumulators start from the biases: the epilogue is ReLU and
+        // the bf16 conversion only
+        floatx16 acc0, acc1;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float b = bias[32 * r + 16 * (i >> 3) + 8 * g + (i & 7)];
+            acc0[i] = b;
+            acc1[i] = b;
+        }
         const int row = 32 * r + rr;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
@@ -151,10 +161,8 @@ __device__ __attribute__((always_inline)) inline void nf_layer(const __bf16* wim
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int f = 32 * r + 16 * (i >> 3) + 8 * g + (i & 7);
-            const float b = bias[f];
-            out[0][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc0[i] + b);
-            out[1][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc1[i] + b);
+            out[0][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc0[i]);
+            out[1][2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc1[i]);
         }
     }
 }
