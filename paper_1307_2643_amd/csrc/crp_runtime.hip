@@ -87,6 +87,8 @@ struct crp_ctx {
     DevCounters* cnt = nullptr;
     PropParams* d_params = nullptr;          // kernel parameter block (device)
     unsigned long long* scratch = nullptr;   // small device scratch (validation)
+    void* xfer = nullptr;                    // read-back staging (grow-only)
+    size_t xfer_bytes = 0;
 
     int64_t pending = 0;
     int64_t fin_unread = 0, neu_unread = 0, traj_unread = 0;
@@ -287,23 +289,47 @@ void launch_propagate(int nb, int bs, size_t lds, hipStream_t s, const PropParam
         k_propagate<MODE, GT, LAYOUT, 256, false><<<nb, 256, lds, s>>>(dp);
 }
 
-// Copies [start, start+k) of a planar [3][cap] device array into host [k][3].
-hipError_t copy_planar(double* host, const double* dev, int64_t cap, int64_t start, int64_t k,
-                       hipStream_t s)
+// [start, start+k) of a planar [3][cap] array as [k][3] (a thread per row, grid
+// stride: coalesced reads of each plane, 24-byte rows written side by side).
+__global__ void k_interleave3(const double* __restrict__ planar, int64_t cap, int64_t start,
+                              int64_t k, double* __restrict__ out)
 {
-    std::vector<double> tmp((size_t)k);
-    for (int a = 0; a < 3; ++a) {
-        hipError_t e = hipMemcpyAsync(tmp.data(), dev + a * cap + start, k * sizeof(double),
-                                      hipMemcpyDeviceToHost, s);
-        if (e != hipSuccess)
-            return e;
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess)
-            return e;
-        for (int64_t i = 0; i < k; ++i)
-            host[3 * i + a] = tmp[(size_t)i];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += stride) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            out[3 * i + a] = planar[a * cap + start + i];
     }
-    return hipSuccess;
+}
+
+// Copies [start, start+k) of a planar [3][cap] device array into host [k][3]:
+// interleaved on the device into the context's grow-only staging buffer, then
+// one copy (ordered on the stream, so consecutive calls may reuse the buffer).
+hipError_t copy_planar(crp_ctx* ctx, double* host, const double* dev, int64_t cap, int64_t start,
+                       int64_t k)
+{
+    if (k == 0 || host == nullptr)
+        return hipSuccess;
+    const size_t need = (size_t)k * 3 * sizeof(double);
+    if (need > ctx->xfer_bytes) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess)
+            return e;
+        if (ctx->xfer)
+            (void)hipFree(ctx->xfer);
+        ctx->xfer = nullptr;
+        ctx->xfer_bytes = 0;
+        e = hipMalloc(&ctx->xfer, need);
+        if (e != hipSuccess)
+            return e;
+        ctx->xfer_bytes = need;
+    }
+    const int nb = (int)std::min<int64_t>(blocks_for(std::min<int64_t>(k, 1ll << 30), 256), 65536);
+    k_interleave3<<<nb, 256, 0, ctx->stream>>>(dev, cap, start, k, (double*)ctx->xfer);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return hipMemcpyAsync(host, ctx->xfer, need, hipMemcpyDeviceToHost, ctx->stream);
 }
 
 template <class T>
@@ -710,7 +736,8 @@ void crp_destroy(crp_ctx* ctx)
     for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, ctx->tmem, ctx->obs_mem,
                     (void*)ctx->cnt,
                     (void*)ctx->d_params,
-                    (void*)ctx->scratch, ctx->grid_owned, (void*)ctx->tab, (void*)ctx->corner})
+                    (void*)ctx->scratch, ctx->xfer, ctx->grid_owned, (void*)ctx->tab,
+                    (void*)ctx->corner})
         if (p)
             (void)hipFree(p);
     if (ctx->ev0)
@@ -1091,11 +1118,11 @@ crp_status crp_read_finished(crp_ctx* ctx, int64_t cap, const crp_finished_soa* 
         HIPCHK(ctx, copy_d2h(out->L, f.L + s, k, ctx->stream));
         HIPCHK(ctx, copy_d2h(out->E0, f.E0 + s, k, ctx->stream));
         if (out->x)
-            HIPCHK(ctx, copy_planar(out->x, f.x, f.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->x, f.x, f.cap, s, k));
         if (out->u)
-            HIPCHK(ctx, copy_planar(out->u, f.u, f.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->u, f.u, f.cap, s, k));
         if (out->u0)
-            HIPCHK(ctx, copy_planar(out->u0, f.u0, f.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->u0, f.u0, f.cap, s, k));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     ctx->fin_unread -= k;
@@ -1119,9 +1146,9 @@ crp_status crp_read_neutral(crp_ctx* ctx, int64_t cap, const crp_neutral_soa* ou
         HIPCHK(ctx, copy_d2h(out->chan, f.chan + s, k, ctx->stream));
         HIPCHK(ctx, copy_d2h(out->E, f.E + s, k, ctx->stream));
         if (out->x)
-            HIPCHK(ctx, copy_planar(out->x, f.x, f.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->x, f.x, f.cap, s, k));
         if (out->u)
-            HIPCHK(ctx, copy_planar(out->u, f.u, f.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->u, f.u, f.cap, s, k));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     ctx->neu_unread -= k;
@@ -1146,7 +1173,7 @@ crp_status crp_read_trajectory(crp_ctx* ctx, int64_t cap, const crp_traj_soa* ou
         HIPCHK(ctx, copy_d2h(out->L, t.L + s, k, ctx->stream));
         HIPCHK(ctx, copy_d2h(out->E, t.E + s, k, ctx->stream));
         if (out->x)
-            HIPCHK(ctx, copy_planar(out->x, t.x, t.cap, s, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->x, t.x, t.cap, s, k));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     }
     ctx->traj_unread -= k;
@@ -1421,11 +1448,11 @@ crp_status crp_peek_pending(crp_ctx* ctx, int64_t cap, const crp_finished_soa* o
         HIPCHK(ctx, copy_d2h(out->L, q.L, k, ctx->stream));
         HIPCHK(ctx, copy_d2h(out->E0, q.E0, k, ctx->stream));
         if (out->x)
-            HIPCHK(ctx, copy_planar(out->x, q.x, q.cap, 0, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->x, q.x, q.cap, 0, k));
         if (out->u)
-            HIPCHK(ctx, copy_planar(out->u, q.u, q.cap, 0, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->u, q.u, q.cap, 0, k));
         if (out->u0)
-            HIPCHK(ctx, copy_planar(out->u0, q.u0, q.cap, 0, k, ctx->stream));
+            HIPCHK(ctx, copy_planar(ctx, out->u0, q.u0, q.cap, 0, k));
         HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
         if (out->status)
             for (int64_t i = 0; i < k; ++i)
