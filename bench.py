@@ -610,10 +610,10 @@ def galactic_variant(args, crp, I, torch, stream):
 
 def lens_measure(crp, torch, ctx, sky_n=32, n_maps=16):
     """Galactic lenses (section 4) from the backtracked events still unread in
-    ctx: build time, then the application to n_maps random border maps.  The
-    application streams the matrix once per four maps (12 bytes per entry for
-    column and value, 8 per row pointer) and reads each border map and writes
-    each Earth map once (8 + 8 bytes per row and map)."""
+    ctx: build time, then the application to n_maps random border maps, priced
+    at its algorithmic bytes: the matrix once (12 bytes per entry for column
+    and value, 8 per row pointer) and each border map read and each Earth map
+    written once (8 + 8 bytes per row and map)."""
     edges = 10.0 ** np.linspace(16.5, 20.0, 8)
     spec = dict(r_edges=edges, sky_n=sky_n, status_mask=1 << crp.BOUNDARY)
     _, first_ms = ctx.lens_build(spec)                  # allocates the construction scratch
@@ -626,8 +626,9 @@ def lens_measure(crp, torch, ctx, sky_n=32, n_maps=16):
     y = torch.empty_like(x)
     ctx.lens_apply(x, y)                                # warm
     _, ams = ctx.lens_apply(x, y)
-    passes = (n_maps + 3) // 4
-    app_bytes = passes * (12 * nnz + 8 * (nrows + 1)) + n_maps * 16 * nrows
+    # algorithmic bytes: the matrix once (column and value per entry, the row
+    # pointers) and every border map read and Earth map written once
+    app_bytes = 12 * nnz + 8 * (nrows + 1) + n_maps * 16 * nrows
     per_map = app_bytes / n_maps
     gbs = app_bytes / (ams * 1e-3) / 1e9
     log(f"[bench] lenses: {nr} rigidity bins x {npix} pixels, {nnz} entries, built in "
