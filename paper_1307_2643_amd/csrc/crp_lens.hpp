@@ -22,6 +22,9 @@ struct Lens {
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
     int64_t cap_rows = 0, cap_nnz = 0;
+    // application scratch (grow-only): border maps interleaved by pixel
+    double* xt = nullptr;
+    int64_t xt_cap = 0;                 // doubles
 };
 
 struct LensKeyParams {
@@ -46,8 +49,8 @@ struct LensApplyParams {
 };
 
 hipError_t lens_build(Lens& L, const LensKeyParams& kp, int64_t nrows, hipStream_t s);
-hipError_t lens_apply(const Lens& L, int n_maps, const double* x, double* y, hipStream_t s);
+hipError_t lens_apply(Lens& L, int n_maps, const double* x, double* y, hipStream_t s);
 void lens_free(Lens& L);           // the matrix buffers
-void lens_free_scratch(Lens& L);
+void lens_free_scratch(Lens& L);   // construction and application scratch
 
 }  // namespace crp

@@ -1394,7 +1394,7 @@ crp_status crp_lens_apply(crp_ctx* ctx, int32_t n_maps, const double* x, double*
     if (n_maps == 0)
         return CRP_OK;
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
-    const Lens& L = ctx->lens;
+    Lens& L = ctx->lens;
     const size_t bytes = (size_t)n_maps * (size_t)L.nrows * sizeof(double);
     const double* dx = x;
     double* dy = y;

@@ -184,3 +184,24 @@ def test_rebuilds_in_one_context(P, O, events):
         if nnz:
             check_apply(P, ctx, Lo, sky_n + 100, n_maps=5)
     ctx.close()
+
+
+def test_grouped_application_matches_four_map_passes(P, O, events):
+    """More than four maps go through the pixel-interleaved path (groups of
+    16 maps, the last one partial); every map's result has the bits of the
+    same map applied in a pass of at most four, and the oracle's bound."""
+    inj, fo = events
+    ctx = backtrack_gpu(P, inj)
+    sp = LN.spec(10.0 ** np.linspace(16.5, 20.0, 6), sky_n=8)
+    ctx.lens_build(sp)
+    Lo = LN.build(sp, fo)
+    rng = np.random.default_rng(44)
+    x = rng.uniform(0.0, 1.0, (21, Lo["n_r"], Lo["npix"]))
+    say("grouped lens application, 21 maps")
+    y, _ = ctx.lens_apply(x)
+    parts = np.concatenate([ctx.lens_apply(x[k:k + 4])[0] for k in range(0, 21, 4)])
+    assert np.array_equal(y, parts)
+    ref = LN.apply(Lo, x)
+    nrow = np.diff(Lo["rowptr"]).reshape(Lo["n_r"], Lo["npix"])
+    assert np.all(np.abs(y - ref) <= (nrow + 2) * 2.0 ** -52 * ref + 1e-300)
+    ctx.close()
