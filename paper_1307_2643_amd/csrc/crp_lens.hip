@@ -9,9 +9,11 @@
 // and an integer sum per row the normalisation.
 //
 // Application: a sparse matrix times border maps, one group of LPR lanes per
-// row (LPR chosen from the mean row length), four maps per pass, the group's
-// partial sums combined by lane shuffles.  HBM-bound: the matrix is streamed
-// once per four maps.
+// row (LPR sized for about four entries per lane), the group's partial sums
+// combined by lane shuffles; up to four maps in one pass over the matrix, more
+// maps interleaved by pixel first and applied sixteen per pass.  The time goes
+// to each row's dependent loads and to the per-map shuffle reductions rather
+// than to the bytes streamed.
 #include <hipcub/hipcub.hpp>
 
 #include "crp_lens.hpp"
