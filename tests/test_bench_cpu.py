@@ -1,0 +1,54 @@
+"""Host-side logic of bench.py that needs no GPU: the refusal of more than one
+GPU, and the traffic summary that scales the FETCH_SIZE / WRITE_SIZE counters
+of the propagation launch by what the same counters read for a 1 GiB copy."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run(*args):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args],
+                          capture_output=True, text=True, cwd=ROOT, timeout=300)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run("--gpus", "2")
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def _csv(path, rows):
+    with open(path, "w") as f:
+        f.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for d, k, c, v in rows:
+            f.write(f'{d},"{k}",{c},{v}\n')
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    prop = "void crp::k_propagate<1, float, 2, 128, false>(crp::PropParams const*)"
+    other = "void crp::k_propagate<0, double, 4, 128, false>(crp::PropParams const*)"
+    copy = "__amd_rocclr_copyBuffer"
+    gib_kib = float(1 << 20)
+    (tmp_path / "fetch").mkdir()
+    (tmp_path / "write").mkdir()
+    # the copy reads half its bytes as counted (FETCH_SIZE), writes all of them;
+    # two propagation launches (the larger is the timed one) and a kernel of
+    # another instantiation that must be ignored
+    _csv(tmp_path / "fetch" / "fetch_counter_collection.csv",
+         [(1, copy, "FETCH_SIZE", gib_kib / 2), (2, prop, "FETCH_SIZE", 1000.0),
+          (3, prop, "FETCH_SIZE", 3000.0), (4, other, "FETCH_SIZE", 9e9)])
+    _csv(tmp_path / "write" / "write_counter_collection.csv",
+         [(1, copy, "WRITE_SIZE", gib_kib), (2, prop, "WRITE_SIZE", 10.0),
+          (3, prop, "WRITE_SIZE", 20.0), (4, other, "WRITE_SIZE", 9e9)])
+    r = _run("--summarize-pmc", str(tmp_path))
+    assert r.returncode == 0, r.stderr
+    out = json.loads(r.stdout)
+    assert out["read_scale_factor"] == 2.0 and out["write_scale_factor"] == 1.0
+    assert out["read_bytes_per_launch"] == 3000.0 * 1024 * 2
+    assert out["write_bytes_per_launch"] == 20.0 * 1024
+    assert out["hbm_bytes_per_launch"] == 3000.0 * 1024 * 2 + 20.0 * 1024
+    assert len(out["kernel_sources_sha"]) == 16
