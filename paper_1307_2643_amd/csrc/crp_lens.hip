@@ -407,8 +407,10 @@ hipError_t lens_apply(Lens& L, int n_maps, const double* x, double* y, hipStream
     p.npix = L.npix;
     p.map_len = L.nrows;
     p.n_maps = n_maps;
-    if (n_maps > LENS_MAPS) {
-        const int64_t need = L.nrows * LENS_GROUP;
+    // the grouped path stages 128 bytes per row; lens sets whose staging would
+    // pass 1 GiB take the four-map passes instead
+    const int64_t need = L.nrows * LENS_GROUP;
+    if (n_maps > LENS_MAPS && need <= (int64_t)((1ll << 30) / sizeof(double))) {
         if (need > L.xt_cap) {
             hipError_t e = hipStreamSynchronize(s);
             if (e != hipSuccess)
