@@ -303,14 +303,17 @@ __global__ void k_interleave3(const double* __restrict__ planar, int64_t cap, in
 }
 
 // Copies [start, start+k) of a planar [3][cap] device array into host [k][3]:
-// interleaved on the device into the context's grow-only staging buffer, then
-// one copy (ordered on the stream, so consecutive calls may reuse the buffer).
+// interleaved on the device into the context's grow-only staging buffer
+// (chunks of at most 2^25 rows, 768 MiB), each chunk then copied once; the
+// steps are ordered on the stream, so a chunk's copy ends before the next
+// chunk overwrites the buffer.
 hipError_t copy_planar(crp_ctx* ctx, double* host, const double* dev, int64_t cap, int64_t start,
                        int64_t k)
 {
     if (k == 0 || host == nullptr)
         return hipSuccess;
-    const size_t need = (size_t)k * 3 * sizeof(double);
+    const int64_t chunk_max = 1ll << 25;
+    const size_t need = (size_t)std::min<int64_t>(k, chunk_max) * 3 * sizeof(double);
     if (need > ctx->xfer_bytes) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess)
@@ -324,12 +327,18 @@ hipError_t copy_planar(crp_ctx* ctx, double* host, const double* dev, int64_t ca
             return e;
         ctx->xfer_bytes = need;
     }
-    const int nb = (int)std::min<int64_t>(blocks_for(std::min<int64_t>(k, 1ll << 30), 256), 65536);
-    k_interleave3<<<nb, 256, 0, ctx->stream>>>(dev, cap, start, k, (double*)ctx->xfer);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    return hipMemcpyAsync(host, ctx->xfer, need, hipMemcpyDeviceToHost, ctx->stream);
+    for (int64_t c0 = 0; c0 < k; c0 += chunk_max) {
+        const int64_t kc = std::min<int64_t>(chunk_max, k - c0);
+        const int nb = (int)std::min<int64_t>(blocks_for(kc, 256), 65536);
+        k_interleave3<<<nb, 256, 0, ctx->stream>>>(dev, cap, start + c0, kc, (double*)ctx->xfer);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host + 3 * c0, ctx->xfer, (size_t)kc * 3 * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 template <class T>

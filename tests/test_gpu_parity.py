@@ -395,3 +395,37 @@ def test_field_free_and_fixed_step_match_oracle(P, O, mixed_grid):
     assert compare_records(fg, fo, "fixed step").all()
     compare_neutral(ng, no, "fixed step neutral")
     ctx.close()
+
+
+def test_read_back_in_chunks(P):
+    """More finished records than one read-back chunk (2^25 rows): positions
+    and directions interleaved chunk by chunk come back in the right rows.  A
+    field-free grid and a trajectory limit below the minimum step make every
+    candidate one straight step, x = x0 + L u0."""
+    import torch
+    w = I.W_SMALL
+    n = (1 << 25) + 1000
+    rng = np.random.default_rng(91)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    pos = rng.uniform(-1.0, 1.0, (n, 3)) * 3 * I.MPC_M
+    dev = dict(id=torch.arange(n, dtype=torch.int32, device="cuda:0"),
+               A=torch.ones(n, dtype=torch.int32, device="cuda:0"),
+               Z=torch.ones(n, dtype=torch.int32, device="cuda:0"),
+               E=torch.full((n,), 1e19, dtype=torch.float64, device="cuda:0"),
+               pos=torch.as_tensor(pos, device="cuda:0"), dir=torch.as_tensor(d, device="cuda:0"),
+               lmax=torch.full((n,), 1e-3 * w.hmin_m, dtype=torch.float64, device="cuda:0"))
+    ctx = make_ctx(P, w, np.zeros((8, 8, 8, 3)), w.make_tables(), P.FP64, qcap=n, ncap=1 << 10)
+    say(f"read-back in chunks: {n} candidates")
+    ctx.inject(**dev, on_device=True)
+    assert ctx.propagate()
+    fin = ctx.read_finished()
+    assert len(fin["id"]) == n
+    order = np.argsort(fin["id"])
+    ids = fin["id"][order].astype(np.int64)
+    assert np.array_equal(ids, np.arange(n))
+    x, u, u0, L = fin["x"][order], fin["u"][order], fin["u0"][order], fin["L"][order]
+    assert np.array_equal(u0, d)
+    assert np.all(np.abs(u - d) <= 4e-16)
+    assert np.all(np.linalg.norm(x - (pos + L[:, None] * d), axis=1) <= 1e-12 * 3 * I.MPC_M)
+    ctx.close()
