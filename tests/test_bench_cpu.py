@@ -52,3 +52,32 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     assert out["write_bytes_per_launch"] == 20.0 * 1024
     assert out["hbm_bytes_per_launch"] == 3000.0 * 1024 * 2 + 20.0 * 1024
     assert len(out["kernel_sources_sha"]) == 16
+
+
+def test_error_report_keys_records_and_measures_differences():
+    """The precision-form error summary pairs records by (id, lineage), counts
+    records present on one side only, and measures known perturbations."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    n = 1000
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    ref = dict(id=np.arange(n, dtype=np.uint32), lineage=np.zeros(n, np.uint32),
+               x=rng.standard_normal((n, 3)) * 1e22, u=u, u0=u.copy(), E=np.full(n, 1e19),
+               L=np.full(n, 1e23), status=np.full(n, 2, np.int32), A=np.ones(n, np.int32),
+               Z=np.ones(n, np.int32), m=np.zeros(n, np.uint32), nsteps=np.full(n, 7, np.uint32))
+    gpu = {k: v.copy() for k, v in ref.items()}
+    gpu["E"] = gpu["E"] * (1.0 + 1e-9)                  # every energy off by 1e-9
+    gpu["x"][:, 0] += 1e23 * 1e-6                       # every position off by 1e-6 of L
+    gpu["status"][:3] = 3                               # three integer mismatches
+    order = rng.permutation(n)[:-5]                     # shuffled, five records missing
+    gpu = {k: v[order] for k, v in gpu.items()}
+    r = bench.error_report(gpu, ref)
+    assert r["records_compared"] == n - 5 and r["records_in_one_only"] == 5
+    assert abs(r["energy_rel"]["median"] - 1e-9) < 1e-15
+    assert abs(r["position_rel"]["max"] - 1e-6) < 1e-12
+    assert r["direction_deg"]["max"] < 1e-5          # arccos of a dot product rounded near 1
+    assert r["integer_mismatches"]["status"] == sum(1 for i in order if i < 3)
+    assert r["deflection_hist_distance"] == 0.0
