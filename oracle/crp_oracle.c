@@ -76,15 +76,20 @@ static double grid_value(const or_grid* g, int64_t i, int64_t j, int64_t k, int 
     return (double)((const float*)g->data)[off];
 }
 
-/* floor(f) reduced modulo n into [0, n).  Offsets beyond 32-bit cell indices
- * (positions some 2^31 cells from the origin, reachable only through a forced
- * step with an enormous error) saturate to [-2^31, 2^31 - 1] first; a NaN
- * offset takes -2^31 (its t is NaN). */
+/* floor(f) reduced modulo n into [0, n), exactly for every finite f: the
+ * grid is periodic with period n cells, so the cell of any position is
+ * floor(f) mod n.  Through 64-bit integers where they hold the value, else
+ * through fmod (exact); a non-finite offset takes cell 0 (its t is NaN). */
 static int64_t wrap_cell(double fl, int64_t n)
 {
-    double fc = fmin(fmax(fl, -0x1p31), 0x1p31 - 1.0);
-    int64_t i = (int64_t)fc;
-    return ((i % n) + n) % n;
+    if (fabs(fl) < 0x1p62) {
+        int64_t i = (int64_t)fl;
+        return ((i % n) + n) % n;
+    }
+    double r = fmod(fl, (double)n);
+    if (r < 0.0)
+        r += (double)n;
+    return r == r ? (int64_t)r : 0;
 }
 
 /* Cell index pair and fractional offset along one axis (FP64 in all modes). */
@@ -100,12 +105,12 @@ static void axis_cell(const or_grid* g, int a, double p, int64_t idx[2], double*
     *t = f - fl;
 }
 
-/* Analytic galactic field (model in crp_oracle.h), FP64 in the order written:
- * derived constants first, then the toroidal factor g with B_t = g (-y, x, 0),
- * g = b_disk / X + b_halo (z/h_halo) / Y over the common denominator X Y
- * (X, Y the disk and halo denominators), then the X-field with one reciprocal
- * iD = 1/D: B_x = x q, B_y = y q, B_z = b_x iD - b_x (r^2/r_x^2) iD^2,
- * q = b_x (z/h_x^2) iD^2.  Two divisions per evaluation. */
+/* Analytic galactic field (model in crp_oracle.h), FP64, each term of the
+ * model divided out on its own: derived constants first, then the toroidal
+ * factor g = g_disk + g_halo with B_t = g (-y, x, 0) (B_phi / r of each
+ * part), then the X-field B_x = x q, B_y = y q,
+ * B_z = b_x / D - b_x r^2 / (r_x^2 D^2), q = b_x z / (h_x^2 D^2).  Five
+ * divisions per evaluation. */
 static void field_analytic(const or_analytic* a, const double p[3], double B[3])
 {
     double kd = 1.0 / (a->r_disk * a->r_disk), ld = 1.0 / (a->h_disk * a->h_disk);
@@ -115,17 +120,16 @@ static void field_analytic(const or_analytic* a, const double p[3], double B[3])
     double dx = p[0] - a->center[0], dy = p[1] - a->center[1], dz = p[2] - a->center[2];
     double r2 = dx * dx + dy * dy;
     double z2 = dz * dz;
-    double X = (a->r_disk * (1.0 + r2 * kd)) * (1.0 + z2 * ld);
+    double gd = a->b_disk / ((a->r_disk * (1.0 + r2 * kd)) * (1.0 + z2 * ld));
     double wh = 1.0 + z2 * lh;
-    double Y = (a->r_halo * (1.0 + r2 * kh)) * (wh * wh);
-    double g = (a->b_disk * Y + (a->b_halo * (dz * ih)) * X) / (X * Y);
+    double gh = (a->b_halo * (dz * ih)) / ((a->r_halo * (1.0 + r2 * kh)) * (wh * wh));
+    double g = gd + gh;
     double D = (1.0 + r2 * kx) + z2 * lx;
-    double iD = 1.0 / D;
-    double iD2 = iD * iD;
-    double q = (a->b_x * (dz * lx)) * iD2;
+    double D2 = D * D;
+    double q = (a->b_x * (dz * lx)) / D2;
     B[0] = (-g) * dy + dx * q;
     B[1] = g * dx + dy * q;
-    B[2] = a->b_x * iD - (a->b_x * (r2 * kx)) * iD2;
+    B[2] = a->b_x / D - (a->b_x * (r2 * kx)) / D2;
 }
 
 /* Multi-resolution grid: the cell that holds position p.  The base cell
@@ -428,6 +432,10 @@ int32_t oracle_ctrl_k(double r)
 {
     const int32_t KMAX = 5121;
     double g = (0.95 * 1024.0) * pow(r, -0.2);
+    /* a NaN ratio (from a NaN field or position) fails every test k^5 r <= c,
+     * so its factor is k = 0; taken before any conversion of g */
+    if (!(g >= 0.0))
+        return 0;
     int32_t k = g > (double)KMAX ? KMAX : (int32_t)floor(g);
     while (k < KMAX && ctrl_pred(k + 1, r))
         ++k;

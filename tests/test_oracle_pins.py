@@ -636,32 +636,45 @@ def test_small_workload_matches_stored_summary(oracle_lib):
 
 
 def test_periodic_cell_of_far_positions(oracle_lib):
-    """The cell of a position is floor(x / d) mod N for offsets below 2^31
-    cells; beyond (reachable only through a forced step with an enormous error
-    estimate) the offset saturates to [-2^31, 2^31 - 1] first.  Every point
-    here sits on a vertex (offsets >= 2^31 are integers), so the field is the
-    value of one vertex, whose index Python's exact integers give."""
+    """The grid is periodic (section 4: a regular grid of the precomputed field
+    with period N cells), so the cell of any finite position is floor(x / d)
+    mod N -- also far beyond the box, as a forced step with a huge error
+    estimate can fling a candidate.  At |x / d| >= 2^52 every double is an
+    integer, so the field there is the value of one vertex, whose index
+    Python's exact integers give; the offsets span both sides of 2^31, 2^62
+    and 2^63."""
     O = oracle_lib
     rng = np.random.default_rng(41)
     n = (6, 7, 5)
     g = rng.standard_normal(n + (3,))
     G = O.GridRef(g, 1.0)
-    vals = [2.0 ** 31 - 2, 2.0 ** 31 - 1, 2.0 ** 31, 2.0 ** 52 + 2, 2.0 ** 62, 2.0 ** 63,
-            2.0 ** 64 + 2 ** 12, 3.0 * 2.0 ** 70, 1e300, 12345.0]
+    vals = [2.0 ** 31 - 1, 2.0 ** 31, 2.0 ** 52 + 2, 2.0 ** 62 - 2 ** 10, 2.0 ** 62,
+            2.0 ** 62 + 2 ** 11, 2.0 ** 63, 2.0 ** 64 + 2 ** 12, 3.0 * 2.0 ** 70, 1e300,
+            12345.0]
     vals = vals + [-v for v in vals]
     p = np.array([[vals[k], vals[(k + 3) % len(vals)], vals[(k + 7) % len(vals)]]
                   for k in range(len(vals))])
     got = O.eval_field(G, p)
-
-    def cell(v, m):
-        i = min(max(int(v), -2 ** 31), 2 ** 31 - 1)
-        return i % m                                        # Python: non-negative
-
+    # every point sits on a vertex (all offsets here are integers)
     for k in range(len(p)):
-        idx = [cell(p[k, a], n[a]) for a in range(3)]
+        idx = [int(p[k, a]) % n[a] for a in range(3)]      # Python: exact, non-negative
         assert np.array_equal(got[k], g[idx[0], idx[1], idx[2]]), k
-    # below the saturation the cell is periodic: shifting by whole periods
-    # (exact for these integers) selects the same vertex
-    small = np.array([[12345.0, -2.0 ** 30, 2.0 ** 31 - 2]])
-    shift = np.array([[6.0 * 1000, -7.0 * 1000, -5.0 * 1000]])
-    assert np.array_equal(O.eval_field(G, small), O.eval_field(G, small + shift))
+    # shifting a fractional position by whole periods selects the same cell and
+    # weights (shifts exact in FP64 at these magnitudes)
+    small = np.array([[0.25, -2.0 ** 30 + 0.5, 2.0 ** 31 - 2 + 0.75]])
+    for m in (1, 1000, 2 ** 20):
+        shift = np.array([[6.0 * m, -7.0 * m, -5.0 * m]])
+        assert np.array_equal(O.eval_field(G, small), O.eval_field(G, small + shift))
+    # a non-finite position gives a non-finite field (and reads inside the grid)
+    bad = np.array([[np.nan, 0.0, 0.0], [np.inf, 0.0, 0.0], [0.0, -np.inf, 0.5]])
+    assert np.all(np.isnan(O.eval_field(G, bad)).any(axis=1))
+
+
+def test_controller_factor_special_ratios(oracle_lib):
+    """r = 0 (an exact step) takes the cap 5121; a NaN ratio satisfies no
+    k^5 r <= (0.95 1024)^5, so k = 0; r = 1 gives floor(972.8) = 972."""
+    O = oracle_lib
+    assert O.ctrl_k(0.0) == 5121
+    assert O.ctrl_k(float("nan")) == 0
+    assert O.ctrl_k(1.0) == 972
+    assert O.ctrl_k(float("inf")) == 0
