@@ -244,21 +244,57 @@ __device__ inline int wrap_index(int i, int n, int mask)
     return r < 0 ? r + n : r;
 }
 
+// Cell of a position some 2^31 or more cells out on some axis (as a forced
+// step with a huge error estimate can produce), or not finite: floor(f) mod n
+// by fmod, exact for every finite value, so the periodic cell is the same as
+// for any nearer image; a non-finite offset takes cell 0 (its t is NaN, and so
+// is the field).  Out of line, arguments and result in registers: no lane of
+// a normal run takes it.
+struct CellIdx {
+    int i[3];
+};
+
+__device__ __attribute__((noinline)) CellIdx far_cells(int n0, int n1, int n2, double f0,
+                                                       double f1, double f2)
+{
+    const int n[3] = {n0, n1, n2};
+    const double fl[3] = {f0, f1, f2};
+    CellIdx r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double m = fmod(fl[a], (double)n[a]);
+        if (m < 0.0)
+            m += (double)n[a];
+        r.i[a] = m == m ? (int)m : 0;
+    }
+    return r;
+}
+
 __device__ inline Cell locate(const GridView& g, const double p[3])
 {
     Cell c;
+    double fl[3];
+    bool near = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double f = (p[a] - g.origin[a]) * g.inv_spacing;
-        const double fl = floor(f);
-        // offsets beyond 32-bit cell indices (positions ~2^31 cells out)
-        // saturate; a NaN offset takes the lowest index
-        const double fc = fmin(fmax(fl, -0x1p31), 0x1p31 - 1.0);
-        const int i0 = wrap_index((int)fc, g.n[a], g.mask[a]);
-        c.i0[a] = i0;
-        c.i1[a] = (i0 + 1 == g.n[a]) ? 0 : i0 + 1;
-        c.t[a] = f - fl;
+        fl[a] = floor(f);
+        near = near & (fabs(fl[a]) < 0x1p31);   // false for a non-finite offset
+        // the conversion is only used for offsets within 32 bits; the clamp
+        // keeps it defined for the others, which far_cells then replaces
+        const double fc = fmin(fmax(fl[a], -0x1p31), 0x1p31 - 1.0);
+        c.i0[a] = wrap_index((int)fc, g.n[a], g.mask[a]);
+        c.t[a] = f - fl[a];
     }
+    if (__builtin_expect(!near, 0)) {
+        const CellIdx r = far_cells(g.n[0], g.n[1], g.n[2], fl[0], fl[1], fl[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            c.i0[a] = r.i[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        c.i1[a] = (c.i0[a] + 1 == g.n[a]) ? 0 : c.i0[a] + 1;
     return c;
 }
 

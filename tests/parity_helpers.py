@@ -50,7 +50,37 @@ def compare_records(fg, fo, what, x_tol=1e-9, e_tol=1e-6):
     return same
 
 
-def compare_neutral(ng, no, what):
+def compare_records_chaotic(fg, fo, what, min_frac, x_tol=1e-9, e_tol=1e-6):
+    """For runs whose two sides evaluate the field with different rounding
+    orders (a few ulp apart): over long confined paths the motion is chaotic
+    and an ulp grows, so the position bar is checked per record and at least
+    `min_frac` of the records must meet it; integer fields (status, steps,
+    events, species) stay exact and energies within e_tol for every record.
+    The states after a fixed number of cycles are compared separately, at the
+    full bar for every record.  Returns the fraction within the bar."""
+    from paper_1307_2643_amd import crp
+    fg = crp.sort_finished(fg)
+    fo = crp.sort_finished(fo)
+    assert len(fg["id"]) == len(fo["id"]), what
+    for k in INT_FIELDS:
+        bad = np.nonzero(fg[k] != fo[k])[0]
+        assert bad.size == 0, f"{what}: field {k} differs at {bad[:5]}"
+    assert np.all(np.abs(fg["E"] / fo["E"] - 1) <= e_tol), what
+    scale = np.maximum(np.maximum(fo["L"], np.linalg.norm(fo["x"], axis=1)), 1.0)
+    rel = np.linalg.norm(fg["x"] - fo["x"], axis=1) / scale
+    ok = rel <= x_tol
+    frac = float(ok.mean()) if len(ok) else 1.0
+    say(f"{what}: {len(ok)} records, within {x_tol:g} of max(L, |x|): {ok.sum()} "
+        f"({100 * frac:.2f}%), diverged {np.count_nonzero(~ok)} (max {rel.max() if len(rel) else 0:.2e})")
+    assert frac >= min_frac, what
+    return frac
+
+
+def compare_neutral(ng, no, what, fo=None):
+    """Neutral records: keys and channels exact, energies within 1e-6, positions
+    within 1e-9 of max(|x|, L) where L is the emitting candidate's path length
+    (bounded by the length in its finished record `fo`, L only grows; without
+    `fo`, |x| alone and 1 m)."""
     from paper_1307_2643_amd import crp
     ng = crp.sort_neutral(ng)
     no = crp.sort_neutral(no)
@@ -58,7 +88,17 @@ def compare_neutral(ng, no, what):
     for k in ("id", "lineage", "m", "chan"):
         assert np.array_equal(ng[k], no[k]), f"{what}: {k}"
     assert np.allclose(ng["E"], no["E"], rtol=1e-6, atol=0), what
-    assert np.allclose(ng["x"], no["x"], rtol=0, atol=1e-9 * 1e26), what
+    scale = np.maximum(np.linalg.norm(no["x"], axis=1), 1.0)
+    if fo is not None and len(no["id"]):
+        key_f = (fo["id"].astype(np.uint64) << np.uint64(32)) | fo["lineage"].astype(np.uint64)
+        key_n = (no["id"].astype(np.uint64) << np.uint64(32)) | no["lineage"].astype(np.uint64)
+        order = np.argsort(key_f)
+        pos = np.searchsorted(key_f[order], key_n)
+        assert np.all(key_f[order][np.minimum(pos, len(key_f) - 1)] == key_n), what
+        scale = np.maximum(scale, fo["L"][order][pos])
+    dx = np.linalg.norm(ng["x"] - no["x"], axis=1)
+    assert np.all(dx <= 1e-9 * scale), f"{what}: max dx/scale {np.max(dx / scale)}"
+    assert np.all(np.linalg.norm(ng["u"] - no["u"], axis=1) <= 1e-7), what
 
 
 def compare_counts(cg, co, what):

@@ -1,10 +1,12 @@
 """GPU parity of the galactic lenses (section 4: PARSEC-style transformation
 matrices per energy range), through the C-ABI: construction from the records
-of a backtracking run on the GPU against the oracle's construction from its
-own run of the same events (bitwise: integer counts and one FP64 division per
+of a backtracking run on the GPU against the oracle's construction from the
+same records read back (bitwise: integer counts and one FP64 division per
 entry), and the application to border maps against the oracle's sparse
 product (FP64, the order of the sums differs: within (row length + 2) ulp of
-the sum of |terms|)."""
+the sum of |terms|).  The backtracking itself is compared with the oracle's
+in tests/test_gpu_galactic.py; the GPU run is deterministic (the same records
+for the same events in every launch), which the lens tests rely on."""
 import numpy as np
 import pytest
 
@@ -42,11 +44,13 @@ def backtrack_gpu(P, inj, model=None, precision=0):
 
 
 @pytest.fixture(scope="module")
-def events(O):
+def events(P):
+    """6000 seeded events and the GPU's backtracked records of them."""
     inj = W.make_injection(6000)
-    fo, _, _, _ = O.propagate(O.config_for(W), O.AnalyticRef(I.GALACTIC_FIELD),
-                              O.TablesRef(W.make_tables()), inj, nthreads=0)
-    return inj, fo
+    ctx = backtrack_gpu(P, inj)
+    fg = ctx.read_finished()
+    ctx.close()
+    return inj, fg
 
 
 def compare_lens(Lg, Lo, what):
@@ -75,14 +79,14 @@ def check_apply(P, ctx, Lo, seed, n_maps=3):
 
 @pytest.mark.parametrize("sky_n", [2, 8, 24], ids=["long-rows", "mid", "short-rows"])
 def test_lens_build_and_apply_parity(P, O, events, sky_n):
-    inj, fo = events
+    inj, fg = events
     sp = LN.spec(10.0 ** np.linspace(16.5, 20.0, 6), sky_n=sky_n)
     ctx = backtrack_gpu(P, inj)
     say(f"lens sky_n={sky_n}")
     nnz, ms = ctx.lens_build(sp)
     Lg = ctx.lens_read()
-    assert ctx.counts()["finished_unread"] == len(fo["id"])     # records stay unread
-    Lo = LN.build(sp, fo)
+    assert ctx.counts()["finished_unread"] == len(fg["id"])     # records stay unread
+    Lo = LN.build(sp, fg)
     assert nnz == len(Lo["col"])
     compare_lens(Lg, Lo, f"lens sky_n={sky_n}")
     check_apply(P, ctx, Lo, sky_n)
@@ -122,7 +126,8 @@ def test_field_free_identity_and_edge_cases(P, O):
 def test_full_size_lens_properties(P, O):
     """The bench's lens set: 1e7 backtracked events (the full galactic batch),
     7 rigidity bins x 6144 pixels.  Checked by properties that hold at any
-    size, and the first 2000 events' lens against the oracle's."""
+    size, and the first 2000 events' lens against the oracle's construction
+    from the same records."""
     import torch
     n = 10_000_000
     inj = W.make_injection(n)
@@ -161,24 +166,23 @@ def test_full_size_lens_properties(P, O):
     c2 = backtrack_gpu(P, sub)
     c2.lens_build(sp)
     Lg = c2.lens_read()
+    fg = c2.read_finished()
     c2.close()
-    fo, _, _, _ = O.propagate(O.config_for(W), O.AnalyticRef(I.GALACTIC_FIELD),
-                              O.TablesRef(W.make_tables()), sub, nthreads=0)
-    compare_lens(Lg, LN.build(sp, fo), "first 2000 events")
+    compare_lens(Lg, LN.build(sp, fg), "first 2000 events")
 
 
 def test_rebuilds_in_one_context(P, O, events):
     """Builds of growing, empty and shrinking lens sets in one context (the
     construction scratch and matrix buffers are reused) each equal the
     oracle's."""
-    inj, fo = events
+    inj, fg = events
     ctx = backtrack_gpu(P, inj)
     edges = 10.0 ** np.linspace(16.5, 20.0, 6)
     for sky_n, e in ((2, edges), (24, edges), (3, [1e25, 1e26]), (8, edges), (24, edges[:3])):
         sp = LN.spec(e, sky_n=sky_n)
         say(f"rebuild sky_n={sky_n} bins={len(e) - 1}")
         nnz, _ = ctx.lens_build(sp)
-        Lo = LN.build(sp, fo)
+        Lo = LN.build(sp, fg)
         assert nnz == len(Lo["col"])
         compare_lens(ctx.lens_read(), Lo, f"rebuild sky_n={sky_n}")
         if nnz:
@@ -190,11 +194,11 @@ def test_grouped_application_matches_four_map_passes(P, O, events):
     """More than four maps go through the pixel-interleaved path (groups of
     16 maps, the last one partial); every map's result has the bits of the
     same map applied in a pass of at most four, and the oracle's bound."""
-    inj, fo = events
+    inj, fg = events
     ctx = backtrack_gpu(P, inj)
     sp = LN.spec(10.0 ** np.linspace(16.5, 20.0, 6), sky_n=8)
     ctx.lens_build(sp)
-    Lo = LN.build(sp, fo)
+    Lo = LN.build(sp, fg)
     rng = np.random.default_rng(44)
     x = rng.uniform(0.0, 1.0, (21, Lo["n_r"], Lo["npix"]))
     say("grouped lens application, 21 maps")

@@ -80,6 +80,54 @@ def test_eval_field_non_power_of_two_grid(P, O):
     ctx.close()
 
 
+def _far_positions(spacing):
+    """Offsets on both sides of 2^31, 2^62 and 2^63 cells and far beyond, with
+    fractional offsets near 2^31 and a few non-finite positions."""
+    vals = [2.0 ** 31 - 1, 2.0 ** 31, 2.0 ** 31 + 0.5, 2.0 ** 52 + 2, 2.0 ** 62 - 2 ** 10,
+            2.0 ** 62, 2.0 ** 63, 2.0 ** 64 + 2 ** 12, 3.0 * 2.0 ** 70, 1e300, 12345.25,
+            2.0 ** 31 - 2 + 0.75]
+    vals = vals + [-v for v in vals]
+    p = np.array([[vals[k], vals[(k + 3) % len(vals)], vals[(k + 7) % len(vals)]]
+                  for k in range(len(vals))]) * spacing
+    bad = np.array([[np.nan, 0.0, 0.0], [np.inf, 1.0, 0.0], [0.0, -np.inf, 0.5]]) * spacing
+    return p, bad
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (6, 5, 7)], ids=["pow2", "odd"])
+def test_eval_field_far_positions_exact_wrap(P, O, shape):
+    """The periodic cell is floor(x / d) mod N for every finite offset, on the
+    GPU as in the oracle: bitwise for FP64/FP32 grids, both interpolation
+    forms, linear and corner layouts.  Non-finite positions give a non-finite
+    field on both sides."""
+    w = I.W_SMALL
+    rng = np.random.default_rng(3)
+    g64 = rng.standard_normal(shape + (3,)) * 1e-13
+    pos, bad = _far_positions(1.0)              # spacing 1 m: positions are offsets in cells
+    for gdtype in (np.float64, np.float32):
+        g = g64.astype(gdtype)
+        prm = P.params_for(w, P.FP64, queue_capacity=1 << 12, neutral_capacity=1 << 12)
+        ctx = P.Context(prm)
+        ctx.set_field_grid(g, 1.0)
+        ctx.set_tables(w.make_tables())
+        for mode in (0, 1):
+            say(f"far positions shape={shape} dtype={np.dtype(gdtype).name} mode={mode}")
+            ref = O.eval_field(O.GridRef(g, 1.0), pos, O.MIX if mode == 1 else O.FP64)
+            assert np.array_equal(ctx.eval_field(pos, mode), ref)
+            assert np.all(np.isnan(ctx.eval_field(bad, mode)).any(axis=1))
+        if gdtype == np.float32:
+            ctx.set_launch(layout=P.LAYOUT_CORNER)
+            inj = w.make_injection(64)
+            inj = I.Injection(inj.id, inj.A, inj.Z, inj.E, inj.pos * 0.0, inj.dir,
+                              np.full(64, 10.0))
+            ctx.inject(inj)
+            ctx.propagate()                     # builds the corner records on first use
+            for mode in (0, 1):
+                say(f"far positions corner layout mode={mode}")
+                ref = O.eval_field(O.GridRef(g, 1.0), pos, O.MIX if mode == 1 else O.FP64)
+                assert np.array_equal(ctx.eval_field(pos, mode), ref)
+        ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # Whole path: small workload (1000 protons, 32^3 FP64 grid, loss table).
 # ---------------------------------------------------------------------------
@@ -121,7 +169,7 @@ def test_mixed_workload_subset_parity(P, O, mixed_grid, precision):
     assert co["charged_sec"] > 0 and co["neutral_sec"] > 0
     same = compare_records(fg, fo, f"mixed p{precision}")
     assert same.mean() > 0.99
-    compare_neutral(ng, no, "mixed neutral")
+    compare_neutral(ng, no, "mixed neutral", fo)
     ctx.close()
 
 
@@ -357,7 +405,7 @@ def test_degenerate_cases_match_oracle(P, O, mixed_grid, precision):
     assert co["energy_floor"] > 0 and co["charged_sec"] > 0 and co["forced"] > 0
     same = compare_records(fg, fo, f"degenerate p{precision}")
     assert same.all()
-    compare_neutral(ng, no, "degenerate neutral")
+    compare_neutral(ng, no, "degenerate neutral", fo)
     ctx.close()
 
 
@@ -393,7 +441,7 @@ def test_field_free_and_fixed_step_match_oracle(P, O, mixed_grid):
                                 nthreads=0, neu_cap=1 << 20)
     compare_counts(cg, co, "fixed step")
     assert compare_records(fg, fo, "fixed step").all()
-    compare_neutral(ng, no, "fixed step neutral")
+    compare_neutral(ng, no, "fixed step neutral", fo)
     ctx.close()
 
 

@@ -155,7 +155,7 @@ def test_full_batch_sampled_parity(P, O, big, precision):
     fg = _select(fin, ids)
     same = compare_records(fg, fo, f"1024^3 sample p{precision}")
     assert same.all()
-    compare_neutral(_select(neu, ids), no, f"1024^3 sample neutral p{precision}")
+    compare_neutral(_select(neu, ids), no, f"1024^3 sample neutral p{precision}", fo)
 
 
 def test_full_batch_trajectory_and_observables(P, O, big):
