@@ -372,6 +372,21 @@ crp_status crp_reset_counters(crp_ctx* ctx);
 crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos_m, double* B_T,
                           int32_t mode, int32_t on_device);
 
+/* For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * crp_eval_field for host arrays pos [n][3] (m) and B [n][3] (T), same modes
+ * and the same kernels, bitwise the same results, staged through a static
+ * device array of the library instead of a per-call allocation.  It calls no
+ * hipMalloc, hipFree or other allocating routine.  Limit: n <=
+ * CRP_EVAL_NOALLOC_MAX points (the static array holds 12 MiB per GPU the
+ * library runs on, kept until the process ends); larger n is CRP_EINVAL with
+ * nothing evaluated.  All calls on one GPU share that array: calls that
+ * overlap on one GPU (from several contexts or threads) race and must be
+ * serialised by the caller.  Errors: CRP_EINVAL, CRP_ESTATE, CRP_EDEVICE. */
+#define CRP_EVAL_NOALLOC_MAX 262144
+crp_status crp_eval_field_noalloc(crp_ctx* ctx, int64_t n, const double* pos_m, double* B_T,
+                                  int32_t mode);
+
 /* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
  * A new context starts with {128, 0, 4, CRP_LAYOUT_LINEAR}.
  * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra

@@ -23,6 +23,7 @@ FP64, MIX = 0, 1
 FIELD_GRID, FIELD_NEURAL, FIELD_ANALYTIC = 0, 1, 2
 EVAL_NEURAL = 16 + FIELD_NEURAL
 EVAL_ANALYTIC = 16 + FIELD_ANALYTIC
+EVAL_NOALLOC_MAX = 262144          # CRP_EVAL_NOALLOC_MAX
 F32, F64 = 0, 1
 LAYOUT_LINEAR, LAYOUT_CORNER = 0, 1
 ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR, BOUNDARY = 0, 1, 2, 3, 4
@@ -34,7 +35,8 @@ EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_field_pat
            "crp_propagate", "crp_read_finished", "crp_read_neutral", "crp_read_trajectory",
            "crp_set_observables", "crp_observe", "crp_read_observables", "crp_lens_build",
            "crp_lens_read", "crp_lens_apply", "crp_peek_pending",
-           "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_set_launch",
+           "crp_counts", "crp_reset_counters", "crp_eval_field", "crp_eval_field_noalloc",
+           "crp_set_launch",
            "crp_get_launch", "crp_tune", "crp_last_timing", "crp_gather_ceiling",
            "crp_snapshot", "crp_restore",
            "crp_free", "crp_nf_init", "crp_nf_get_params", "crp_nf_loss_grad", "crp_nf_train",
@@ -163,6 +165,7 @@ def load():
         "crp_counts": ([vp, _P(Counters)], C.c_int),
         "crp_reset_counters": ([vp], C.c_int),
         "crp_eval_field": ([vp, i64, vp, vp, i32, i32], C.c_int),
+        "crp_eval_field_noalloc": ([vp, i64, vp, vp, i32], C.c_int),
         "crp_set_launch": ([vp, _P(Launch)], C.c_int),
         "crp_get_launch": ([vp, _P(Launch)], C.c_int),
         "crp_tune": ([vp, i64, C.c_char_p, _P(Launch), _P(dbl)], C.c_int),
@@ -556,6 +559,20 @@ class Context:
             out = np.empty_like(pos)
         self._check(self.L.crp_eval_field(self.h, pos.shape[0], _ptr(pos), _ptr(out), mode,
                                           int(on_dev)))
+        return out
+
+    def eval_field_noalloc(self, pos, mode=FP64, out=None):
+        """crp_eval_field for host arrays through the library's static staging
+        (no device allocation; at most EVAL_NOALLOC_MAX points).  `out`, if
+        given, is a C-contiguous float64 [n][3] array written in place."""
+        pos = _host(np.asarray(pos, np.float64).reshape(-1, 3), np.float64, (None, 3), "pos")
+        if out is None:
+            out = np.empty_like(pos)
+        elif not (isinstance(out, np.ndarray) and out.dtype == np.float64 and
+                  out.flags.c_contiguous and out.shape == pos.shape):
+            raise ValueError("out: a C-contiguous float64 [n][3] host array is expected")
+        self._check(self.L.crp_eval_field_noalloc(self.h, pos.shape[0], _ptr(pos), _ptr(out),
+                                                  mode))
         return out
 
     # -- launch shape / tuning / timing ---------------------------------------

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -626,6 +627,86 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
 
 }  // namespace
 
+// -------------------------------------------------------------------------
+// Field evaluation shared by crp_eval_field and crp_eval_field_noalloc.
+// -------------------------------------------------------------------------
+static crp_status eval_field_check(crp_ctx* ctx, int32_t mode, const char* who)
+{
+    const bool neural = mode == 16 + CRP_FIELD_NEURAL;
+    const bool analytic = mode == 16 + CRP_FIELD_ANALYTIC;
+    if (!(mode == CRP_FP64 || mode == CRP_MIX || neural || analytic))
+        return fail(ctx, CRP_EINVAL, std::string(who) + ": bad mode");
+    if (analytic ? !ctx->has_analytic : !ctx->has_grid)
+        return fail(ctx, CRP_ESTATE, std::string(who) + ": no such field set");
+    if (neural && !ctx->nf)
+        return fail(ctx, CRP_ESTATE, std::string(who) + ": neural field not initialised");
+    return CRP_OK;
+}
+
+// Launches the evaluation of n device positions into device B on the
+// context stream (mode checked by eval_field_check).
+static crp_status eval_field_launch(crp_ctx* ctx, int64_t n, const double* dpos, double* dB,
+                                    int32_t mode)
+{
+    if (mode == 16 + CRP_FIELD_ANALYTIC) {
+        k_eval_analytic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->ana, n, dpos, dB);
+        return CRP_OK;
+    }
+    if (mode == 16 + CRP_FIELD_NEURAL)
+        return nf_eval(ctx->nf, make_view(ctx), n, dpos, dB, ctx->stream);
+    GridView g = make_view(ctx);
+    const int md = mode == CRP_MIX ? MODE_MIX : MODE_FP64;
+    if (ctx->nest.np > 0 && ctx->grid_dtype == CRP_F64)
+        k_eval_nested<double><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n, dpos,
+                                                                           dB, md);
+    else if (ctx->nest.np > 0)
+        k_eval_nested<float><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n, dpos,
+                                                                          dB, md);
+    else if (ctx->grid_dtype == CRP_F64)
+        k_eval_field<double, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+    else if (ctx->launch.layout == CRP_LAYOUT_CORNER && ctx->corner)
+        k_eval_field<float, 1><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+    else
+        k_eval_field<float, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
+    return CRP_OK;
+}
+
+// -------------------------------------------------------------------------
+// Static staging for crp_eval_field_noalloc: positions [CRP_EVAL_NOALLOC_MAX][3]
+// then fields [CRP_EVAL_NOALLOC_MAX][3], FP64 (12 MiB).  Every GPU the library
+// runs on holds its own copy until the process ends.  In host code the array's
+// name is not a device address: its address on each device is looked up once,
+// at crp_create with that device current, and only that address is used.
+// -------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[6 * CRP_EVAL_NOALLOC_MAX];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex scratch_mu;
+static double* scratch_dev[SCRATCH_MAX_DEVICES];
+
+// Looks up this device's copy of `scratch` (the device must be current).
+static hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device])
+        return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess)
+        scratch_dev[device] = (double*)p;
+    return e;
+}
+
+static double* scratch_ptr(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_dev[device];
+}
+
 extern "C" {
 
 const char* crp_last_error(const crp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
@@ -678,6 +759,9 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
         return bail(CRP_EDEVICE, "hipGetDeviceProperties", e);
     ctx->num_cus = prop.multiProcessorCount;
     ctx->device_name = prop.gcnArchName;
+    e = scratch_setup(c.device);
+    if (e != hipSuccess)
+        return bail(CRP_EDEVICE, "static scratch lookup (hipGetSymbolAddress)", e);
     const int64_t qc = c.queue_capacity;
     for (int b = 0; b < 2; ++b) {
         size_t bytes = queue_layout(nullptr, qc, nullptr);
@@ -1498,14 +1582,9 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
         return CRP_EINVAL;
     if (n == 0)
         return CRP_OK;
-    const bool neural = mode == 16 + CRP_FIELD_NEURAL;
-    const bool analytic = mode == 16 + CRP_FIELD_ANALYTIC;
-    if (!(mode == CRP_FP64 || mode == CRP_MIX || neural || analytic))
-        return fail(ctx, CRP_EINVAL, "eval_field: bad mode");
-    if (analytic ? !ctx->has_analytic : !ctx->has_grid)
-        return fail(ctx, CRP_ESTATE, "eval_field: no such field set");
-    if (neural && !ctx->nf)
-        return fail(ctx, CRP_ESTATE, "eval_field: neural field not initialised");
+    crp_status st = eval_field_check(ctx, mode, "eval_field");
+    if (st != CRP_OK)
+        return st;
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     const double* dpos = pos;
     double* dB = B;
@@ -1518,33 +1597,13 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
     hipError_t e = on_device ? hipSuccess
                              : hipMemcpyAsync((void*)dpos, pos, n * 24, hipMemcpyHostToDevice,
                                               ctx->stream);
-    if (e != hipSuccess) {
-        // the copy failed: nothing launched; the staging buffer is freed below
-    } else if (analytic) {
-        k_eval_analytic<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(ctx->ana, n, dpos, dB);
-        e = hipGetLastError();
-    } else if (neural) {
-        crp_status st = nf_eval(ctx->nf, make_view(ctx), n, dpos, dB, ctx->stream);
+    if (e == hipSuccess) {
+        st = eval_field_launch(ctx, n, dpos, dB, mode);
         if (st != CRP_OK) {
             if (stage)
                 (void)hipFree(stage);
             return fail(ctx, st, "eval_field: neural evaluation failed");
         }
-    } else {
-        GridView g = make_view(ctx);
-        const int md = mode == CRP_MIX ? MODE_MIX : MODE_FP64;
-        if (ctx->nest.np > 0 && ctx->grid_dtype == CRP_F64)
-            k_eval_nested<double><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n,
-                                                                               dpos, dB, md);
-        else if (ctx->nest.np > 0)
-            k_eval_nested<float><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, ctx->nest, n,
-                                                                              dpos, dB, md);
-        else if (ctx->grid_dtype == CRP_F64)
-            k_eval_field<double, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
-        else if (ctx->launch.layout == CRP_LAYOUT_CORNER && ctx->corner)
-            k_eval_field<float, 1><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
-        else
-            k_eval_field<float, 0><<<blocks_for(n, 256), 256, 0, ctx->stream>>>(g, n, dpos, dB, md);
         e = hipGetLastError();
     }
     if (e == hipSuccess && !on_device)
@@ -1555,6 +1614,43 @@ crp_status crp_eval_field(crp_ctx* ctx, int64_t n, const double* pos, double* B,
         (void)hipFree(stage);
     if (e != hipSuccess)
         return fail(ctx, CRP_EDEVICE, std::string("eval_field: ") + hipGetErrorString(e));
+    return CRP_OK;
+}
+
+crp_status crp_eval_field_noalloc(crp_ctx* ctx, int64_t n, const double* pos, double* B,
+                                  int32_t mode)
+{
+    if (!ctx || n < 0 || (n > 0 && (!pos || !B)))
+        return CRP_EINVAL;
+    if (n > CRP_EVAL_NOALLOC_MAX)
+        return fail(ctx, CRP_EINVAL,
+                    "eval_field_noalloc: more than CRP_EVAL_NOALLOC_MAX (262144) points");
+    if (n == 0)
+        return CRP_OK;
+    crp_status st = eval_field_check(ctx, mode, "eval_field_noalloc");
+    if (st != CRP_OK)
+        return st;
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    // the device's copy of the static staging array, looked up at crp_create
+    double* sp = scratch_ptr(ctx->cfg.device);
+    if (!sp)
+        return fail(ctx, CRP_EDEVICE, "eval_field_noalloc: static scratch not set up");
+    double* dpos = sp;
+    double* dB = sp + 3 * CRP_EVAL_NOALLOC_MAX;
+    hipError_t e = hipMemcpyAsync(dpos, pos, n * 24, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        st = eval_field_launch(ctx, n, dpos, dB, mode);
+        if (st != CRP_OK)
+            return fail(ctx, st, "eval_field_noalloc: neural evaluation failed");
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B, dB, n * 24, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return fail(ctx, CRP_EDEVICE,
+                    std::string("eval_field_noalloc: ") + hipGetErrorString(e));
     return CRP_OK;
 }
 
