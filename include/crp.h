@@ -437,6 +437,13 @@ crp_status crp_nf_get_params(crp_ctx* ctx, float* params);
  * b_scale; writes out [n][3] and grad [CRP_NF_NPARAM]; loss = mean |out - t|^2. */
 crp_status crp_nf_loss_grad(crp_ctx* ctx, int64_t n, const double* pos_m, const float* target,
                             float* out, float* grad, double* loss);
+/* One Adam update (Kingma & Ba 2015: beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrections with the context's step count, which crp_nf_init resets and
+ * every update advances) of the FP32 masters with a caller-given gradient:
+ * grad [CRP_NF_NPARAM] host FP32 in the flat parameter order, e.g. the sum of
+ * per-GPU crp_nf_loss_grad gradients in data-parallel training.  Errors:
+ * CRP_EINVAL (non-finite gradient or lr <= 0; nothing changed), CRP_ESTATE. */
+crp_status crp_nf_adam_step(crp_ctx* ctx, const float* grad, double lr);
 /* Trains on points drawn uniformly in one period of the grid with targets from
  * the grid's trilinear field: steps Adam updates (beta1 0.9, beta2 0.999,
  * eps 1e-8) of batch points, cosine learning rate lr0 -> lr1.  loss_out[steps]

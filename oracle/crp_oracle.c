@@ -180,6 +180,10 @@ static double level_value(const or_grid* g, int level, int64_t i, int64_t j, int
 
 static void field_fp64(const or_grid* g, const double p[3], double B[3])
 {
+    if (g->field_cb) {
+        g->field_cb(g->cb_user, p, B);
+        return;
+    }
     if (g->analytic) {
         field_analytic(g->analytic, p, B);
         return;
@@ -208,9 +212,9 @@ static void field_fp64(const or_grid* g, const double p[3], double B[3])
 /* Precision form: offsets in FP64, weights and accumulation in FP32. */
 static void field_mix(const or_grid* g, const double p[3], float B[3])
 {
-    if (g->analytic) {      /* the analytic field in FP64, rounded once */
+    if (g->analytic || g->field_cb) {   /* the FP64 field, rounded once */
         double b[3];
-        field_analytic(g->analytic, p, b);
+        field_fp64(g, p, b);
         for (int c = 0; c < 3; ++c)
             B[c] = (float)b[c];
         return;
@@ -902,6 +906,8 @@ int oracle_propagate_traj(const or_config* cfg, const or_grid* grid, const or_ta
 #ifdef _OPENMP
     if (nthreads <= 0)
         nthreads = omp_get_max_threads();
+    if (grid->field_cb)     /* the caller's field function is not thread-safe */
+        nthreads = 1;
 #pragma omp parallel num_threads(nthreads)
 #endif
     {

@@ -87,6 +87,11 @@ typedef struct {
     int32_t n_patches;      /* refinement patches (0: a single-resolution grid) */
     int32_t pad2_;
     const or_patch* patches;
+    /* non-NULL: a caller-supplied field instead of the grid (and of
+     * `analytic`): B (T, FP64) at one position p (m); the precision form
+     * rounds it to FP32.  A propagation with it runs on one thread. */
+    void (*field_cb)(void* user, const double p[3], double B[3]);
+    void* cb_user;
 } or_grid;
 
 typedef struct {

@@ -54,11 +54,14 @@ class Patch(C.Structure):
                 ("refine", C.c_int32), ("pad_", C.c_int32)]
 
 
+FIELD_CB = C.CFUNCTYPE(None, C.c_void_p, _P(C.c_double), _P(C.c_double))
+
+
 class Grid(C.Structure):
     _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("pad_", C.c_int32),
                 ("n", C.c_int64 * 3), ("spacing", C.c_double), ("origin", C.c_double * 3),
                 ("analytic", _P(Analytic)), ("n_patches", C.c_int32), ("pad2_", C.c_int32),
-                ("patches", _P(Patch))]
+                ("patches", _P(Patch)), ("field_cb", FIELD_CB), ("cb_user", C.c_void_p)]
 
 
 class Tables(C.Structure):
@@ -185,6 +188,28 @@ class AnalyticRef:
             self.s.n[a] = 1
         self.s.spacing = 1.0
         self.s.analytic = C.pointer(self.a)
+
+
+class FieldRef:
+    """A Python function as the field source: fn(p) -> B for one position p
+    (numpy [3], metres) returning [3] tesla in FP64.  Propagation with it runs
+    on one thread."""
+
+    def __init__(self, fn):
+        self.fn = fn
+
+        def cb(_user, p, B):
+            b = fn(np.array([p[0], p[1], p[2]]))
+            B[0], B[1], B[2] = float(b[0]), float(b[1]), float(b[2])
+
+        self.cb = FIELD_CB(cb)          # kept alive with this object
+        self.s = Grid()
+        self.s.data = None
+        self.s.dtype = GRID_F64
+        for a in range(3):
+            self.s.n[a] = 1
+        self.s.spacing = 1.0
+        self.s.field_cb = self.cb
 
 
 class TablesRef:

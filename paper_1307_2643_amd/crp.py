@@ -39,7 +39,8 @@ EXPORTS = ("crp_create", "crp_destroy", "crp_set_field_grid", "crp_set_field_pat
            "crp_set_launch",
            "crp_get_launch", "crp_tune", "crp_last_timing", "crp_gather_ceiling",
            "crp_snapshot", "crp_restore",
-           "crp_free", "crp_nf_init", "crp_nf_get_params", "crp_nf_loss_grad", "crp_nf_train",
+           "crp_free", "crp_nf_init", "crp_nf_get_params", "crp_nf_loss_grad", "crp_nf_adam_step",
+           "crp_nf_train",
            "crp_last_error")
 
 
@@ -177,6 +178,7 @@ def load():
         "crp_nf_init": ([vp, vp, vp, dbl], C.c_int),
         "crp_nf_get_params": ([vp, vp], C.c_int),
         "crp_nf_loss_grad": ([vp, i64, vp, vp, vp, vp, _P(dbl)], C.c_int),
+        "crp_nf_adam_step": ([vp, vp, dbl], C.c_int),
         "crp_nf_train": ([vp, i64, i64, dbl, dbl, C.c_uint64, vp], C.c_int),
         "crp_last_error": ([vp], C.c_char_p),
     }
@@ -639,6 +641,10 @@ class Context:
         self._check(self.L.crp_nf_loss_grad(self.h, pos.shape[0], _ptr(pos), _ptr(t), _ptr(out),
                                             _ptr(g), C.byref(loss)))
         return out, g, loss.value
+
+    def nf_adam_step(self, grad, lr):
+        g = _host(grad, np.float32, (NF_NPARAM,), "grad")
+        self._check(self.L.crp_nf_adam_step(self.h, _ptr(g), float(lr)))
 
     def nf_train(self, steps, batch, lr0, lr1, seed):
         losses = np.empty(max(int(steps), 1), np.float32)

@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
             int64_t p = base + 32 * cb + (lane & 31);
             pt[cb] = p;
             const int64_t q = p < n ? p : n - 1;
-            nf_embed(v.freq, xh[3 * q], xh[3 * q + 1], xh[3 * q + 2], g, a[cb]);
+            nf_embed_fp64(v.freq, xh[3 * q], xh[3 * q + 1], xh[3 * q + 2], g, a[cb]);
         }
         auto store = [&](int L, const bf16x8 h[2][8]) {
 #pragma unroll
@@ -641,6 +641,38 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
     return hipGetLastError();
 }
 
+// One Adam step of the masters with the gradient in nf->grad (step count
+// t + 1 for the bias corrections, formed in FP64 and rounded once), then the
+// bf16 images are repacked.
+static hipError_t nf_adam_launch(NeuralField* nf, double lr)
+{
+    nf->t += 1;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)nf->t));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)nf->t));
+    k_nf_adam<<<(NF_NPARAM + 255) / 256, 256, 0, nf->stream>>>(nf->master, nf->grad, nf->am,
+                                                                 nf->av, NF_NPARAM, (float)lr, c1,
+                                                                 c2);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = nf_pack(nf);
+    return e;
+}
+
+crp_status nf_adam_step(NeuralField* nf, const float* grad, double lr, std::string& err)
+{
+    hipError_t e = hipMemcpyAsync(nf->grad, grad, NF_NPARAM * 4, hipMemcpyHostToDevice,
+                                  nf->stream);
+    if (e == hipSuccess)
+        e = nf_adam_launch(nf, lr);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(nf->stream);
+    if (e != hipSuccess) {
+        err = std::string("nf_adam_step: ") + hipGetErrorString(e);
+        return CRP_EDEVICE;
+    }
+    return CRP_OK;
+}
+
 crp_status nf_loss_grad(NeuralField* nf, const GridView& g, int64_t n, const double* pos,
                         const float* target, float* out, float* grad, double* loss,
                         std::string& err)
@@ -700,18 +732,9 @@ crp_status nf_train(NeuralField* nf, const GridView& g, int64_t steps, int64_t b
         if (e == hipSuccess)
             e = nf_fwd_bwd(nf, G, batch);
         if (e == hipSuccess) {
-            nf->t += 1;
             const double frac = steps > 1 ? (double)it / (double)(steps - 1) : 1.0;
-            const double lr = lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * frac));
-            const float c1 = (float)(1.0 - std::pow(0.9, (double)nf->t));
-            const float c2 = (float)(1.0 - std::pow(0.999, (double)nf->t));
-            k_nf_adam<<<(NF_NPARAM + 255) / 256, 256, 0, s>>>(nf->master, nf->grad, nf->am,
-                                                                nf->av, NF_NPARAM, (float)lr, c1,
-                                                                c2);
-            e = hipGetLastError();
+            e = nf_adam_launch(nf, lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * frac)));
         }
-        if (e == hipSuccess)
-            e = nf_pack(nf);
         if (e == hipSuccess && loss_out)
             e = hipMemcpyAsync(&losses[(size_t)it], nf->loss, 8, hipMemcpyDeviceToHost, s);
     }

@@ -25,6 +25,7 @@ crp_status nf_loss_grad(NeuralField* nf, const GridView& g, int64_t n, const dou
                         std::string& err);
 crp_status nf_train(NeuralField* nf, const GridView& g, int64_t steps, int64_t batch, double lr0,
                     double lr1, uint64_t seed, float* loss_out, std::string& err);
+crp_status nf_adam_step(NeuralField* nf, const float* grad, double lr, std::string& err);
 void nf_prop_params(const NeuralField* nf, const GridView& g, NFProp* p);
 
 }  // namespace crp

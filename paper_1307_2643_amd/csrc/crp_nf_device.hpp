@@ -131,6 +131,34 @@ __device__ __attribute__((always_inline)) inline void nf_embed(const float* freq
     }
 }
 
+// Fourier features for training, in FP64: the phase F . xhat (integer F, FP32
+// xhat: each product exact in FP64) reduced to its fraction in [0, 1) (exact),
+// cos and sin of 2 pi times it by the FP64 library (sincospi), then rounded to
+// bf16.  The features are then within an FP64 rounding of their exact values,
+// so their bf16 roundings are those of the exact features (the stepper's
+// FP32 phase and hardware sin / cos above move a feature by up to ~1e-5).
+__device__ __attribute__((always_inline)) inline void nf_embed_fp64(const float* freq, float x0,
+                                                                     float x1, float x2, int g,
+                                                                     bf16x8 act[8])
+{
+    freq = nf_launder(freq);
+    const double d0 = x0, d1 = x1, d2 = x2;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int jj = 16 * m + 8 * g + j;
+            double ph = ((double)freq[3 * jj] * d0 + (double)freq[3 * jj + 1] * d1) +
+                        (double)freq[3 * jj + 2] * d2;
+            ph = ph - floor(ph);
+            double sv, cv;
+            sincospi(2.0 * ph, &sv, &cv);
+            act[m][j] = (__bf16)cv;
+            act[m + 4][j] = (__bf16)sv;
+        }
+    }
+}
+
 // One hidden layer for the two column blocks: out = relu(W in + b) as bf16.
 // If store_pre is given, it receives the activation (bf16) for later use.
 __device__ __attribute__((always_inline)) inline void nf_layer(const __bf16* wimg, const float* bias, const bf16x8 in[2][8],

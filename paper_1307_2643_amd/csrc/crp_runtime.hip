@@ -2068,5 +2068,18 @@ crp_status crp_nf_train(crp_ctx* ctx, int64_t steps, int64_t batch, double lr0, 
     return nf_train(ctx->nf, make_view(ctx), steps, batch, lr0, lr1, seed, loss_out, ctx->err);
 }
 
+crp_status crp_nf_adam_step(crp_ctx* ctx, const float* grad, double lr)
+{
+    if (!ctx || !grad || !(lr > 0) || !std::isfinite(lr))
+        return CRP_EINVAL;
+    if (!ctx->nf)
+        return fail(ctx, CRP_ESTATE, "nf: not initialised");
+    for (int i = 0; i < CRP_NF_NPARAM; ++i)
+        if (!std::isfinite(grad[i]))
+            return fail(ctx, CRP_EINVAL, "nf_adam_step: non-finite gradient");
+    HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    return nf_adam_step(ctx->nf, grad, lr, ctx->err);
+}
+
 }  // extern "C"
 
