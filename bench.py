@@ -755,7 +755,8 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
            "kernel_share_of_wall": sum(per_batch) * 1e-3 / wall, "launch": tuned,
            "finished": cnt["finished"], "observed": cnt["observed"],
            "charged_sec": cnt["charged_sec"], "neutral_sec": cnt["neutral_sec"],
-           "queue_dropped": cnt["queue_dropped"], "neutral_dropped": cnt["neutral_dropped"]}
+           "queue_deferred": cnt["queue_deferred"],
+           "neutral_deferred": cnt["neutral_deferred"]}
     log(f"[bench] batching form: {out['steps_per_s']:.4e} steps/s over {nb * per} candidates "
         f"({wall:.1f} s)")
     return out

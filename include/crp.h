@@ -41,13 +41,14 @@ extern "C" {
 typedef enum {
     CRP_OK = 0,
     CRP_INCOMPLETE = 1,   /* propagate: cycle budget used up with candidates left */
-    CRP_EOVERFLOW = 2,    /* read: more records remain than fit in the buffer    */
+    CRP_EOVERFLOW = 2,    /* read: more records remain than fit in the buffer;
+                             propagate: stopped with the neutral-record buffer
+                             full (read neutral records, then propagate again) */
     CRP_EINVAL = -1,      /* invalid argument (nothing was changed)               */
     CRP_EDEVICE = -2,     /* HIP runtime error                                    */
     CRP_ENOMEM = -3,      /* device allocation failed                             */
     CRP_ESTATE = -4,      /* call not valid in this state (e.g. no field/tables)  */
-    CRP_EQUEUE = -5       /* queue capacity exceeded (inject, or spawned secondaries
-                             dropped during propagate; see crp_counters)          */
+    CRP_EQUEUE = -5       /* inject: queue capacity exceeded                       */
 } crp_status;
 
 enum { CRP_FP64 = 0, CRP_MIX = 1 };                     /* stage precision        */
@@ -77,7 +78,10 @@ typedef struct {
     double obs_center[3];     /* observer sphere centre, m */
     double obs_radius;        /* observer radius, m; 0 disables the observer */
     uint64_t seed;            /* Philox4x64-10 key word 0 */
-    int64_t queue_capacity;   /* max pending + spawned candidates per propagate (> 0) */
+    int64_t queue_capacity;   /* initial work-queue capacity: pending + spawned
+                                 candidates (> 0).  Injection beyond it is refused;
+                                 secondaries that do not fit make the queue double
+                                 during crp_propagate (their parents wait) */
     int64_t neutral_capacity; /* max undrained neutral records (> 0) */
     int32_t charge_sign;      /* +1 (or 0): forward tracking; -1: backtracking, i.e. the
                                  antiparticle (charge -Z) from the observer along the
@@ -181,7 +185,12 @@ typedef struct {
     int64_t steps, attempts, rejects, forced;
     int64_t events, null_events, inter_pi, inter_n;
     int64_t charged_sec, neutral_sec;
-    int64_t queue_dropped, neutral_dropped;
+    int64_t queue_deferred;   /* interactions whose secondary found the queue full:
+                                 the parent waited (parked just before the
+                                 interaction) and finished its cycle after the
+                                 queue grew; nothing is dropped */
+    int64_t neutral_deferred; /* interactions that found the neutral-record buffer
+                                 full: the parent waits until the records are read */
     int64_t pending;          /* candidates waiting for the next propagate */
     int64_t finished_unread, neutral_unread;
     int64_t lane_slots;       /* 64 x wave iterations of the propagation kernel:
@@ -274,10 +283,16 @@ crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t
 /* Propagates every pending candidate, and every secondary spawned meanwhile,
  * until it stops or has run max_cycles cycles in this call (max_cycles <= 0:
  * no limit).  Runs on the context stream and returns after it completes.
- * Returns CRP_INCOMPLETE if candidates remain pending (call again to
- * continue; the result is identical to an uninterrupted run).
- * Errors: CRP_ESTATE (no field or tables), CRP_EQUEUE (secondaries dropped
- * for lack of queue capacity), CRP_EDEVICE. */
+ * Nothing is dropped: a candidate whose interaction product (a secondary, or
+ * a neutral record) finds no slot keeps its state from just before the
+ * interaction and waits; for secondaries the queue (and the finished-record
+ * buffer) doubles and the run goes on (with a cycle budget, the next call goes
+ * on).  Returns CRP_INCOMPLETE if candidates remain pending (call again to
+ * continue; the result is identical to an uninterrupted run), CRP_EOVERFLOW if
+ * candidates wait because the neutral-record buffer is full (read neutral
+ * records, then call again; the result is again identical).
+ * Errors: CRP_ESTATE (no field or tables), CRP_ENOMEM (the queue could not
+ * grow; the pending work is kept), CRP_EDEVICE. */
 crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles);
 
 /* Copies up to cap finished records into out and removes them from the

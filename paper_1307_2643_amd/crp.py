@@ -115,7 +115,7 @@ class LensSpec(C.Structure):
 
 COUNT_FIELDS = ("finished", "observed", "max_traj", "energy_floor", "steps", "attempts",
                 "rejects", "forced", "events", "null_events", "inter_pi", "inter_n",
-                "charged_sec", "neutral_sec", "queue_dropped", "neutral_dropped", "pending",
+                "charged_sec", "neutral_sec", "queue_deferred", "neutral_deferred", "pending",
                 "finished_unread", "neutral_unread", "lane_slots", "boundary", "traj_points",
                 "traj_dropped", "traj_unread")
 
@@ -410,7 +410,10 @@ class Context:
 
     # -- the hot path ---------------------------------------------------------
     def propagate(self, max_cycles=0):
-        """Returns True when complete, False when candidates remain pending."""
+        """Returns True when complete, False when candidates remain pending.
+        Raises CrpError with status EOVERFLOW when candidates wait for room in
+        the full neutral-record buffer: read neutral records, then call again
+        (nothing is lost)."""
         st = self._check(self.L.crp_propagate(self.h, int(max_cycles)), ok=(OK, INCOMPLETE))
         return st == OK
 

@@ -54,7 +54,7 @@ struct DevCounters {
     unsigned long long events, null_events, inter_pi, inter_n;
     unsigned long long charged_sec, neutral_sec;
     unsigned long long finished, observed, max_traj, energy_floor;
-    unsigned long long queue_dropped, neutral_dropped;
+    unsigned long long queue_deferred, neutral_deferred;   // interactions that found no slot
     unsigned long long lane_slots;          // 64 x wave iterations
     unsigned long long boundary;            // stopped by the spherical boundary
     unsigned long long traj_n;              // trajectory-point append cursor (may pass the

@@ -16,6 +16,16 @@
 namespace crp {
 
 enum { LIM_CTRL = 0, LIM_TRAJ = 1, LIM_INTER = 2, LIM_LOSS = 3, LIM_OBS = 4 };
+// interaction channel chosen in a cycle: none due, a null event (no channel
+// open at this energy), pion-like (neutral record), nucleon loss (secondary)
+enum { CH_NONE = -1, CH_PI = 0, CH_N = 1, CH_NULL = 2 };
+
+// A parked candidate whose cycle stopped just before its interaction (no
+// slot for the product) carries -(1 + step-limit flag) as its optical depth:
+// a stored optical depth is otherwise always positive (an interaction resets
+// it to at least 2^-24, and without one it stayed above zero).
+__device__ inline double event_due_marker(int flag) { return -1.0 - (double)flag; }
+__device__ inline int event_due_flag(double tau) { return (int)(-tau) - 1; }
 enum { ST_ACTIVE = 0, ST_OBSERVED = 1, ST_MAX_TRAJ = 2, ST_ENERGY_FLOOR = 3, ST_BOUNDARY = 4 };
 
 struct Cand {
@@ -53,7 +63,7 @@ __device__ inline void store_cand(const QueueSoA& q, int64_t i, const Cand& c)
 // with an LDS atomic where they happen.
 enum {
     WC_STEPS = 0, WC_ATTEMPTS, WC_REJECTS, WC_FORCED, WC_EVENTS, WC_NULL, WC_PI, WC_N,
-    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDROP, WC_NDROP, WC_LANES, WC_BOUNDARY,
+    WC_FINISHED, WC_OBSERVED, WC_MAXTRAJ, WC_EFLOOR, WC_QDEFER, WC_NDEFER, WC_LANES, WC_BOUNDARY,
     WC_COUNT
 };
 enum : uint32_t { EV_ATTEMPT = 1u << 0, EV_ACCEPT = 1u << 1, EV_FORCED = 1u << 2, EV_FIN = 1u << 3 };
@@ -86,8 +96,8 @@ __device__ inline unsigned long long* count_dst(DevCounters* cnt, int i)
     case WC_OBSERVED: return &cnt->observed;
     case WC_MAXTRAJ: return &cnt->max_traj;
     case WC_EFLOOR: return &cnt->energy_floor;
-    case WC_QDROP: return &cnt->queue_dropped;
-    case WC_NDROP: return &cnt->neutral_dropped;
+    case WC_QDEFER: return &cnt->queue_deferred;
+    case WC_NDEFER: return &cnt->neutral_deferred;
     case WC_LANES: return &cnt->lane_slots;
     default: return &cnt->boundary;
     }
@@ -317,6 +327,9 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
     double h = 0.0, kappa = 0.0;
     int64_t slot = 0;
     bool active = false, fresh = true;
+    // the lane holds a candidate whose last cycle stopped just before an
+    // interaction for want of an output slot: it finishes that cycle first
+    bool resume = false;
     // field at the current position, kept for the retry after a rejection
     using BT = typename DirType<MODE>::T;
     BT b1[3] = {0, 0, 0};
@@ -389,11 +402,14 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                 S.nsteps[t] = q.nsteps[slot];
                 S.nrej[t] = q.nrej[slot];
                 S.cycles[t] = 0u;
-                S.azf[t] = pack_azf(q.A[slot], q.Z[slot], LIM_CTRL);
+                resume = S.tau[t] < 0.0;
+                // a resumed cycle keeps the step limit its step had
+                S.azf[t] = pack_azf(q.A[slot], q.Z[slot],
+                                    resume ? event_due_flag(S.tau[t]) : LIM_CTRL);
                 if ((unsigned long long)slot >= tail0)
                     q.ready[slot] = 0u;   // clean for the next run
                 active = true;
-                fresh = true;
+                fresh = !resume;
                 reuse = false;
                 pref = false;
             }
@@ -491,19 +507,21 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
         // ---- one Cash-Karp attempt -------------------------------------------
         uint32_t ev = 0u;
         int status = ST_ACTIVE;
-        double dE = 0.0, Esec = 0.0;
-        bool neutral = false, spawn = false, park = false, rec = false;
+        bool park = false, rec = false;
+        // lanes that step in this iteration (a resumed lane only finishes its
+        // interrupted cycle)
+        const bool stepping = active && !resume;
         // with the cooperative gather every lane of the wave takes part in the
         // attempt (idle lanes on a harmless cell); results are used only by
         // busy lanes
         double x5[3];
         UT u5[3];
         double err = 0.0;
-        if (active || wave_gather<LAYOUT> || LAYOUT == 3) {
+        if (stepping || wave_gather<LAYOUT> || LAYOUT == 3) {
             if constexpr (MODE == MODE_FP64) {
                 const double y[6] = {x[0], x[1], x[2], u[0], u[1], u[2]};
                 double y5[6];
-                err = ck_attempt_fp64(F, kappa, y, h, y5, active, reuse, b1);
+                err = ck_attempt_fp64(F, kappa, y, h, y5, stepping, reuse, b1);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     x5[q] = y5[q];
@@ -513,18 +531,22 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                 if constexpr (LAYOUT == 3)
                     err = ck_attempt_mix_rolled(F, kappa, x, u, h, x5, u5);
                 else
-                    err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5, active, reuse, b1);
+                    err = ck_attempt_mix_f(F, kappa, x, u, h, x5, u5, stepping, reuse, b1);
             }
         }
         if constexpr (wave_gather<LAYOUT>) {
             // accepted lanes move to x5: start fetching B(x5) now, so that the
             // loads overlap the rest of the cycle
-            const bool acc = active && (err / sp.tol <= 1.0 || h <= sp.hmin);
+            const bool acc = stepping && (err / sp.tol <= 1.0 || h <= sp.hmin);
             if (__ballot(acc) != 0ull)
                 F.prefetch(x5, acc);
             pref = acc;
         }
-        if (active) {
+        // the cycle's energy and optical depth after the step, and whether an
+        // interaction is due
+        double E = 0.0, tau = 0.0;
+        bool evt = false, cycle = false;
+        if (stepping) {
             ev |= EV_ATTEMPT;
             const double r = err / sp.tol;
             if (r <= 1.0 || h <= sp.hmin) {
@@ -569,7 +591,7 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                 S.L[t] = L;
                 S.nsteps[t] += 1u;
                 // continuous loss: (2,2) Pade form of exp(-beta h)
-                double E = S.E[t];
+                E = S.E[t];
                 {
                     const double z = S.beta[t] * h;
                     const double z2 = z * z;
@@ -578,80 +600,9 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                     E = E * (num / den);
                 }
                 // stochastic interactions: optical-depth clock
-                const uint32_t azf = S.azf[t];
-                const int flag = unpack_flag(azf);
-                double tau = S.tau[t] - S.R[t] * h;
-                if (flag == LIM_INTER || tau <= 0.0) {
-                    const uint32_t m = S.m[t] + 1u;
-                    S.m[t] = m;
-                    const U64x4 w = event_draw(sp.seed, S.id[t], S.lineage[t], m);
-                    int A = unpack_A(azf), Z = unpack_Z(azf);
-                    const double Eint = E;
-                    const Rates ri = species_rates(T, A, Z, Eint);
-                    const double Ptot = ri.rpi + ri.rn;
-                    atomicAdd(&bc[WC_EVENTS], 1ull);
-                    if (Ptot > 0.0) {
-                        const double Uc = unit_uniform(w.w[0]);
-                        if (Uc * Ptot < ri.rpi) {
-                            dE = (sp.kappa_pi * Eint) / (double)A;
-                            E = Eint - dE;
-                            atomicAdd(&bc[WC_PI], 1ull);
-                            neutral = true;
-                        } else {
-                            const int pout = (2 * Z > A) ? 1 : 0;
-                            Esec = Eint / (double)A;
-                            Z -= pout;
-                            A -= 1;
-                            E = Eint - Esec;
-                            S.azf[t] = pack_azf(A, Z, flag);
-                            atomicAdd(&bc[WC_N], 1ull);
-                            spawn = true;
-                        }
-                    } else {
-                        atomicAdd(&bc[WC_NULL], 1ull);
-                    }
-                    // all interaction state is reset after an interaction
-                    tau = optical_depth(w.w[1]);
-                }
-                S.E[t] = E;
-                S.tau[t] = tau;
-                // boundary and observer modules, checked after the cycle
-                const uint32_t cyc = S.cycles[t] + 1u;
-                S.cycles[t] = cyc;
-                if (sp.obs_r > 0.0) {
-                    const double d[3] = {x[0] - sp.obs[0], x[1] - sp.obs[1], x[2] - sp.obs[2]};
-                    if (sqrt(dot3(d, d)) <= sp.obs_r)
-                        status = ST_OBSERVED;
-                }
-                if (status == ST_ACTIVE && sp.bnd_r > 0.0) {
-                    const double d[3] = {x[0] - sp.bnd[0], x[1] - sp.bnd[1], x[2] - sp.bnd[2]};
-                    if (sqrt(dot3(d, d)) >= sp.bnd_r)
-                        status = ST_BOUNDARY;
-                }
-                if (status == ST_ACTIVE && (flag == LIM_TRAJ || L >= S.Lmax[t]))
-                    status = ST_MAX_TRAJ;
-                if (status == ST_ACTIVE && E < sp.e_floor)
-                    status = ST_ENERGY_FLOOR;
-                if (status != ST_ACTIVE) {
-                    ev |= EV_FIN;
-                    atomicAdd(&bc[WC_FINISHED], 1ull);
-                    atomicAdd(&bc[status == ST_OBSERVED   ? WC_OBSERVED
-                                  : status == ST_BOUNDARY ? WC_BOUNDARY
-                                  : status == ST_MAX_TRAJ ? WC_MAXTRAJ
-                                                          : WC_EFLOOR],
-                              1ull);
-                } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
-                    park = true;
-                }
-                // output module: every traj_every-th step and the last one
-                if constexpr (TRAJ) {
-                    // read here rather than kept in scalar registers all loop long
-                    const StepParams& spp = opaque(PP)->sp;
-                    const uint32_t every = spp.traj_every;
-                    if (every != 0u && S.id[t] < spp.traj_ids)
-                        rec = S.nsteps[t] % every == 0u || status != ST_ACTIVE;
-                }
-                fresh = true;
+                tau = S.tau[t] - S.R[t] * h;
+                evt = unpack_flag(S.azf[t]) == LIM_INTER || tau <= 0.0;
+                cycle = true;
             } else {
                 reuse = true;             // same position: b1 holds its field
                 S.nrej[t] += 1u;
@@ -663,6 +614,161 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                     h = sp.hmin;
                 S.azf[t] = (S.azf[t] & 0xffffu) | ((uint32_t)LIM_CTRL << 16);
             }
+        }
+        if (resume) {
+            // the interrupted cycle: its step and loss are done, its
+            // interaction is due (the clock value is replaced after it)
+            E = S.E[t];
+            evt = true;
+            cycle = true;
+            resume = false;
+        }
+
+        // ---- interaction: channel first, then a slot for its product --------
+        // (one atomic per wave for each kind of product); a lane that finds no
+        // slot keeps its state as before the interaction and is parked, to
+        // finish the cycle in a later run: nothing is lost
+        int chan = CH_NONE;
+        U64x4 w = {{0ull, 0ull, 0ull, 0ull}};
+        double dE = 0.0, Esec = 0.0;
+        if (evt) {
+            w = event_draw(sp.seed, S.id[t], S.lineage[t], S.m[t] + 1u);
+            const uint32_t azf = S.azf[t];
+            const Rates ri = species_rates(T, unpack_A(azf), unpack_Z(azf), E);
+            const double Ptot = ri.rpi + ri.rn;
+            chan = !(Ptot > 0.0) ? CH_NULL : (unit_uniform(w.w[0]) * Ptot < ri.rpi ? CH_PI : CH_N);
+        }
+        bool defer = false;
+        unsigned long long slot_n = 0, slot_pi = 0;
+        {
+            const uint64_t mk = __ballot(chan == CH_N);
+            if (mk) {
+                unsigned long long base = 0;
+                if (lane == 0)
+                    base = atomicAdd(&cnt->tail, (unsigned long long)__popcll(mk));
+                slot_n = __shfl(base, 0) + (unsigned long long)lanes_below(mk);
+                defer = chan == CH_N && slot_n >= qcap;
+            }
+        }
+        {
+            const uint64_t mk = __ballot(chan == CH_PI);
+            if (mk) {
+                unsigned long long base = 0;
+                if (lane == 0)
+                    base = atomicAdd(&cnt->neu_n, (unsigned long long)__popcll(mk));
+                slot_pi = __shfl(base, 0) + (unsigned long long)lanes_below(mk);
+                defer = defer || (chan == CH_PI &&
+                                  slot_pi >= (unsigned long long)opaque(PP)->neu.cap);
+            }
+        }
+        if (defer) {
+            atomicAdd(&bc[chan == CH_N ? WC_QDEFER : WC_NDEFER], 1ull);
+            S.E[t] = E;
+            S.tau[t] = event_due_marker(unpack_flag(S.azf[t]));
+            park = true;
+        } else if (cycle) {
+            if (evt) {
+                const uint32_t m = S.m[t] + 1u;
+                S.m[t] = m;
+                const uint32_t azf = S.azf[t];
+                int A = unpack_A(azf), Z = unpack_Z(azf);
+                const double Eint = E;
+                atomicAdd(&bc[WC_EVENTS], 1ull);
+                if (chan == CH_PI) {
+                    dE = (sp.kappa_pi * Eint) / (double)A;
+                    E = Eint - dE;
+                    atomicAdd(&bc[WC_PI], 1ull);
+                    const NeutralSoA& nq = opaque(PP)->neu;
+                    const int64_t k = (int64_t)slot_pi;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        nq.x[a * nq.cap + k] = x[a];
+                        nq.u[a * nq.cap + k] = (double)u[a];
+                    }
+                    nq.E[k] = dE;
+                    nq.id[k] = S.id[t];
+                    nq.lineage[k] = S.lineage[t];
+                    nq.m[k] = m;
+                    nq.chan[k] = 0;
+                } else if (chan == CH_N) {
+                    const int pout = (2 * Z > A) ? 1 : 0;
+                    Esec = Eint / (double)A;
+                    Z -= pout;
+                    A -= 1;
+                    E = Eint - Esec;
+                    S.azf[t] = pack_azf(A, Z, unpack_flag(azf));
+                    atomicAdd(&bc[WC_N], 1ull);
+                    // the secondary proton: a new candidate in the queue
+                    const QueueSoA& q = opaque(PP)->q;
+                    const int64_t k = (int64_t)slot_n;
+                    const uint32_t id = S.id[t];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        q.x[a * q.cap + k] = x[a];
+                        q.u[a * q.cap + k] = (double)u[a];
+                        q.u0[a * q.cap + k] = q.u0[a * q.cap + slot];
+                    }
+                    q.E[k] = Esec;
+                    q.L[k] = S.L[t];
+                    q.Lmax[k] = S.Lmax[t];
+                    q.hctrl[k] = sp.hmin;
+                    q.E0[k] = q.E0[slot];
+                    q.id[k] = id;
+                    q.lineage[k] = m;
+                    q.m[k] = 0u;
+                    q.nsteps[k] = 0u;
+                    q.nrej[k] = 0u;
+                    q.A[k] = 1;
+                    q.Z[k] = 1;
+                    q.tau[k] = optical_depth(event_draw(sp.seed, id, m, 0u).w[1]);
+                    __hip_atomic_store(q.ready + k, 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    atomicAdd(&bc[WC_NULL], 1ull);
+                }
+                // all interaction state is reset after an interaction
+                tau = optical_depth(w.w[1]);
+            }
+            S.E[t] = E;
+            S.tau[t] = tau;
+            // boundary and observer modules, checked after the cycle
+            const uint32_t cyc = S.cycles[t] + 1u;
+            S.cycles[t] = cyc;
+            if (sp.obs_r > 0.0) {
+                const double d[3] = {x[0] - sp.obs[0], x[1] - sp.obs[1], x[2] - sp.obs[2]};
+                if (sqrt(dot3(d, d)) <= sp.obs_r)
+                    status = ST_OBSERVED;
+            }
+            if (status == ST_ACTIVE && sp.bnd_r > 0.0) {
+                const double d[3] = {x[0] - sp.bnd[0], x[1] - sp.bnd[1], x[2] - sp.bnd[2]};
+                if (sqrt(dot3(d, d)) >= sp.bnd_r)
+                    status = ST_BOUNDARY;
+            }
+            if (status == ST_ACTIVE &&
+                (unpack_flag(S.azf[t]) == LIM_TRAJ || S.L[t] >= S.Lmax[t]))
+                status = ST_MAX_TRAJ;
+            if (status == ST_ACTIVE && E < sp.e_floor)
+                status = ST_ENERGY_FLOOR;
+            if (status != ST_ACTIVE) {
+                ev |= EV_FIN;
+                atomicAdd(&bc[WC_FINISHED], 1ull);
+                atomicAdd(&bc[status == ST_OBSERVED   ? WC_OBSERVED
+                              : status == ST_BOUNDARY ? WC_BOUNDARY
+                              : status == ST_MAX_TRAJ ? WC_MAXTRAJ
+                                                      : WC_EFLOOR],
+                          1ull);
+            } else if (max_cycles > 0 && (int64_t)cyc >= max_cycles) {
+                park = true;
+            }
+            // output module: every traj_every-th step and the last one
+            if constexpr (TRAJ) {
+                // read here rather than kept in scalar registers all loop long
+                const StepParams& spp = opaque(PP)->sp;
+                const uint32_t every = spp.traj_every;
+                if (every != 0u && S.id[t] < spp.traj_ids)
+                    rec = S.nsteps[t] % every == 0u || status != ST_ACTIVE;
+            }
+            fresh = true;
         }
         const bool fin = (ev & EV_FIN) != 0u;
 
@@ -689,74 +795,6 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
                         tq.n[k] = S.nsteps[t];
                         tq.A[k] = unpack_A(S.azf[t]);
                     }   // points past the capacity are counted by the host
-                }
-            }
-        }
-        {
-            const uint64_t mk = __ballot(neutral);
-            if (mk) {
-                unsigned long long base = 0;
-                if (lane == 0)
-                    base = atomicAdd(&cnt->neu_n, (unsigned long long)__popcll(mk));
-                base = __shfl(base, 0);
-                if (neutral) {
-                    const NeutralSoA& nq = opaque(PP)->neu;
-                    const unsigned long long i = base + (unsigned long long)lanes_below(mk);
-                    if (i < (unsigned long long)nq.cap) {
-                        const int64_t k = (int64_t)i;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            nq.x[a * nq.cap + k] = x[a];
-                            nq.u[a * nq.cap + k] = (double)u[a];
-                        }
-                        nq.E[k] = dE;
-                        nq.id[k] = S.id[t];
-                        nq.lineage[k] = S.lineage[t];
-                        nq.m[k] = S.m[t];
-                        nq.chan[k] = 0;
-                    } else {
-                        atomicAdd(&bc[WC_NDROP], 1ull);
-                    }
-                }
-            }
-        }
-        {
-            const uint64_t mk = __ballot(spawn);
-            if (mk) {
-                unsigned long long base = 0;
-                if (lane == 0)
-                    base = atomicAdd(&cnt->tail, (unsigned long long)__popcll(mk));
-                base = __shfl(base, 0);
-                if (spawn) {
-                    const unsigned long long i = base + (unsigned long long)lanes_below(mk);
-                    if (i < qcap) {
-                        const QueueSoA& q = opaque(PP)->q;
-                        const int64_t k = (int64_t)i;
-                        const uint32_t id = S.id[t], lin = S.m[t];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            q.x[a * q.cap + k] = x[a];
-                            q.u[a * q.cap + k] = (double)u[a];
-                            q.u0[a * q.cap + k] = q.u0[a * q.cap + slot];
-                        }
-                        q.E[k] = Esec;
-                        q.L[k] = S.L[t];
-                        q.Lmax[k] = S.Lmax[t];
-                        q.hctrl[k] = sp.hmin;
-                        q.E0[k] = q.E0[slot];
-                        q.id[k] = id;
-                        q.lineage[k] = lin;
-                        q.m[k] = 0u;
-                        q.nsteps[k] = 0u;
-                        q.nrej[k] = 0u;
-                        q.A[k] = 1;
-                        q.Z[k] = 1;
-                        q.tau[k] = optical_depth(event_draw(sp.seed, id, lin, 0u).w[1]);
-                        __hip_atomic_store(q.ready + i, 1u, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        atomicAdd(&bc[WC_QDROP], 1ull);
-                    }
                 }
             }
         }

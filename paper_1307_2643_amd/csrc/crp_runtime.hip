@@ -608,8 +608,8 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
         t.inter_n += dc.inter_n;
         t.charged_sec += dc.charged_sec;
         t.neutral_sec += dc.neutral_sec;
-        t.queue_dropped += dc.queue_dropped;
-        t.neutral_dropped += dc.neutral_dropped;
+        t.queue_deferred += dc.queue_deferred;
+        t.neutral_deferred += dc.neutral_deferred;
         t.lane_slots += dc.lane_slots;
         t.boundary += dc.boundary;
         t.traj_points += ctx->traj_unread - traj_before;
@@ -623,6 +623,113 @@ void after_run(crp_ctx* ctx, const DevCounters& dc, bool add_totals)
         std::swap(ctx->q, ctx->park);
         std::swap(ctx->qmem[0], ctx->qmem[1]);
     }
+}
+
+// Copies the first n slots of every array of a queue into another queue
+// (planar vectors plane by plane).
+hipError_t copy_queue_slots(const QueueSoA& d, const QueueSoA& s, int64_t n, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes)
+            e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+    };
+    for (int a = 0; a < 3; ++a) {
+        cp(d.x + a * d.cap, s.x + a * s.cap, n * 8);
+        cp(d.u + a * d.cap, s.u + a * s.cap, n * 8);
+        cp(d.u0 + a * d.cap, s.u0 + a * s.cap, n * 8);
+    }
+    cp(d.E, s.E, n * 8);
+    cp(d.L, s.L, n * 8);
+    cp(d.Lmax, s.Lmax, n * 8);
+    cp(d.hctrl, s.hctrl, n * 8);
+    cp(d.tau, s.tau, n * 8);
+    cp(d.E0, s.E0, n * 8);
+    cp(d.id, s.id, n * 4);
+    cp(d.lineage, s.lineage, n * 4);
+    cp(d.m, s.m, n * 4);
+    cp(d.nsteps, s.nsteps, n * 4);
+    cp(d.nrej, s.nrej, n * 4);
+    cp(d.A, s.A, n * 4);
+    cp(d.Z, s.Z, n * 4);
+    return e;
+}
+
+// Same for the finished-record buffer.
+hipError_t copy_finished_slots(const FinishedSoA& d, const FinishedSoA& s, int64_t n,
+                               hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    auto cp = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes)
+            e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+    };
+    for (int a = 0; a < 3; ++a) {
+        cp(d.x + a * d.cap, s.x + a * s.cap, n * 8);
+        cp(d.u + a * d.cap, s.u + a * s.cap, n * 8);
+        cp(d.u0 + a * d.cap, s.u0 + a * s.cap, n * 8);
+    }
+    cp(d.E, s.E, n * 8);
+    cp(d.L, s.L, n * 8);
+    cp(d.E0, s.E0, n * 8);
+    cp(d.id, s.id, n * 4);
+    cp(d.lineage, s.lineage, n * 4);
+    cp(d.m, s.m, n * 4);
+    cp(d.nsteps, s.nsteps, n * 4);
+    cp(d.nrej, s.nrej, n * 4);
+    cp(d.status, s.status, n * 4);
+    cp(d.A, s.A, n * 4);
+    cp(d.Z, s.Z, n * 4);
+    return e;
+}
+
+// Grows the work queue (and its park buffer) to cap slots and the finished-
+// record buffer to 2 cap, keeping the pending candidates and the unread
+// records.  On failure nothing is changed.
+crp_status grow_queue(crp_ctx* ctx, int64_t cap)
+{
+    if (cap <= ctx->q.cap)
+        return CRP_OK;
+    hipStream_t s = ctx->stream;
+    void* nq[2] = {nullptr, nullptr};
+    void* nf = nullptr;
+    QueueSoA q2, p2;
+    FinishedSoA f2;
+    hipError_t e = hipMalloc(&nq[0], queue_layout(nullptr, cap, nullptr));
+    if (e == hipSuccess)
+        e = hipMalloc(&nq[1], queue_layout(nullptr, cap, nullptr));
+    if (e == hipSuccess)
+        e = hipMalloc(&nf, finished_layout(nullptr, 2 * cap, nullptr));
+    if (e == hipSuccess) {
+        queue_layout((char*)nq[0], cap, &q2);
+        queue_layout((char*)nq[1], cap, &p2);
+        finished_layout((char*)nf, 2 * cap, &f2);
+        e = hipMemsetAsync(q2.ready, 0, cap * sizeof(uint32_t), s);
+    }
+    if (e == hipSuccess)
+        e = hipMemsetAsync(p2.ready, 0, cap * sizeof(uint32_t), s);
+    if (e == hipSuccess)
+        e = copy_queue_slots(q2, ctx->q, ctx->pending, s);
+    if (e == hipSuccess)
+        e = copy_finished_slots(f2, ctx->fin, ctx->fin_unread, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        for (void* p : {nq[0], nq[1], nf})
+            if (p)
+                (void)hipFree(p);
+        return fail(ctx, e == hipErrorOutOfMemory ? CRP_ENOMEM : CRP_EDEVICE,
+                    std::string("queue growth: ") + hipGetErrorString(e));
+    }
+    for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem})
+        (void)hipFree(p);
+    ctx->qmem[0] = nq[0];
+    ctx->qmem[1] = nq[1];
+    ctx->fmem = nf;
+    ctx->q = q2;
+    ctx->park = p2;
+    ctx->fin = f2;
+    return CRP_OK;
 }
 
 }  // namespace
@@ -1177,15 +1284,29 @@ crp_status crp_propagate(crp_ctx* ctx, int64_t max_cycles)
     if (ctx->fin_unread > ctx->q.cap)
         return fail(ctx, CRP_ESTATE, "propagate: read finished records first");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
-    DevCounters dc;
-    const crp_status st = run_kernel(ctx, max_cycles, &dc);
-    if (st != CRP_OK)
-        return st;
-    after_run(ctx, dc, true);
-    if (dc.queue_dropped > 0)
-        return fail(ctx, CRP_EQUEUE,
-                    "propagate: " + std::to_string(dc.queue_dropped) +
-                        " spawned secondaries dropped (queue capacity)");
+    for (;;) {
+        DevCounters dc;
+        const crp_status st = run_kernel(ctx, max_cycles, &dc);
+        if (st != CRP_OK)
+            return st;
+        after_run(ctx, dc, true);
+        if (dc.neutral_deferred > 0)
+            // the neutral records stay until read: the caller drains them
+            return fail(ctx, CRP_EOVERFLOW,
+                        "propagate: the neutral-record buffer is full (" +
+                            std::to_string(dc.neutral_deferred) +
+                            " interactions wait for a slot); read neutral records and "
+                            "propagate again (nothing was lost)");
+        if (dc.queue_deferred == 0)
+            break;
+        // secondaries found the queue full: their parents wait, parked just
+        // before the interaction; double the queue and go on
+        const crp_status g = grow_queue(ctx, 2 * ctx->q.cap);
+        if (g != CRP_OK)
+            return g;
+        if (max_cycles > 0)
+            break;   // a cycle budget ends the call; the next call resumes
+    }
     return ctx->pending > 0 ? CRP_INCOMPLETE : CRP_OK;
 }
 
@@ -1950,10 +2071,24 @@ crp_status crp_restore(crp_ctx* ctx, const void* blob, size_t bytes)
     std::memcpy(&h, blob, sizeof h);
     if (h.magic != kMagic || h.precision != ctx->cfg.precision)
         return fail(ctx, CRP_EINVAL, "restore: not a snapshot of this version / precision");
-    if (h.pending > ctx->q.cap || h.fin_unread > ctx->fin.cap || h.neu_unread > ctx->neu.cap ||
+    if (h.pending < 0 || h.fin_unread < 0 || h.neu_unread < 0 || h.neu_unread > ctx->neu.cap ||
         h.traj_unread > ctx->traj.cap || h.traj_unread < 0)
         return fail(ctx, CRP_EINVAL, "restore: snapshot exceeds this context's capacity");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
+    {
+        // a queue grown in the snapshotted context: grow this one to match
+        int64_t cap = ctx->q.cap;
+        while (cap < h.pending || 2 * cap < h.fin_unread)
+            cap *= 2;
+        const int64_t keep_p = ctx->pending, keep_f = ctx->fin_unread;
+        ctx->pending = 0;           // nothing of this context's own state is kept
+        ctx->fin_unread = 0;
+        const crp_status g = grow_queue(ctx, cap);
+        ctx->pending = keep_p;
+        ctx->fin_unread = keep_f;
+        if (g != CRP_OK)
+            return g;
+    }
     hipStream_t s = ctx->stream;
     const char* p = (const char*)blob + sizeof h;
     const char* end = (const char*)blob + bytes;

@@ -331,18 +331,78 @@ def test_empty_and_capacity(P, mixed_grid):
     with pytest.raises(P.CrpError) as ei:
         ctx.inject(w.make_injection(300))
     assert ei.value.status == -5
-    # a full queue of heavy nuclei that spawn: secondaries beyond capacity are
-    # dropped and reported
-    inj = w.make_injection(256)
+    assert ctx.counts()["pending"] == 0     # all or nothing
+    ctx.close()
+
+
+def _spawning_injection(w, n):
+    """Heavy nuclei above the channels' thresholds: many secondaries (nucleon
+    loss) and neutral records (pion-like) per primary."""
+    inj = w.make_injection(n)
     inj.A[:] = 56
     inj.Z[:] = 26
-    inj.E[:] = 5e20
+    inj.E[:] = np.where(np.arange(n) % 2 == 0, 5e20, 3e21)
+    return inj
+
+
+def _drain_run(P, ctx, inj, max_cycles=0):
+    """Propagates to completion, reading the neutral records whenever the
+    buffer is full; returns (finished, neutral, counters, number of waits)."""
     ctx.inject(inj)
-    with pytest.raises(P.CrpError) as ei:
-        ctx.propagate()
-    assert ei.value.status == -5
-    assert ctx.counts()["queue_dropped"] > 0
-    ctx.close()
+    fins, neus, waits = [], [], 0
+    while True:
+        try:
+            done = ctx.propagate(max_cycles)
+        except P.CrpError as e:
+            assert e.status == P.EOVERFLOW, e
+            waits += 1
+            done = False
+        fins.append(ctx.read_finished())
+        neus.append(ctx.read_neutral())
+        if done:
+            break
+    fin = {k: np.concatenate([f[k] for f in fins]) for k in fins[0]}
+    neu = {k: np.concatenate([n[k] for n in neus]) for k in neus[0]}
+    return fin, neu, ctx.counts(), waits
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_capacity_starved_run_equals_roomy_run(P, O, mixed_grid, precision):
+    """Nothing is lost when the queue or the neutral-record buffer is too
+    small: spawning candidates wait (parked just before their interaction),
+    the queue doubles and the run goes on; with a full neutral buffer the
+    caller reads the records and propagates again.  The records equal those
+    of a run with room to spare, bit for bit, and the oracle's."""
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    grid = mixed_grid if precision == 0 else mixed_grid.astype(np.float32)
+    inj = _spawning_injection(w, 256)
+    say(f"roomy run precision={precision}")
+    roomy = make_ctx(P, w, grid, tables, precision, qcap=1 << 16, ncap=1 << 16)
+    fr, nr, cr, waits = _drain_run(P, roomy, inj)
+    roomy.close()
+    assert waits == 0 and cr["queue_deferred"] == 0 and cr["charged_sec"] > 256
+    assert cr["neutral_sec"] > 64
+    for qcap, ncap, budget in ((256, 1 << 16, 0), (256, 16, 0), (300, 40, 25)):
+        say(f"starved run qcap={qcap} ncap={ncap} budget={budget}")
+        ctx = make_ctx(P, w, grid, tables, precision, qcap=qcap, ncap=ncap)
+        fs, ns, cs, waits = _drain_run(P, ctx, inj, budget)
+        ctx.close()
+        assert cs["queue_deferred"] > 0
+        if ncap < cr["neutral_sec"]:
+            assert waits > 0 and cs["neutral_deferred"] > 0
+        _assert_identical(fr, fs)
+        a, b = P.sort_neutral(nr), P.sort_neutral(ns)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+        for k in CNT_KEYS:
+            assert cr[k] == cs[k], k
+    fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
+                                O.GridRef(grid, w.spacing_m), O.TablesRef(tables), inj,
+                                nthreads=0, neu_cap=1 << 16)
+    compare_counts(cr, co, "spawning")
+    compare_records(fr, fo, f"spawning p{precision}")
+    compare_neutral(nr, no, "spawning neutral", fo)
 
 
 def test_single_candidate_and_ragged_batch(P, O, mixed_grid):

@@ -104,7 +104,7 @@ def _check_whole_batch(P, fin, neu, cnt, n):
     assert cnt["observed"] + cnt["max_traj"] + cnt["energy_floor"] == cnt["finished"]
     assert cnt["finished"] == n + cnt["charged_sec"]
     assert len(neu["id"]) == cnt["neutral_sec"]
-    assert cnt["queue_dropped"] == 0 and cnt["neutral_dropped"] == 0
+    assert cnt["queue_deferred"] == 0 and cnt["neutral_deferred"] == 0
     assert np.all(fin["Z"] >= 1) and np.all(fin["Z"] <= fin["A"])
     assert np.all(np.isfinite(fin["x"])) and np.all(fin["E"] > 0)
     # the last step is shortened to end on the trajectory budget
