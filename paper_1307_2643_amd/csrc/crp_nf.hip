@@ -194,12 +194,12 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
 
 // Training backward for activations: dOut = 2 (out - target) / n; dH4 = W5^T
 // dOut(bf16); dZ_k = dH_k * (h_k > 0); dH_{k-1} = W_k^T dZ_k(bf16) by MFMA with
-// the transposed images.  Stores dZ_k as bf16 (weight gradients) and FP32
-// (bias gradients), and dOut (FP32 and bf16-rounded) for the output layer.
+// the transposed images.  Stores dZ_k and dOut in FP32, feature-major
+// ([128][ld] and [3][ld]), for the weight and bias gradients.
 __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int64_t n,
                                                 int64_t ld, const float* out, const float* tgt,
-                                                const __bf16* acts, __bf16* dz, float* dzf,
-                                                float* dout, float* dout_r, float inv_n)
+                                                const __bf16* acts, float* dzf, float* dout,
+                                                float inv_n)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img_t);
@@ -218,8 +218,7 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
             for (int c = 0; c < 3; ++c) {
                 d[c] = 2.0f * (out[3 * me + c] - tgt[3 * me + c]) * inv_n;
                 dr[c] = (float)(__bf16)d[c];
-                dout[3 * me + c] = d[c];
-                dout_r[3 * me + c] = dr[c];
+                dout[(int64_t)c * ld + me] = d[c];
             }
         }
         bf16x8 dzb[2][8];
@@ -242,10 +241,8 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                                     (float)acts[((int64_t)4 * NF_WIDTH + f) * ld + pt[cb]] > 0.0f;
                     s = on ? s : 0.0f;
                     dzb[cb][m][j] = (__bf16)s;
-                    if (pt[cb] < n) {
-                        dz[((int64_t)3 * NF_WIDTH + f) * ld + pt[cb]] = (__bf16)s;
+                    if (pt[cb] < n)
                         dzf[((int64_t)3 * NF_WIDTH + f) * ld + pt[cb]] = s;
-                    }
                 }
         }
         // layers 4 -> 1: dH_{k-1} = W_k^T dZ_k, mask with h_{k-1} > 0
@@ -274,10 +271,8 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                             (float)acts[((int64_t)k * NF_WIDTH + f) * ld + pt[cb]] > 0.0f;
                         s = on ? s : 0.0f;
                         nxt[cb][2 * r + (i >> 3)][i & 7] = (__bf16)s;
-                        if (pt[cb] < n) {
-                            dz[((int64_t)(k - 1) * NF_WIDTH + f) * ld + pt[cb]] = (__bf16)s;
+                        if (pt[cb] < n)
                             dzf[((int64_t)(k - 1) * NF_WIDTH + f) * ld + pt[cb]] = s;
-                        }
                     }
                 }
             }
@@ -290,85 +285,140 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
     }
 }
 
-// Weight gradient dW[o][i] += sum_p dz[o][p] a[i][p] over a chunk of points per
-// block (MFMA; each wave one 32-row strip of the 128x128 result).
-__global__ void __launch_bounds__(256) k_nf_wgrad(const __bf16* dz, const __bf16* a, int64_t n,
-                                                  int64_t ld, int64_t chunk, float* dW)
+// Weight and bias gradients of all five layers in one launch, split over the
+// points: block (chunk c, layer L) forms the partial sums over its chunk
+//   dW_L[o][i] = sum_p bf16(g_L[o][p]) a_L[i][p],   db_L[o] = sum_p g_L[o][p]
+// with g_L the FP32 gradient at layer L's output (g_4: the output gradient,
+// 3 rows) and a_L its bf16 input activations, both feature-major with leading
+// dimension ld, and writes them to part[c][L] (NF_PART_LAYER floats per layer:
+// dW row-major, then db).  Matrix products on MFMA 32x32x16 bf16: the A
+// operand is eight consecutive points of a gradient row (converted to bf16
+// with round to nearest even, as the backward's own products use it), the B
+// operand eight consecutive points of an activation row, both straight from
+// memory as 16-byte loads.  Hidden layers: wave w forms rows 32 w.. of the
+// 128 x 128 result; output layer: wave w forms columns 32 w.. of the 3 x 128
+// result (rows 3..31 of its tile are zero).
+constexpr int NF_PART_LAYER = NF_WIDTH * NF_WIDTH + NF_WIDTH;
+constexpr int NF_GRAD_CHUNKS = 64;      // point chunks of one gradient launch (at most)
+
+struct NFGradIn {
+    const float* g[5];       // FP32 gradients: [128][ld] (layers 1-4), [3][ld] (output)
+    const __bf16* a[5];      // bf16 activations [128][ld] (layer inputs)
+};
+
+__device__ inline bf16x8 nf_cvt8(const float4 lo, const float4 hi)
 {
+    bf16x8 r;
+    r[0] = (__bf16)lo.x;
+    r[1] = (__bf16)lo.y;
+    r[2] = (__bf16)lo.z;
+    r[3] = (__bf16)lo.w;
+    r[4] = (__bf16)hi.x;
+    r[5] = (__bf16)hi.y;
+    r[6] = (__bf16)hi.z;
+    r[7] = (__bf16)hi.w;
+    return r;
+}
+
+// One block's partial sums for layer L; NCT column tiles per wave (4 for a
+// hidden layer, 1 for the output layer).
+template <int NCT>
+__device__ inline void nf_wgrad_block(const NFGradIn& in, int L, int64_t p0, int64_t p1,
+                                      int64_t ld, float* out)
+{
+    constexpr bool out_layer = NCT == 1;
     const int lane = (int)(threadIdx.x & 63u);
     const int g = lane >> 5;
-    const int rt = (int)(threadIdx.x >> 6);     // row tile of this wave
+    const int w = (int)(threadIdx.x >> 6);
+    // this lane's gradient row (A operand) and activation rows (B operands)
+    const int arow = out_layer ? (lane & 31) : 32 * w + (lane & 31);
+    const bool alive = !out_layer || arow < 3;
+    const float* grow = in.g[L] + (int64_t)(alive ? arow : 0) * ld;
+    const __bf16* abase = in.a[L];
+    floatx16 acc[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+        acc[ct] = floatx16{};
+    float bsum = 0.0f;
+    for (int64_t p = p0; p < p1; p += 16) {
+        const int64_t q = p + 8 * g;          // this lane's eight points
+        float4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
+        const bool full = q + 8 <= p1;
+        if (alive && full) {
+            lo = *(const float4*)(grow + q);
+            hi = *(const float4*)(grow + q + 4);
+        } else if (alive) {
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = q + j < p1 ? grow[q + j] : 0.0f;
+            lo = make_float4(v[0], v[1], v[2], v[3]);
+            hi = make_float4(v[4], v[5], v[6], v[7]);
+        }
+        bsum += ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
+        const bf16x8 A = nf_cvt8(lo, hi);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const int col = out_layer ? 32 * w + (lane & 31) : 32 * ct + (lane & 31);
+            const __bf16* brow = abase + (int64_t)col * ld;
+            bf16x8 B;
+            if (full) {
+                B = *(const bf16x8*)(brow + q);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    B[j] = q + j < p1 ? brow[q + j] : (__bf16)0.0f;
+            }
+            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[ct], 0, 0, 0);
+        }
+    }
+    // result element i of a lane: row 8 (i / 4) + 4 g + i % 4 of the tile, its column
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int r = 8 * (i >> 2) + 4 * g + (i & 3);
+            if (out_layer) {
+                if (r < 3)
+                    out[r * NF_WIDTH + 32 * w + (lane & 31)] = acc[ct][i];
+            } else {
+                out[(32 * w + r) * NF_WIDTH + 32 * ct + (lane & 31)] = acc[ct][i];
+            }
+        }
+    // bias partials: the two lanes of a row hold its two halves of each step
+    bsum += __shfl_xor(bsum, 32);
+    if (g == 0 && alive && (!out_layer || w == 0))
+        out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + arow] = bsum;
+}
+
+__global__ void __launch_bounds__(256) k_nf_wgrad(NFGradIn in, int64_t n, int64_t ld,
+                                                  int64_t chunk, float* part)
+{
+    const int L = (int)blockIdx.y;
     const int64_t p0 = (int64_t)blockIdx.x * chunk;
     const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
-    floatx16 acc[4] = {{}, {}, {}, {}};
-    const int o = 32 * rt + (lane & 31);
-    for (int64_t p = p0; p < p1; p += 16) {
-        bf16x8 A, Bv[4];
-        for (int j = 0; j < 8; ++j) {
-            const int64_t q = p + 8 * g + j;
-            A[j] = q < p1 ? dz[(int64_t)o * ld + q] : (__bf16)0.0f;
-        }
-        for (int ct = 0; ct < 4; ++ct)
-            for (int j = 0; j < 8; ++j) {
-                const int64_t q = p + 8 * g + j;
-                Bv[ct][j] = q < p1 ? a[(int64_t)(32 * ct + (lane & 31)) * ld + q] : (__bf16)0.0f;
-            }
-        for (int ct = 0; ct < 4; ++ct)
-            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, Bv[ct], acc[ct], 0, 0, 0);
-    }
-    for (int ct = 0; ct < 4; ++ct)
-        for (int i = 0; i < 16; ++i) {
-            const int row = 32 * rt + 8 * (i >> 2) + 4 * g + (i & 3);
-            const int col = 32 * ct + (lane & 31);
-            atomicAdd(dW + row * NF_WIDTH + col, acc[ct][i]);
-        }
+    float* out = part + ((int64_t)blockIdx.x * 5 + L) * NF_PART_LAYER;
+    if (L == 4)
+        nf_wgrad_block<1>(in, L, p0, p1, ld, out);
+    else
+        nf_wgrad_block<4>(in, L, p0, p1, ld, out);
 }
 
-// Row sums of an FP32 feature-major array: db[f] += sum_p x[f][p] (one block per row).
-__global__ void k_nf_rowsum(const float* x, int64_t n, int64_t ld, float* db)
+// Sum of the chunk partials into the flat gradient (W1, b1, ..., W4, b4, W5,
+// b5): one thread per parameter, chunks summed in order.
+__global__ void k_nf_wgrad_reduce(const float* part, int nchunks, float* grad)
 {
-    __shared__ float red[256];
-    const int f = blockIdx.x;
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= NF_NPARAM)
+        return;
+    // hidden layers: W [128][128] then b [128], as in the partials; output
+    // layer: W5 [3][128] then b5 [3], also as in its partial
+    const int L = e < NF_W5 ? e / NF_LAYER_PARAMS : 4;
+    const int k = e < NF_W5 ? e % NF_LAYER_PARAMS : e - NF_W5;
     float s = 0.0f;
-    for (int64_t p = threadIdx.x; p < n; p += blockDim.x)
-        s += x[(int64_t)f * ld + p];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        db[f] += red[0];
-}
-
-// Output layer gradients: dW5[c][f] = sum_p dout_r[p][c] h4[f][p] and
-// db5[c] = sum_p dout[p][c] (one block per (c, f) pair, plus 3 for db5).
-__global__ void k_nf_grad5(const float* dout, const float* dout_r, const __bf16* h4, int64_t n,
-                           int64_t ld, float* grad)
-{
-    __shared__ float red[256];
-    const int b = blockIdx.x;
-    float s = 0.0f;
-    if (b < 3 * NF_WIDTH) {
-        const int c = b / NF_WIDTH, f = b % NF_WIDTH;
-        for (int64_t p = threadIdx.x; p < n; p += blockDim.x)
-            s += dout_r[3 * p + c] * (float)h4[(int64_t)f * ld + p];
-    } else {
-        const int c = b - 3 * NF_WIDTH;
-        for (int64_t p = threadIdx.x; p < n; p += blockDim.x)
-            s += dout[3 * p + c];
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        grad[b < 3 * NF_WIDTH ? NF_W5 + b : NF_B5 + (b - 3 * NF_WIDTH)] = red[0];
+    for (int c = 0; c < nchunks; ++c)
+        s += part[((int64_t)c * 5 + L) * NF_PART_LAYER + k];
+    grad[e] = s;
 }
 
 // Mean squared error sum_c (out - tgt)^2 averaged over points.
@@ -425,9 +475,10 @@ struct NeuralField {
     int64_t t = 0;              // Adam step
     // training buffers
     int64_t cap = 0;
-    float *xh = nullptr, *tgt = nullptr, *out = nullptr, *dout = nullptr, *dout_r = nullptr;
-    __bf16 *acts = nullptr, *dz = nullptr;
+    float *xh = nullptr, *tgt = nullptr, *out = nullptr, *dout = nullptr;
+    __bf16* acts = nullptr;
     float* dzf = nullptr;
+    float* part = nullptr;      // split-K partial gradients [NF_GRAD_CHUNKS][5][NF_PART_LAYER]
     double* loss = nullptr;
     int num_cus = 256;
     bool loaded = false;
@@ -437,11 +488,11 @@ struct NeuralField {
 static void nf_free_train(NeuralField* nf)
 {
     for (void* p : {(void*)nf->xh, (void*)nf->tgt, (void*)nf->out, (void*)nf->dout,
-                    (void*)nf->dout_r, (void*)nf->acts, (void*)nf->dz, (void*)nf->dzf})
+                    (void*)nf->acts, (void*)nf->dzf, (void*)nf->part})
         if (p)
             (void)hipFree(p);
-    nf->xh = nf->tgt = nf->out = nf->dout = nf->dout_r = nf->dzf = nullptr;
-    nf->acts = nf->dz = nullptr;
+    nf->xh = nf->tgt = nf->out = nf->dout = nf->dzf = nf->part = nullptr;
+    nf->acts = nullptr;
     nf->cap = 0;
 }
 
@@ -601,10 +652,9 @@ static hipError_t nf_ensure_cap(NeuralField* nf, int64_t n)
     al((void**)&nf->tgt, ld * 12);
     al((void**)&nf->out, ld * 12);
     al((void**)&nf->dout, ld * 12);
-    al((void**)&nf->dout_r, ld * 12);
     al((void**)&nf->acts, (size_t)5 * NF_WIDTH * ld * 2);
-    al((void**)&nf->dz, (size_t)4 * NF_WIDTH * ld * 2);
     al((void**)&nf->dzf, (size_t)4 * NF_WIDTH * ld * 4);
+    al((void**)&nf->part, (size_t)NF_GRAD_CHUNKS * 5 * NF_PART_LAYER * 4);
     if (e == hipSuccess)
         nf->cap = ld;
     return e;
@@ -616,28 +666,28 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
     hipStream_t s = nf->stream;
     const int64_t ld = nf->cap;
     const int nb = nf_eval_blocks(nf, n);
-    hipError_t e = hipMemsetAsync(nf->grad, 0, NF_NPARAM * 4, s);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(nf->loss, 0, 8, s);
+    // (the gradient is written whole by the reduction)
+    hipError_t e = hipMemsetAsync(nf->loss, 0, 8, s);
     if (e != hipSuccess)
         return e;
     k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, nf->acts, nf->out);
     k_nf_loss<<<256, 256, 0, s>>>(nf->out, nf->tgt, n, nf->loss);
     k_nf_bwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->acts,
-                                           nf->dz, nf->dzf, nf->dout, nf->dout_r,
-                                           (float)(1.0 / (double)n));
-    const int64_t chunk = 1024;
-    const int wb = (int)((n + chunk - 1) / chunk);
-    for (int k = 0; k < 4; ++k) {
-        float* dW = nf->grad + k * NF_LAYER_PARAMS;
-        k_nf_wgrad<<<wb, 256, 0, s>>>(nf->dz + (int64_t)k * NF_WIDTH * ld,
-                                      nf->acts + (int64_t)k * NF_WIDTH * ld, n, ld, chunk, dW);
-        k_nf_rowsum<<<NF_WIDTH, 256, 0, s>>>(nf->dzf + (int64_t)k * NF_WIDTH * ld, n, ld,
-                                             dW + NF_WIDTH * NF_WIDTH);
-    }
-    k_nf_grad5<<<3 * NF_WIDTH + 3, 256, 0, s>>>(nf->dout, nf->dout_r,
-                                                nf->acts + (int64_t)4 * NF_WIDTH * ld, n, ld,
-                                                nf->grad);
+                                           nf->dzf, nf->dout, (float)(1.0 / (double)n));
+    // split over at most NF_GRAD_CHUNKS chunks of a multiple of 16 points
+    int64_t chunk = (n + NF_GRAD_CHUNKS - 1) / NF_GRAD_CHUNKS;
+    chunk = (chunk + 15) & ~int64_t(15);
+    if (chunk < 256)
+        chunk = 256;
+    const int nchunks = (int)((n + chunk - 1) / chunk);
+    NFGradIn gi;
+    for (int k = 0; k < 4; ++k)
+        gi.g[k] = nf->dzf + (int64_t)k * NF_WIDTH * ld;
+    gi.g[4] = nf->dout;
+    for (int k = 0; k < 5; ++k)
+        gi.a[k] = nf->acts + (int64_t)k * NF_WIDTH * ld;
+    k_nf_wgrad<<<dim3(nchunks, 5), 256, 0, s>>>(gi, n, ld, chunk, nf->part);
+    k_nf_wgrad_reduce<<<(NF_NPARAM + 255) / 256, 256, 0, s>>>(nf->part, nchunks, nf->grad);
     return hipGetLastError();
 }
 
