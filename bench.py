@@ -69,6 +69,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-nf", action="store_true", help="skip the neural-field variant")
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
+    ap.add_argument("--nf-narrow-steps", type=int, default=45780,
+                    help="training steps of the network on the narrow-band field "
+                         "(45780 steps = 3e9 points; 0 skips that point)")
     ap.add_argument("--nf-steps", type=int, default=1526,
                     help="training steps of 65536 points (1526 steps = 1e8 points)")
     ap.add_argument("--no-outputs", action="store_true",
@@ -84,9 +87,16 @@ def main():
     ap.add_argument("--nf-only", action="store_true",
                     help="diagnostic: only the neural-field variant (training, field error, "
                          "surrogate vs grid); prints that variant's JSON")
-    ap.add_argument("--batching", type=int, default=0, metavar="NBATCH",
-                    help="also run the batching form: NBATCH batches of 1e7 candidates at "
-                         "distances 1..1000 Mpc (10 = the 1e8-candidate stream)")
+    ap.add_argument("--batching", type=int, default=10, metavar="NBATCH",
+                    help="batches of 1e7 candidates at distances 1..1000 Mpc in the batching "
+                         "form (10 = the 1e8-candidate stream; 0 skips it)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the FP64 lines of the 32^3 and 256^3 workloads")
+    ap.add_argument("--nf-sweep", type=str, default=None, metavar="NMAX,..:STEPS,..:LR",
+                    help="diagnostic: neural-field RMS error on the 1024^3 grid against the "
+                         "field band's n_max (band 2..n_max cycles per box) and the training "
+                         "length (steps of 65536 points, one cosine schedule each, from lr LR "
+                         "to 1e-5); one JSON line per point")
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -114,6 +124,10 @@ def main():
         b.copy_(a)                       # reads and writes exactly 1 GiB
         torch.cuda.synchronize()
         del a, b
+
+    if args.nf_sweep:
+        nf_sweep(args.nf_sweep, crp, I, torch, dev, stream)
+        return
 
     w = I.W_MIXED1024
     n = args.n or w.n_candidates
@@ -227,6 +241,10 @@ def main():
         f"{len(hf['id'])} finished and {len(hn['id'])} neutral records read back)")
     del hf, hn
 
+    # ---- a plain device copy: the HBM bandwidth this machine reaches -----------
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"[bench] device copy of 4 GiB: {copy_gbs:.0f} GB/s (read + write)")
+
     # ---- the gather pattern alone on the same corner records (diagnostic) ---
     ceiling = None
     if launch["layout"] == crp.LAYOUT_CORNER:
@@ -334,6 +352,13 @@ def main():
         log(f"[bench] CPU oracle: {cpu['value']:.3e} steps/s on {used} threads")
         del host_grid
 
+    # ---- the FP64 method on the small and mid-size workloads ----------------
+    if not args.no_small:
+        variants["fp64_grid32"] = small_config_variant(args, crp, I, torch, stream, I.W_SMALL,
+                                                       None)
+        variants["fp64_grid256"] = small_config_variant(args, crp, I, torch, stream,
+                                                        I.W_MIXED256, 10_000)
+
     # ---- galactic backtracking through the analytic field --------------------
     if not args.no_galactic:
         variants["galactic"] = galactic_variant(args, crp, I, torch, stream)
@@ -388,10 +413,101 @@ def main():
                      "gathers_per_launch": gathers_per_launch,
                      "gather_ceiling": ceiling,
                      "attempts_per_launch": attempts_per_launch,
-                     "rejects_per_launch": cnt["rejects"] / args.steps},
+                     "rejects_per_launch": cnt["rejects"] / args.steps,
+                     "copy_GBps_measured": copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(torch, dev, nbytes=1 << 32):
+    """A plain device-to-device copy of nbytes timed with HIP events: bytes
+    read plus bytes written per second (the best of three)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    best = 0.0
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
+def small_config_variant(args, crp, I, torch, stream, w, subset):
+    """The FP64 method on a workload whose grid is FP64 and small: all of its
+    candidates on the GPU (timed with the library's HIP events and by wall
+    clock), and the oracle on the host beside it -- the whole workload, or
+    its first `subset` candidates (ids 0.. , all species alike), whose records
+    are also compared with the GPU's records of the same candidates."""
+    grid = w.make_grid()
+    tables = w.make_tables()
+    n = w.n_candidates
+    inj = w.make_injection(n)
+    dev = torch.device("cuda:0")
+    d = [torch.as_tensor(a, device=dev) for a in
+         (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+    prm = crp.params_for(w, crp.FP64, device=0, queue_capacity=2 * n,
+                         neutral_capacity=max(n, 1 << 16))
+    ctx = crp.Context(prm, stream)
+    ctx.set_field_grid(torch.as_tensor(grid, device=dev), w.spacing_m)
+    ctx.set_tables(tables)
+
+    def run(keep):
+        ctx.reset_counters()
+        ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
+                   on_device=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.propagate(0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, _ = ctx.last_timing()
+        c = ctx.counts()
+        fin = crp.sort_finished(ctx.read_finished()) if keep else None
+        ctx.discard_finished()
+        return wall, ms, c, fin
+
+    run(False)                                   # untimed first run
+    wall, ms, c, fin = run(True)
+    ctx.close()
+    out = {"workload": f"{w.name} ({n} candidates, FP64 method, {w.grid_n}^3 FP64 grid)",
+           "steps_per_s": c["steps"] / wall, "steps_per_s_kernel": c["steps"] / (ms * 1e-3),
+           "wall_s": wall, "kernel_ms": ms, "steps": c["steps"], "attempts": c["attempts"],
+           "finished": c["finished"], "charged_sec": c["charged_sec"],
+           "neutral_sec": c["neutral_sec"]}
+    log(f"[bench] {w.name}: {out['steps_per_s']:.3e} steps/s ({wall * 1e3:.1f} ms wall, "
+        f"kernel {ms:.1f} ms)")
+    if not args.no_cpu:
+        from oracle import oracle as O
+        m = n if subset is None else subset
+        sub = inj.subset(slice(0, m))
+        threads = len(os.sched_getaffinity(0))
+        t0 = time.perf_counter()
+        fo, _, co, used = O.propagate(O.config_for(w), O.GridRef(grid, w.spacing_m),
+                                      O.TablesRef(tables), sub, nthreads=threads)
+        tc = time.perf_counter() - t0
+        out["oracle"] = {"steps_per_s": co["steps"] / tc, "cores": used, "wall_s": tc,
+                         "sample": "the whole workload" if subset is None else
+                         f"first {m} candidates (ids 0..{m - 1})"}
+        fo = O.sort_finished(fo)
+        mine = fin["id"] < m
+        fg = {k: v[mine] for k, v in fin.items()}
+        same = 0
+        if len(fg["id"]) == len(fo["id"]) and np.array_equal(fg["id"], fo["id"]) and \
+                np.array_equal(fg["lineage"], fo["lineage"]):
+            same = int(np.sum(np.all(fg["x"] == fo["x"], axis=1) & (fg["E"] == fo["E"]) &
+                              (fg["nsteps"] == fo["nsteps"])))
+        out["parity"] = {"records": int(len(fo["id"])), "gpu_records": int(len(fg["id"])),
+                         "bitwise_identical": same}
+        log(f"[bench] {w.name} oracle: {co['steps'] / tc:.3e} steps/s on {used} threads; "
+            f"{same}/{len(fo['id'])} records bitwise identical to the GPU's")
+    return out
 
 
 # Bytes the observable reduction reads per record: the status of every record,
@@ -763,9 +879,30 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
 
 
 def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
-    """Trains the Fourier-feature network on the 1024^3 grid with the library's
-    own kernels and compares the surrogate with the grid path on a batch of
-    the distance-distributed workload (sources at 1-1000 Mpc, secondaries on)."""
+    """The learned form at two points of its capacity curve.  'c3_band': the
+    network trained (1e8 points, lr 1e-3 -> 1e-5) on the 1024^3 grid of the
+    timed batch (band 2..16 cycles per box), far from its 1% target.
+    'narrow_band': the same network on a 1024^3 field of the band 2..3 cycles
+    per box (seed 3, 1 nG RMS), trained until its RMS error falls below 1%
+    (3e9 points, lr 3e-3 -> 1e-5).  At each point: the RMS field error on 1e6
+    held-out points, and the surrogate against the grid on 1e6 candidates of
+    the distance workload (sources at 1-1000 Mpc, secondaries on)."""
+    out = {"c3_band": nf_point(args, crp, I, torch, grid, tables, stream, launch,
+                               band=(2.0, 16.0), steps=args.nf_steps, lr0=1e-3)}
+    if args.nf_narrow_steps > 0:
+        g3 = I.turbulent_grid(w.grid_n, w.spacing_m, 2.0, 3.0, w.brms_T, 3, np.float32,
+                              grid.device)
+        out["narrow_band"] = nf_point(args, crp, I, torch, g3, tables, stream, launch,
+                                      band=(2.0, 3.0), steps=args.nf_narrow_steps, lr0=3e-3)
+        del g3
+        torch.cuda.empty_cache()
+    return out
+
+
+def nf_point(args, crp, I, torch, grid, tables, stream, launch, band, steps, lr0):
+    """Trains the Fourier-feature network on `grid` (its 64 frequencies drawn
+    from `band`) with the library's own kernels and compares the surrogate with
+    the grid path on a batch of the distance workload."""
     wd = I.W_DIST1024
     nprm = crp.params_for(wd, crp.MIX, device=0, field_mode=crp.FIELD_NEURAL,
                           queue_capacity=2 * args.nf_candidates,
@@ -773,14 +910,15 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
     cnf = crp.Context(nprm, stream)
     cnf.set_field_grid(grid, wd.spacing_m)
     cnf.set_tables(tables)
-    cnf.nf_init(I.nf_frequencies(seed=505), I.nf_init_flat(509), wd.brms_T)
+    cnf.nf_init(I.nf_frequencies(nmin=band[0], nmax=band[1], seed=505), I.nf_init_flat(509),
+                wd.brms_T)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = cnf.nf_train(args.nf_steps, 65536, 1e-3, 1e-5, 506)
+    losses = cnf.nf_train(steps, 65536, lr0, 1e-5, 506)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    log(f"[bench] NF trained on {args.nf_steps * 65536:.3g} points in {train_s:.1f}s, "
-        f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    log(f"[bench] NF (band {band[0]:g}..{band[1]:g}) trained on {steps * 65536:.3g} points "
+        f"in {train_s:.1f}s, loss {losses[0]:.4f} -> {losses[-1]:.5f}")
     # field error on held-out points (the grid path is the reference)
     box = wd.grid_n * wd.spacing_m
     pos = I.uniform_points(1_000_000, box, 507)
@@ -824,10 +962,11 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
     hg, thg = hist(fin_g)
     from scipy import stats
     ks = float(stats.ks_2samp(thn, thg).statistic)
-    out = {"steps_per_s": rate_nf, "kernel_ms": ms_nf, "grid_steps_per_s_same_batch": rate_g,
+    out = {"band_cycles_per_box": list(band), "steps_per_s": rate_nf, "kernel_ms": ms_nf,
+           "grid_steps_per_s_same_batch": rate_g,
            "speedup_vs_grid": rate_nf / rate_g, "rms_field_error": rms,
            "deflection_hist_distance": float(0.5 * np.abs(hn - hg).sum()), "deflection_ks": ks,
-           "train_points": args.nf_steps * 65536, "train_s": train_s,
+           "train_points": steps * 65536, "train_lr0": lr0, "train_s": train_s,
            "final_train_loss": float(losses[-1]), "field_bytes_network": 66435 * 2,
            "field_bytes_grid": int(grid.numel() * 4),
            "workload": f"{wd.name} subset of {args.nf_candidates} candidates (seed 508)",
@@ -835,7 +974,7 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
            "attempts": {"nf": c_nf["attempts"], "grid": c_g["attempts"]},
            "kernel_time_ratio_nf_over_grid": ms_nf / ms_g}
     # MFMA work of the network: four 128x128 layers per evaluation, six
-    # evaluations per Cash-Karp attempt (the 128->3 output layer runs on the VALU)
+    # evaluations per Cash-Karp attempt (the 128->3 output layer is not counted)
     flop = 6 * 4 * 2 * 128 * 128
     achieved = c_nf["attempts"] * flop / (ms_nf * 1e-3) / 1e12
     out["mfma"] = {"bound": "mfma", "flop_per_attempt": flop, "achieved": achieved,
@@ -843,6 +982,44 @@ def neural_variant(args, crp, I, torch, w, grid, tables, stream, launch):
     log(f"[bench] NF form: {rate_nf:.3e} steps/s vs grid {rate_g:.3e} on the same batch; "
         f"deflection histogram distance {out['deflection_hist_distance']:.4f}, KS {ks:.4f}")
     return out
+
+
+def nf_sweep(spec, crp, I, torch, dev, stream):
+    """Field error of the network against the band of the turbulent field and
+    the training length: for each n_max a 1024^3 FP32 grid of the band
+    2..n_max cycles per box (seed 3, 1 nG RMS, 10 kpc cells), the network's 64
+    frequencies drawn from that band (seed 505), then for each length a fresh
+    network (seed 509) trained with one cosine schedule (lr LR -> 1e-5, batch
+    65536, Philox seed 506) and its RMS error on 1e6 held-out points (seed 507)."""
+    nmaxes, steps_list, lr0 = spec.split(":")
+    w = I.W_DIST1024
+    box = w.grid_n * w.spacing_m
+    pos = I.uniform_points(1_000_000, box, 507)
+    for nmax in [float(v) for v in nmaxes.split(",")]:
+        grid = I.turbulent_grid(w.grid_n, w.spacing_m, 2.0, nmax, w.brms_T, 3, np.float32, dev)
+        prm = crp.params_for(w, crp.MIX, device=0, field_mode=crp.FIELD_NEURAL,
+                             queue_capacity=1 << 16, neutral_capacity=1 << 16)
+        ctx = crp.Context(prm, stream)
+        ctx.set_field_grid(grid, w.spacing_m)
+        ctx.set_tables(w.make_tables())
+        F = I.nf_frequencies(nmin=2.0, nmax=nmax, seed=505)
+        Bg = ctx.eval_field(pos, crp.MIX)
+        for steps in [int(v) for v in steps_list.split(",")]:
+            ctx.nf_init(F, I.nf_init_flat(509), w.brms_T)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            losses = ctx.nf_train(steps, 65536, float(lr0), 1e-5, 506)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            Bn = ctx.eval_field(pos, crp.EVAL_NEURAL)
+            rms = float(np.sqrt(((Bn - Bg) ** 2).sum(1).mean()) / w.brms_T)
+            print(json.dumps({"nmax": nmax, "band_modes": int(len(I.turbulence_modes(
+                0, 2.0, nmax, exclude_nyquist=False))), "steps": steps,
+                "points": steps * 65536, "lr0": float(lr0), "rms": rms, "train_s": dt,
+                "final_loss": float(np.mean(losses[-20:]))}), flush=True)
+        ctx.close()
+        del grid
+        torch.cuda.empty_cache()
 
 
 def summarize_pmc(d):
@@ -901,10 +1078,26 @@ def error_report(gpu, ref):
     th_r = np.degrees(np.arccos(np.clip((ref["u"] * ref["u0"]).sum(1), -1, 1)))
     hg = np.histogram(th_g, bins=36, range=(0, 180))[0] / len(th_g)
     hr = np.histogram(th_r, bins=36, range=(0, 180))[0] / len(th_r)
+    # the same, stratified by the record's rigidity E/Z (volts, the oracle's
+    # final energy and charge): low rigidity means small gyroradii and chaotic
+    # paths, where FP32 stage differences grow fastest
+    lgR = np.log10(ref["E"] / ref["Z"])
+    strata = {}
+    for lo, hi in ((-np.inf, 18.0), (18.0, 19.0), (19.0, 20.0), (20.0, np.inf)):
+        sel = (lgR >= lo) & (lgR < hi)
+        if not sel.any():
+            continue
+        name = f"lgR[{lo:g},{hi:g})"
+        strata[name] = {"records": int(sel.sum()), "position_rel": q(dx[sel]),
+                        "direction_deg": q(dang[sel]), "energy_rel": q(dE[sel]),
+                        "length_rel": q(dL[sel]),
+                        "integer_mismatches": {k: int(np.sum(gpu[k][sel] != ref[k][sel]))
+                                               for k in ("status", "A", "Z", "m", "nsteps")}}
     return {"records_compared": int(len(ref["id"])), "records_in_one_only": only,
             "position_rel": q(dx), "direction_deg": q(dang),
             "energy_rel": q(dE), "length_rel": q(dL), "integer_mismatches": ints,
-            "deflection_hist_distance": float(0.5 * np.abs(hg - hr).sum())}
+            "deflection_hist_distance": float(0.5 * np.abs(hg - hr).sum()),
+            "by_rigidity": strata}
 
 
 if __name__ == "__main__":

@@ -385,15 +385,28 @@ def nf_frequencies(nfeat=64, nmin=2.0, nmax=16.0, seed=505):
 
     Drawn without replacement from the representative modes of the field's
     band with probability proportional to the per-mode power |m|^(-11/3), so
-    the low, energetic modes are favoured.
+    the low, energetic modes are favoured.  A band with fewer than nfeat modes
+    gives all of them, and the rest is drawn the same way from the next shell
+    nmax < |m| <= nmax + 1.
     """
     modes = turbulence_modes(0, nmin, nmax, exclude_nyquist=False)
-    mag = np.sqrt((modes.astype(np.float64) ** 2).sum(axis=1))
-    p = mag ** (-11.0 / 3.0)
-    p /= p.sum()
     rng = np.random.default_rng(seed)
-    pick = rng.choice(modes.shape[0], size=nfeat, replace=False, p=p)
-    return modes[np.sort(pick)].astype(np.int32)
+
+    def draw(cand, k):
+        mag = np.sqrt((cand.astype(np.float64) ** 2).sum(axis=1))
+        p = mag ** (-11.0 / 3.0)
+        p /= p.sum()
+        return cand[rng.choice(cand.shape[0], size=k, replace=False, p=p)]
+
+    if modes.shape[0] >= nfeat:
+        pick = draw(modes, nfeat)
+    else:
+        outer = turbulence_modes(0, nmax, nmax + 1.0, exclude_nyquist=False)
+        mag = np.sqrt((outer.astype(np.float64) ** 2).sum(axis=1))
+        outer = outer[mag > nmax]
+        pick = np.concatenate([modes, draw(outer, nfeat - modes.shape[0])])
+    order = np.lexsort(pick.T[::-1])
+    return pick[order].astype(np.int32)
 
 
 def nf_init_weights(seed=509, width=128, depth=4, nout=3, nin=128):

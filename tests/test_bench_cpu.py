@@ -81,3 +81,32 @@ def test_error_report_keys_records_and_measures_differences():
     assert r["direction_deg"]["max"] < 1e-5          # arccos of a dot product rounded near 1
     assert r["integer_mismatches"]["status"] == sum(1 for i in order if i < 3)
     assert r["deflection_hist_distance"] == 0.0
+
+
+def test_error_report_strata_by_rigidity():
+    """The strata split the records by log10(E/Z) of the reference record,
+    partition them, and carry each stratum's own errors."""
+    import numpy as np
+    sys.path.insert(0, ROOT)
+    import bench
+    n = 400
+    rng = np.random.default_rng(6)
+    u = rng.standard_normal((n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    Z = rng.choice([1, 2, 7, 26], n).astype(np.int32)
+    E = 10.0 ** rng.uniform(17.5, 21.5, n)
+    ref = dict(id=np.arange(n, dtype=np.uint32), lineage=np.zeros(n, np.uint32),
+               x=rng.standard_normal((n, 3)) * 1e22, u=u, u0=u.copy(), E=E,
+               L=np.full(n, 1e23), status=np.full(n, 2, np.int32), A=2 * Z, Z=Z,
+               m=np.zeros(n, np.uint32), nsteps=np.full(n, 7, np.uint32))
+    gpu = {k: v.copy() for k, v in ref.items()}
+    low = np.log10(E / Z) < 18.0
+    gpu["E"] = np.where(low, E * (1 + 1e-6), E)        # only the lowest stratum is off
+    r = bench.error_report(gpu, ref)
+    st = r["by_rigidity"]
+    assert sum(v["records"] for v in st.values()) == n
+    assert st["lgR[-inf,18)"]["records"] == int(low.sum()) > 0
+    assert abs(st["lgR[-inf,18)"]["energy_rel"]["median"] - 1e-6) < 1e-12
+    for k, v in st.items():
+        if k != "lgR[-inf,18)":
+            assert v["energy_rel"]["max"] == 0.0

@@ -38,3 +38,18 @@ def test_distance_batches_recipe():
     u = (a.lmax - I.MPC_M) / (999 * I.MPC_M)
     assert u.min() >= 0.0 and u.max() <= 1.0
     assert stats.kstest(u, "uniform").pvalue > 1e-3
+
+
+def test_nf_frequencies_narrow_band_takes_every_mode():
+    """A band with fewer modes than features contributes all of them; the rest
+    comes from the next shell; wide bands draw distinct in-band modes."""
+    band = I.turbulence_modes(0, 2.0, 3.0, exclude_nyquist=False)
+    F = I.nf_frequencies(nmin=2.0, nmax=3.0)
+    assert F.shape == (64, 3) and len(np.unique(F, axis=0)) == 64
+    mag = np.sqrt((F.astype(float) ** 2).sum(1))
+    assert {tuple(m) for m in band} <= {tuple(m) for m in F}
+    assert np.all((mag >= 2.0) & (mag <= 4.0))
+    assert np.sum(mag > 3.0) == 64 - len(band)
+    G = I.nf_frequencies(nmin=2.0, nmax=16.0)
+    gm = np.sqrt((G.astype(float) ** 2).sum(1))
+    assert len(np.unique(G, axis=0)) == 64 and np.all((gm >= 2.0) & (gm <= 16.0))
