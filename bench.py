@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--batching", type=int, default=10, metavar="NBATCH",
                     help="batches of 1e7 candidates at distances 1..1000 Mpc in the batching "
                          "form (10 = the 1e8-candidate stream; 0 skips it)")
+    ap.add_argument("--tune-cache", type=str, default=None,
+                    help="autotuner cache file (default: a new file for this run, so the "
+                         "shape is tuned once and reused by the batching form)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the FP64 lines of the 32^3 and 256^3 workloads")
     ap.add_argument("--nf-sweep", type=str, default=None, metavar="NMAX,..:STEPS,..:LR",
@@ -98,6 +101,9 @@ def main():
                          "length (steps of 65536 points, one cosine schedule each, from lr LR "
                          "to 1e-5); one JSON line per point")
     args = ap.parse_args()
+    if args.tune_cache is None:
+        import tempfile
+        args.tune_cache = os.path.join(tempfile.mkdtemp(prefix="crp_bench_"), "tune_cache.txt")
 
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc)
@@ -175,11 +181,13 @@ def main():
         ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
     elif not args.no_tune:
         t0 = time.time()
-        # calibration: 6M candidates (about 30 per lane of a full launch) run to
-        # completion, so that every trial includes the end of a run (its tail
-        # and the secondaries' phase) in the proportion of the timed batch
-        inject(ctx, min(n, 6_000_000))
-        tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
+        # calibration on the batching workload's distribution: 1e6 candidates
+        # at distances 1..1000 Mpc (the first of its batches), run to completion
+        # in every trial (its tail and secondaries included); the shape goes to
+        # the tuner cache, where the batching form finds it
+        cal = I.inject_distances(1_000_000, 404)
+        ctx.inject(cal)
+        tuned, rate = ctx.tune(max_cycles=0, cache_path=args.tune_cache)
         ctx.discard_finished()
         while not ctx.propagate(0):
             pass
@@ -840,16 +848,17 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
         ctx.inject(id=d[0][s], A=d[1][s], Z=d[2][s], E=d[3][s], pos=d[4][s], dir=d[5][s],
                    lmax=d[6][s], on_device=True)
 
-    # calibration: 1e6 candidates of the first batch run to completion (the
-    # distance workload's trajectories are up to 10x the mixed batch's)
+    # the launch shape tuned on this workload's calibration batch (from the
+    # tuner cache when the headline's tuning wrote it; else tuned here), then
+    # that batch once more, untimed, as a warm-up
     log("[bench] batching: inputs on the device; tuning on 1e6 candidates")
     inject(batches[0], 1_000_000)
-    tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
+    tuned, rate = ctx.tune(max_cycles=0, cache_path=args.tune_cache)
     ctx.discard_finished()
     while not ctx.propagate(0):
         pass
     ctx.discard_finished()
-    log(f"[bench] batching: autotuner picked {tuned}")
+    log(f"[bench] batching: launch {tuned}")
     ctx.reset_counters()
     torch.cuda.synchronize()
     per_batch = []

@@ -409,11 +409,17 @@ crp_status crp_eval_field_noalloc(crp_ctx* ctx, int64_t n, const double* pos_m, 
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);
 crp_status crp_get_launch(crp_ctx* ctx, crp_launch* launch);
 
-/* Autotuner: times `trials` candidate launch shapes on a copy of the pending
- * queue (restored after each trial, so the pending work is unchanged), keeps
- * the fastest in the context and appends it to cache_path (NULL: no file)
- * under a key of (device name, grid shape, dtype, precision, field mode).
- * best_rate: accepted steps per second of the chosen shape. */
+/* Autotuner: times candidate launch shapes (block 128 / 256, as many blocks
+ * per compute unit as fit or 3, refill 4 / 16, linear or corner layout), each
+ * twice, on a copy of the pending queue (restored after each trial, so the
+ * pending work is unchanged) run for max_cycles cycles (<= 0: to completion),
+ * keeps the fastest in the context and appends it to cache_path (NULL: no
+ * file) under a key of (device name, grid shape, dtype, precision, field
+ * mode).  If cache_path already holds an entry for this key, its latest shape
+ * is taken without trials.  best_rate: accepted steps per second of the chosen
+ * shape (from the cache when taken from it).  Needs pending work unless the
+ * cache answers.  Errors: CRP_ESTATE (no grid, tables or pending work; not the
+ * grid field mode), CRP_EDEVICE. */
 crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path,
                     crp_launch* best, double* best_rate);
 

@@ -94,7 +94,14 @@ __device__ __attribute__((always_inline)) inline void nf_stage_lds(char* dst, co
         d[i] = s[i];
 }
 
-__device__ __attribute__((always_inline)) inline float nf_relu(float v) { return v > 0.0f ? v : 0.0f; }
+// ReLU as a 32-bit integer maximum with 0: a float is negative exactly when
+// its sign bit is set, i.e. when it is negative as an int32 (-0 included), and
+// non-negative floats order alike, so this is max(v, 0) in one instruction
+// (a floating-point maximum would be preceded by a canonicalisation).
+__device__ __attribute__((always_inline)) inline float nf_relu(float v)
+{
+    return __int_as_float(max(__float_as_int(v), 0));
+}
 
 // Hides an LDS pointer's value from the optimiser: inside persistent loops
 // the weight loads must stay next to their MFMAs instead of being hoisted out

@@ -735,6 +735,50 @@ crp_status grow_queue(crp_ctx* ctx, int64_t cap)
 }  // namespace
 
 // -------------------------------------------------------------------------
+// Autotuner cache: one line per tuning, "KEY : block=B blocks_per_cu=C
+// refill=R layout=L steps_per_s=S", KEY naming the device, the grid shape and
+// element type, the precision and the field mode.
+// -------------------------------------------------------------------------
+static std::string tune_key(const crp_ctx* ctx)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s grid=%lldx%lldx%lld dtype=%d precision=%d field=%d",
+             ctx->device_name.c_str(), (long long)ctx->gn[0], (long long)ctx->gn[1],
+             (long long)ctx->gn[2], ctx->grid_dtype, ctx->cfg.precision, ctx->cfg.field_mode);
+    return buf;
+}
+
+// The latest valid entry for key in the cache file, if any.
+static bool tune_cache_lookup(const char* path, const std::string& key, crp_launch* out,
+                              double* rate)
+{
+    FILE* f = fopen(path, "r");
+    if (!f)
+        return false;
+    bool found = false;
+    char line[512];
+    const std::string prefix = key + " : ";
+    while (fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, prefix.c_str(), prefix.size()) != 0)
+            continue;
+        crp_launch l;
+        double r = 0.0;
+        if (sscanf(line + prefix.size(), "block=%d blocks_per_cu=%d refill=%d layout=%d "
+                                         "steps_per_s=%lf",
+                   &l.block, &l.blocks_per_cu, &l.refill, &l.layout, &r) == 5 &&
+            (l.block == 128 || l.block == 256) && l.blocks_per_cu >= 0 &&
+            l.blocks_per_cu <= 64 && l.refill >= 1 && l.refill <= 64 &&
+            (l.layout == CRP_LAYOUT_LINEAR || l.layout == CRP_LAYOUT_CORNER)) {
+            *out = l;
+            *rate = r;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+// -------------------------------------------------------------------------
 // Field evaluation shared by crp_eval_field and crp_eval_field_noalloc.
 // -------------------------------------------------------------------------
 static crp_status eval_field_check(crp_ctx* ctx, int32_t mode, const char* who)
@@ -1853,10 +1897,26 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
         return CRP_EINVAL;
     if (!ctx->has_grid || !ctx->has_tables)
         return fail(ctx, CRP_ESTATE, "tune: set grid and tables first");
-    if (ctx->pending == 0)
-        return fail(ctx, CRP_ESTATE, "tune: inject a calibration batch first");
     if (ctx->cfg.field_mode != CRP_FIELD_GRID)
         return fail(ctx, CRP_ESTATE, "tune: grid field mode only");
+    // a shape tuned earlier for this device, grid, element type, precision
+    // and field mode: taken from the cache without trials (the latest entry)
+    const std::string key = tune_key(ctx);
+    if (cache_path) {
+        crp_launch cached;
+        double rate = 0.0;
+        if (tune_cache_lookup(cache_path, key, &cached, &rate) &&
+            (cached.layout == CRP_LAYOUT_LINEAR || ctx->grid_dtype == CRP_F32)) {
+            ctx->launch = cached;
+            if (best)
+                *best = cached;
+            if (best_rate)
+                *best_rate = rate;
+            return CRP_OK;
+        }
+    }
+    if (ctx->pending == 0)
+        return fail(ctx, CRP_ESTATE, "tune: inject a calibration batch first");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     // back up the pending queue: slots [0, pending) of every array
     const int64_t np = ctx->pending;
@@ -1942,12 +2002,9 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s grid=%lldx%lldx%lld dtype=%d precision=%d field=%d : block=%d "
-                       "blocks_per_cu=%d refill=%d layout=%d steps_per_s=%.6e\n",
-                    ctx->device_name.c_str(), (long long)ctx->gn[0], (long long)ctx->gn[1],
-                    (long long)ctx->gn[2], ctx->grid_dtype, ctx->cfg.precision,
-                    ctx->cfg.field_mode, bestl.block, bestl.blocks_per_cu, bestl.refill,
-                    bestl.layout, bestr);
+            fprintf(f, "%s : block=%d blocks_per_cu=%d refill=%d layout=%d steps_per_s=%.6e\n",
+                    key.c_str(), bestl.block, bestl.blocks_per_cu, bestl.refill, bestl.layout,
+                    bestr);
             fclose(f);
         }
     }

@@ -537,3 +537,37 @@ def test_read_back_in_chunks(P):
     assert np.all(np.abs(u - d) <= 4e-16)
     assert np.all(np.linalg.norm(x - (pos + L[:, None] * d), axis=1) <= 1e-12 * 3 * I.MPC_M)
     ctx.close()
+
+
+def test_tuner_cache_round_trip(P, mixed_grid, tmp_path):
+    """The autotuner appends its choice under a key of (device, grid shape,
+    element type, precision, field mode) and takes the latest entry of that
+    key from the cache without trials (and without pending work); other keys
+    and malformed lines are ignored; the tuning leaves pending work as it was."""
+    w = I.W_MIXED256
+    tables = w.make_tables()
+    cache = str(tmp_path / "tune.txt")
+    open(cache, "w").write("garbage line\nanother : block=7 refill=x\n")
+    inj = w.make_injection(3000)
+    ctx = make_ctx(P, w, mixed_grid, tables, 0)
+    ctx.inject(inj)
+    say("tuner with an empty cache")
+    best, rate = ctx.tune(max_cycles=0, cache_path=cache)
+    assert rate > 0 and ctx.get_launch() == best
+    assert ctx.counts()["pending"] == 3000           # the calibration work is still there
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 3 and lines[-1].split(" : ")[1].startswith(f"block={best['block']}")
+    ctx.close()
+    # a new context of the same key: the cached shape, no trials, no pending work needed
+    ctx = make_ctx(P, w, mixed_grid, tables, 0)
+    ctx.set_launch(block=256, blocks_per_cu=2, refill=64)
+    best2, rate2 = ctx.tune(max_cycles=0, cache_path=cache)
+    assert best2 == best and rate2 == pytest.approx(rate, rel=1e-6)
+    assert ctx.get_launch() == best
+    ctx.close()
+    # another key (the precision form): no entry, so trials -- which need work
+    ctx = make_ctx(P, w, mixed_grid, tables, 1)
+    with pytest.raises(P.CrpError) as ei:
+        ctx.tune(max_cycles=0, cache_path=cache)
+    assert ei.value.status == -4
+    ctx.close()
