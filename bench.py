@@ -1049,11 +1049,15 @@ def summarize_pmc(d):
             grid_prop = "k_propagate<1, float, 2," in k
             kind = "prop" if grid_prop else ("copy" if "copyBuffer" in k else None)
             if kind:
-                vals.setdefault((kind, c), []).append(float(r["Counter_Value"]))
+                vals.setdefault((kind, c), []).append((int(r["Dispatch_Id"]),
+                                                       float(r["Counter_Value"])))
     gib = float(1 << 30)
     out = {"kernel_sources_sha": kernel_sources_sha()}
     for c, key in (("FETCH_SIZE", "read"), ("WRITE_SIZE", "write")):
-        copy = max(vals[("copy", c)]) * 1024.0          # the 1 GiB copy, bytes as counted
+        # the 1 GiB copy of --calib-copy is the run's first copy dispatch (later
+        # copies, e.g. the 4 GiB copy-bandwidth probe, have other sizes)
+        copy = min(vals[("copy", c)])[1] * 1024.0       # bytes as counted
+        vals[("prop", c)] = [v for _, v in vals[("prop", c)]]
         prop = max(vals[("prop", c)]) * 1024.0          # the largest (timed) propagation launch
         factor = gib / copy
         out[f"{key}_scale_factor"] = factor
