@@ -138,10 +138,101 @@ __global__ void k_nf_sample(GridView g, NFGeom G, int64_t n, uint64_t seed, uint
     tgt[3 * i + 2] = B[2] * inv;
 }
 
-// Training forward: activations of every layer input stored feature-major
-// (acts[L][f][p], bf16, leading dimension ld) and the outputs.
+// -------------------------------------------------------------------------
+// Training buffers in tile order.
+//
+// The weight gradients contract over the points, so they read each feature's
+// values of consecutive points side by side, while a layer holds one point's
+// features per lane.  The training kernels therefore keep activations and
+// gradients by 32-point tiles: in a buffer layer [tile][128 features][32],
+// feature f of tile T holds its 32 points as consecutive values, point p of
+// the tile at position nf_tile_pos(p) = 16 g + i for p = 8 (i / 4) + 4 g +
+// i % 4 -- the row order of an MFMA 32x32 result, so that a lane writes its
+// 16 values of a transposed tile as 32 consecutive bytes.  The tiles are
+// transposed on the matrix cores: an MFMA whose B operand is an identity
+// moves activations from the operand layout (lane = point) to the result
+// layout (lane = feature) exactly (products with 1, sums with 0).
+// -------------------------------------------------------------------------
+__device__ __forceinline__ int nf_tile_pos(int p)
+{
+    return 16 * ((p >> 2) & 1) + ((p >> 3) << 2) + (p & 3);
+}
+
+// Identity B operands of the transposes: lane (column c, group g) holds
+// K = 8 g + j; `lo` selects K = c (columns 0..15), `hi` K = c - 16 (16..31).
+__device__ __forceinline__ void nf_ident(bf16x8& lo, bf16x8& hi)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const int c = lane & 31, k0 = 8 * (lane >> 5);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        lo[j] = (__bf16)(k0 + j == c ? 1.0f : 0.0f);
+        hi[j] = (__bf16)(k0 + j == c - 16 ? 1.0f : 0.0f);
+    }
+}
+
+// Transpose of k-blocks 2q and 2q + 1 of one column block: lane (c, g)
+// receives feature 32 q + c of the tile positions 16 g + i, i = 0..15.
+__device__ __forceinline__ floatx16 nf_transpose(const bf16x8& x0, const bf16x8& x1,
+                                                 const bf16x8& lo, const bf16x8& hi)
+{
+    floatx16 t = {};
+    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x0, lo, t, 0, 0, 0);
+    t = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x1, hi, t, 0, 0, 0);
+    return t;
+}
+
+// Writes a transposed tile of bf16 values (exact in FP32) as 32 bytes.
+__device__ __forceinline__ void nf_store_tile(__bf16* dst, const floatx16& t)
+{
+    bf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        a[i] = (__bf16)t[i];
+        b[i] = (__bf16)t[8 + i];
+    }
+    *(bf16x8*)dst = a;
+    *(bf16x8*)(dst + 8) = b;
+}
+
+// Positive-activation bits of eight non-negative bf16 values (bit j: value
+// j > 0).  A 15-bit half is non-zero exactly when adding 0x7fff sets its top
+// bit, and no carry crosses into the next half.
+__device__ __forceinline__ uint32_t nf_nz8(const bf16x8& v)
+{
+    uint32_t w[4];
+    __builtin_memcpy(w, &v, 16);
+    uint32_t b = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+        b |= ((w[t] + 0x7fff7fffu) & 0x80008000u) >> (15 - 2 * t);
+    return (b | (b >> 15)) & 0xffu;
+}
+
+// ReLU pattern of a lane's 64 activations of one column block: bit 8 m + j
+// of word m / 4 (m mod 4 in place of m) for feature 16 m + 8 g + j.
+__device__ __forceinline__ uint2 nf_relu_bits(const bf16x8 h[8])
+{
+    uint2 r;
+    r.x = nf_nz8(h[0]) | nf_nz8(h[1]) << 8 | nf_nz8(h[2]) << 16 | nf_nz8(h[3]) << 24;
+    r.y = nf_nz8(h[4]) | nf_nz8(h[5]) << 8 | nf_nz8(h[6]) << 16 | nf_nz8(h[7]) << 24;
+    return r;
+}
+
+__device__ __forceinline__ bool nf_on(const uint2 mk, int m, int j)
+{
+    return (((m < 4 ? mk.x : mk.y) >> (8 * (m & 3) + j)) & 1u) != 0;
+}
+
+constexpr int NF_DBP = 4 * NF_WIDTH + 4;     // per-wave bias sums: dZ_1..dZ_4, dOut, pad
+
+// Training forward for the points in xh (whole waves of 64 points, two tiles;
+// points past n repeat point n - 1): the outputs, the input of every layer in
+// tile order (acts: five layers of [tile][128][32] bf16) and the ReLU pattern
+// of the four hidden outputs (relu: [4][tile][64 lanes]) for the backward.
 __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64_t n, int64_t ld,
-                                                const float* xh, __bf16* acts, float* out)
+                                                const float* xh, __bf16* acts, uint2* relu,
+                                                float* out)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img);
@@ -149,39 +240,43 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
     const NFView v = nf_view(nf_lds, G);
     const int lane = (int)(threadIdx.x & 63u);
     const int g = lane >> 5;
+    const int rr = lane & 31;
+    const int64_t ntile = ld >> 5;
+    bf16x8 Ilo, Ihi;
+    nf_ident(Ilo, Ihi);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+        const int64_t T0 = base >> 5;
         bf16x8 a[2][8], b[2][8];
-        int64_t pt[2];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
-            int64_t p = base + 32 * cb + (lane & 31);
-            pt[cb] = p;
+            const int64_t p = base + 32 * cb + rr;
             const int64_t q = p < n ? p : n - 1;
             nf_embed_fp64(v.freq, xh[3 * q], xh[3 * q + 1], xh[3 * q + 2], g, a[cb]);
         }
-        auto store = [&](int L, const bf16x8 h[2][8]) {
+        auto keep = [&](int L, const bf16x8 h[2][8]) {
+            __bf16* dst = acts + (int64_t)L * NF_WIDTH * ld;
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                if (pt[cb] >= n)
-                    continue;
 #pragma unroll
-                for (int m = 0; m < 8; ++m)
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        acts[((int64_t)L * NF_WIDTH + 16 * m + 8 * g + j) * ld + pt[cb]] = h[cb][m][j];
+                for (int q = 0; q < 4; ++q) {
+                    const floatx16 t = nf_transpose(h[cb][2 * q], h[cb][2 * q + 1], Ilo, Ihi);
+                    nf_store_tile(dst + ((T0 + cb) * NF_WIDTH + 32 * q + rr) * 32 + 16 * g, t);
+                }
+                if (L > 0)
+                    relu[((int64_t)(L - 1) * ntile + T0 + cb) * 64 + lane] = nf_relu_bits(h[cb]);
             }
         };
-        store(0, a);
+        keep(0, a);
         nf_layer(v.w[0], v.bias, a, b);
-        store(1, b);
+        keep(1, b);
         nf_layer(v.w[1], v.bias + NF_WIDTH, b, a);
-        store(2, a);
+        keep(2, a);
         nf_layer(v.w[2], v.bias + 2 * NF_WIDTH, a, b);
-        store(3, b);
+        keep(3, b);
         nf_layer(v.w[3], v.bias + 3 * NF_WIDTH, b, a);
-        store(4, a);
+        keep(4, a);
         float o[3];
         nf_output(v.w5, v.bias + 4 * NF_WIDTH, a, o);
         const int64_t me = base + lane;
@@ -192,14 +287,19 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
     }
 }
 
-// Training backward for activations: dOut = 2 (out - target) / n; dH4 = W5^T
-// dOut(bf16); dZ_k = dH_k * (h_k > 0); dH_{k-1} = W_k^T dZ_k(bf16) by MFMA with
-// the transposed images.  Stores dZ_k and dOut in FP32, feature-major
-// ([128][ld] and [3][ld]), for the weight and bias gradients.
+// Training backward: dOut = 2 (out - target) / n (FP32; zero past n); dH4 =
+// W5^T bf16(dOut) on the vector ALU; dZ_k = dH_k where h_k > 0; dH_{k-1} =
+// W_k^T bf16(dZ_k) by MFMA with the transposed images.  For the weight
+// gradients it stores bf16(dZ_k) in tile order (dz: four layers of
+// [tile][128][32]) and dOut in tile order (dout: [tile][3][32], FP32); for the
+// bias gradients, each wave's sums over its 64 points (dbp: [wave][NF_DBP],
+// dZ_1..dZ_4 by 128 features, then the three outputs).  The sums take dZ as
+// bf16(dZ) + bf16(dZ - bf16(dZ)), within 2^-17 of the FP32 value, both parts
+// transposed exactly on the matrix cores.
 __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int64_t n,
                                                 int64_t ld, const float* out, const float* tgt,
-                                                const __bf16* acts, float* dzf, float* dout,
-                                                float inv_n)
+                                                const uint2* relu, __bf16* dz, float* dout,
+                                                float* dbp, float inv_n)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img_t);
@@ -207,10 +307,16 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
     const NFView v = nf_view(nf_lds, G);
     const int lane = (int)(threadIdx.x & 63u);
     const int g = lane >> 5;
+    const int rr = lane & 31;
+    const int64_t ntile = ld >> 5;
+    bf16x8 Ilo, Ihi;
+    nf_ident(Ilo, Ihi);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-        // dOut of this lane's own point, then shared with the column-block lanes
+        const int64_t T0 = base >> 5;
+        float* db = dbp + (base >> 6) * NF_DBP;
+        // dOut of this lane's own point, in tile order, and its wave sums
         float d[3] = {0.f, 0.f, 0.f}, dr[3] = {0.f, 0.f, 0.f};
         const int64_t me = base + lane;
         if (me < n) {
@@ -218,42 +324,86 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
             for (int c = 0; c < 3; ++c) {
                 d[c] = 2.0f * (out[3 * me + c] - tgt[3 * me + c]) * inv_n;
                 dr[c] = (float)(__bf16)d[c];
-                dout[(int64_t)c * ld + me] = d[c];
             }
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dout[((T0 + g) * 3 + c) * 32 + nf_tile_pos(rr)] = d[c];
+            float s = d[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+                s += __shfl_xor(s, o);
+            if (lane == 0)
+                db[4 * NF_WIDTH + c] = s;
+        }
+        // one hidden layer's gradient tile (k-blocks 2q, 2q + 1 of column
+        // block cb, FP32 values s[16] in result order) kept for the weight and
+        // bias gradients
+        auto keep = [&](int k, int cb, int q, const bf16x8& h0, const bf16x8& h1,
+                        const bf16x8& l0, const bf16x8& l1, float& dbs) {
+            const floatx16 th = nf_transpose(h0, h1, Ilo, Ihi);
+            const floatx16 tl = nf_transpose(l0, l1, Ilo, Ihi);
+            nf_store_tile(dz + (int64_t)k * NF_WIDTH * ld +
+                              ((T0 + cb) * NF_WIDTH + 32 * q + rr) * 32 + 16 * g,
+                          th);
+            float s = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                s += th[i] + tl[i];
+            dbs += s;
+        };
+        auto flush = [&](int k, float dbs[4]) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float s = dbs[q] + __shfl_xor(dbs[q], 32);
+                if (g == 0)
+                    db[k * NF_WIDTH + 32 * q + rr] = s;
+            }
+        };
         bf16x8 dzb[2][8];
-        int64_t pt[2];
         // layer 4: dH4 = W5^T dOut on the vector ALU, then the ReLU mask
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        {
             const __bf16* w5 = nf_launder(v.w5);
-            const int src = 32 * cb + (lane & 31);
-            pt[cb] = base + src;
-            const float d0 = __shfl(dr[0], src), d1 = __shfl(dr[1], src), d2 = __shfl(dr[2], src);
+            float dbs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int m = 0; m < 8; ++m)
+            for (int cb = 0; cb < 2; ++cb) {
+                const int src = 32 * cb + rr;
+                const float d0 = __shfl(dr[0], src), d1 = __shfl(dr[1], src),
+                            d2 = __shfl(dr[2], src);
+                const uint2 mk = relu[((int64_t)3 * ntile + T0 + cb) * 64 + lane];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int f = 16 * m + 8 * g + j;
-                    float s = ((float)w5[f] * d0 + (float)w5[NF_WIDTH + f] * d1) +
-                              (float)w5[2 * NF_WIDTH + f] * d2;
-                    const bool on = pt[cb] < n &&
-                                    (float)acts[((int64_t)4 * NF_WIDTH + f) * ld + pt[cb]] > 0.0f;
-                    s = on ? s : 0.0f;
-                    dzb[cb][m][j] = (__bf16)s;
-                    if (pt[cb] < n)
-                        dzf[((int64_t)3 * NF_WIDTH + f) * ld + pt[cb]] = s;
+                for (int q = 0; q < 4; ++q) {
+                    bf16x8 lo[2];
+#pragma unroll
+                    for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int m = 2 * q + mm;
+                            const int f = 16 * m + 8 * g + j;
+                            float s = ((float)w5[f] * d0 + (float)w5[NF_WIDTH + f] * d1) +
+                                      (float)w5[2 * NF_WIDTH + f] * d2;
+                            s = nf_on(mk, m, j) ? s : 0.0f;
+                            const __bf16 h = (__bf16)s;
+                            dzb[cb][m][j] = h;
+                            lo[mm][j] = (__bf16)(s - (float)h);
+                        }
+                    keep(3, cb, q, dzb[cb][2 * q], dzb[cb][2 * q + 1], lo[0], lo[1], dbs[q]);
                 }
+            }
+            flush(3, dbs);
         }
         // layers 4 -> 1: dH_{k-1} = W_k^T dZ_k, mask with h_{k-1} > 0
 #pragma unroll 1
         for (int k = 3; k >= 1; --k) {
             const __bf16* wimg = nf_launder(v.w[0] + k * NF_IMG_LAYER);
+            const uint2 mk0 = relu[((int64_t)(k - 1) * ntile + T0) * 64 + lane];
+            const uint2 mk1 = relu[((int64_t)(k - 1) * ntile + T0 + 1) * 64 + lane];
+            float dbs[4] = {0.f, 0.f, 0.f, 0.f};
             bf16x8 nxt[2][8];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 floatx16 acc0 = {}, acc1 = {};
-                const int row = 32 * r + (lane & 31);
+                const int row = 32 * r + rr;
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
                     const bf16x8 a = *(const bf16x8*)(wimg + nf_img_off(row, 16 * m + 8 * g));
@@ -261,21 +411,22 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                     acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, dzb[1][m], acc1, 0, 0, 0);
                 }
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int f = 32 * r + 16 * (i >> 3) + 8 * g + (i & 7);
+                for (int cb = 0; cb < 2; ++cb) {
+                    bf16x8 lo[2];
 #pragma unroll
-                    for (int cb = 0; cb < 2; ++cb) {
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = 2 * r + (i >> 3), j = i & 7;
                         float s = cb == 0 ? acc0[i] : acc1[i];
-                        const bool on =
-                            pt[cb] < n &&
-                            (float)acts[((int64_t)k * NF_WIDTH + f) * ld + pt[cb]] > 0.0f;
-                        s = on ? s : 0.0f;
-                        nxt[cb][2 * r + (i >> 3)][i & 7] = (__bf16)s;
-                        if (pt[cb] < n)
-                            dzf[((int64_t)(k - 1) * NF_WIDTH + f) * ld + pt[cb]] = s;
+                        s = nf_on(cb == 0 ? mk0 : mk1, m, j) ? s : 0.0f;
+                        const __bf16 h = (__bf16)s;
+                        nxt[cb][m][j] = h;
+                        lo[i >> 3][j] = (__bf16)(s - (float)h);
                     }
+                    keep(k - 1, cb, r, nxt[cb][2 * r], nxt[cb][2 * r + 1], lo[0], lo[1],
+                         dbs[r]);
                 }
             }
+            flush(k - 1, dbs);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -286,27 +437,31 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
 }
 
 // Weight and bias gradients of all five layers in one launch, split over the
-// points: block (chunk c, layer L) forms the partial sums over its chunk
+// points: block (chunk c, layer L) forms the partial sums over the tiles
+// [t0, t1) of its chunk
 //   dW_L[o][i] = sum_p bf16(g_L[o][p]) a_L[i][p],   db_L[o] = sum_p g_L[o][p]
-// with g_L the FP32 gradient at layer L's output (g_4: the output gradient,
-// 3 rows) and a_L its bf16 input activations, both feature-major with leading
-// dimension ld, and writes them to part[c][L] (NF_PART_LAYER floats per layer:
-// dW row-major, then db).  Matrix products on MFMA 32x32x16 bf16: the A
-// operand is eight consecutive points of a gradient row (converted to bf16
-// with round to nearest even, as the backward's own products use it), the B
-// operand eight consecutive points of an activation row, both straight from
-// memory as 16-byte loads.  Hidden layers: wave w forms rows 32 w.. of the
-// 128 x 128 result; output layer: wave w forms columns 32 w.. of the 3 x 128
-// result (rows 3..31 of its tile are zero).
+// with g_L the gradient at layer L's output (g_4: dOut, 3 rows) and a_L its
+// bf16 input, both in tile order, and writes them to part[c][L]
+// (NF_PART_LAYER floats per layer: dW row-major, then db; db from the
+// backward's per-wave sums).  MFMA 32x32x16 bf16: a tile is two K-steps, K
+// index 8 g + j of step h being tile position 16 g + 8 h + j in both operands
+// (any common order of the points gives the same sums up to rounding).
+// Eight waves: wave w forms row tile w % 4 of a hidden layer's 128 x 128
+// result (column tile w % 4 of the output layer's 3 x 128, rows 3..31 of its
+// tile zero) over the even (w < 4) or odd (w >= 4) tiles of the chunk, with
+// the next tile's operands loaded while the current one's products run; the
+// odd half is added to the even half through LDS.
 constexpr int NF_PART_LAYER = NF_WIDTH * NF_WIDTH + NF_WIDTH;
 constexpr int NF_GRAD_CHUNKS = 64;      // point chunks of one gradient launch (at most)
 
 struct NFGradIn {
-    const float* g[5];       // FP32 gradients: [128][ld] (layers 1-4), [3][ld] (output)
-    const __bf16* a[5];      // bf16 activations [128][ld] (layer inputs)
+    const __bf16* dz[4];     // bf16 gradients of layers 1-4, tile order
+    const float* dout;       // FP32 output gradient [tile][3][32]
+    const __bf16* a[5];      // bf16 layer inputs, tile order
+    const float* dbp;        // per-wave bias sums [wave][NF_DBP]
 };
 
-__device__ inline bf16x8 nf_cvt8(const float4 lo, const float4 hi)
+__device__ __forceinline__ bf16x8 nf_cvt8(const float4 lo, const float4 hi)
 {
     bf16x8 r;
     r[0] = (__bf16)lo.x;
@@ -320,88 +475,126 @@ __device__ inline bf16x8 nf_cvt8(const float4 lo, const float4 hi)
     return r;
 }
 
-// One block's partial sums for layer L; NCT column tiles per wave (4 for a
-// hidden layer, 1 for the output layer).
+// Operands of one tile for one wave: A (two K-steps) and B (two K-steps of
+// NCT column tiles).
 template <int NCT>
-__device__ inline void nf_wgrad_block(const NFGradIn& in, int L, int64_t p0, int64_t p1,
-                                      int64_t ld, float* out)
+struct NFTileOps {
+    bf16x8 A[2];
+    bf16x8 B[NCT][2];
+};
+
+template <int NCT>
+__device__ __forceinline__ void nf_wgrad_load(const NFGradIn& in, int L, int64_t T, int wt,
+                                              NFTileOps<NCT>& o)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int rr = lane & 31;
+    const int64_t pos = 16 * g;
+    if (NCT == 1) {
+        // output layer: A rows are the three outputs (rows 3..31 zero)
+        if (rr < 3) {
+            const float* src = in.dout + (T * 3 + rr) * 32 + pos;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                o.A[h] = nf_cvt8(*(const float4*)(src + 8 * h), *(const float4*)(src + 8 * h + 4));
+        } else {
+            o.A[0] = bf16x8{};
+            o.A[1] = bf16x8{};
+        }
+        const __bf16* b = in.a[L] + (T * NF_WIDTH + 32 * wt + rr) * 32 + pos;
+        o.B[0][0] = *(const bf16x8*)b;
+        o.B[0][1] = *(const bf16x8*)(b + 8);
+    } else {
+        const __bf16* a = in.dz[L] + (T * NF_WIDTH + 32 * wt + rr) * 32 + pos;
+        o.A[0] = *(const bf16x8*)a;
+        o.A[1] = *(const bf16x8*)(a + 8);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const __bf16* b = in.a[L] + (T * NF_WIDTH + 32 * ct + rr) * 32 + pos;
+            o.B[ct][0] = *(const bf16x8*)b;
+            o.B[ct][1] = *(const bf16x8*)(b + 8);
+        }
+    }
+}
+
+template <int NCT>
+__device__ inline void nf_wgrad_block(const NFGradIn& in, int L, int64_t t0, int64_t t1,
+                                      float* red, float* out)
 {
     constexpr bool out_layer = NCT == 1;
     const int lane = (int)(threadIdx.x & 63u);
     const int g = lane >> 5;
+    const int rr = lane & 31;
     const int w = (int)(threadIdx.x >> 6);
-    // this lane's gradient row (A operand) and activation rows (B operands)
-    const int arow = out_layer ? (lane & 31) : 32 * w + (lane & 31);
-    const bool alive = !out_layer || arow < 3;
-    const float* grow = in.g[L] + (int64_t)(alive ? arow : 0) * ld;
-    const __bf16* abase = in.a[L];
+    const int wt = w & 3, kg = w >> 2;
     floatx16 acc[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct)
         acc[ct] = floatx16{};
-    float bsum = 0.0f;
-    for (int64_t p = p0; p < p1; p += 16) {
-        const int64_t q = p + 8 * g;          // this lane's eight points
-        float4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
-        const bool full = q + 8 <= p1;
-        if (alive && full) {
-            lo = *(const float4*)(grow + q);
-            hi = *(const float4*)(grow + q + 4);
-        } else if (alive) {
-            float v[8];
+    int64_t T = t0 + kg;
+    NFTileOps<NCT> cur, nxt;
+    if (T < t1)
+        nf_wgrad_load<NCT>(in, L, T, wt, cur);
+    for (; T < t1; T += 2) {
+        if (T + 2 < t1)
+            nf_wgrad_load<NCT>(in, L, T + 2, wt, nxt);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                v[j] = q + j < p1 ? grow[q + j] : 0.0f;
-            lo = make_float4(v[0], v[1], v[2], v[3]);
-            hi = make_float4(v[4], v[5], v[6], v[7]);
-        }
-        bsum += ((lo.x + lo.y) + (lo.z + lo.w)) + ((hi.x + hi.y) + (hi.z + hi.w));
-        const bf16x8 A = nf_cvt8(lo, hi);
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-            const int col = out_layer ? 32 * w + (lane & 31) : 32 * ct + (lane & 31);
-            const __bf16* brow = abase + (int64_t)col * ld;
-            bf16x8 B;
-            if (full) {
-                B = *(const bf16x8*)(brow + q);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    B[j] = q + j < p1 ? brow[q + j] : (__bf16)0.0f;
-            }
-            acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A, B, acc[ct], 0, 0, 0);
-        }
+            for (int ct = 0; ct < NCT; ++ct)
+                acc[ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur.A[h], cur.B[ct][h], acc[ct],
+                                                                  0, 0, 0);
+        cur = nxt;
     }
-    // result element i of a lane: row 8 (i / 4) + 4 g + i % 4 of the tile, its column
+    // the odd tiles' sums to LDS, added by the wave of the same tile
+    if (kg == 1)
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int r = 8 * (i >> 2) + 4 * g + (i & 3);
-            if (out_layer) {
-                if (r < 3)
-                    out[r * NF_WIDTH + 32 * w + (lane & 31)] = acc[ct][i];
-            } else {
-                out[(32 * w + r) * NF_WIDTH + 32 * ct + (lane & 31)] = acc[ct][i];
+            for (int i = 0; i < 16; ++i)
+                red[((wt * NCT + ct) * 16 + i) * 64 + lane] = acc[ct][i];
+    __syncthreads();
+    if (kg == 0) {
+        // result element i of a lane: row 8 (i / 4) + 4 g + i % 4 of the
+        // tile, column rr
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const float s = acc[ct][i] + red[((wt * NCT + ct) * 16 + i) * 64 + lane];
+                const int r = 8 * (i >> 2) + 4 * g + (i & 3);
+                if (out_layer) {
+                    if (r < 3)
+                        out[r * NF_WIDTH + 32 * wt + rr] = s;
+                } else {
+                    out[(32 * wt + r) * NF_WIDTH + 32 * ct + rr] = s;
+                }
             }
-        }
-    // bias partials: the two lanes of a row hold its two halves of each step
-    bsum += __shfl_xor(bsum, 32);
-    if (g == 0 && alive && (!out_layer || w == 0))
-        out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + arow] = bsum;
+    }
+    // bias partials: the chunk's per-wave sums in order
+    const int nb = out_layer ? 3 : NF_WIDTH;
+    const int off = out_layer ? 4 * NF_WIDTH : L * NF_WIDTH;
+    for (int f = (int)threadIdx.x; f < nb; f += (int)blockDim.x) {
+        float s = 0.0f;
+        for (int64_t wv = t0 >> 1; wv < (t1 >> 1); ++wv)
+            s += in.dbp[wv * NF_DBP + off + f];
+        out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + f] = s;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_nf_wgrad(NFGradIn in, int64_t n, int64_t ld,
-                                                  int64_t chunk, float* part)
+__global__ void __launch_bounds__(512) k_nf_wgrad(NFGradIn in, int64_t ntl, int64_t chunk,
+                                                  float* part)
 {
+    __shared__ float red[4 * 4 * 16 * 64];
     const int L = (int)blockIdx.y;
-    const int64_t p0 = (int64_t)blockIdx.x * chunk;
-    const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+    const int64_t t0 = (int64_t)blockIdx.x * chunk;
+    const int64_t t1 = t0 + chunk < ntl ? t0 + chunk : ntl;
     float* out = part + ((int64_t)blockIdx.x * 5 + L) * NF_PART_LAYER;
     if (L == 4)
-        nf_wgrad_block<1>(in, L, p0, p1, ld, out);
+        nf_wgrad_block<1>(in, L, t0, t1, red, out);
     else
-        nf_wgrad_block<4>(in, L, p0, p1, ld, out);
+        nf_wgrad_block<4>(in, L, t0, t1, red, out);
 }
 
 // Sum of the chunk partials into the flat gradient (W1, b1, ..., W4, b4, W5,
@@ -476,8 +669,10 @@ struct NeuralField {
     // training buffers
     int64_t cap = 0;
     float *xh = nullptr, *tgt = nullptr, *out = nullptr, *dout = nullptr;
-    __bf16* acts = nullptr;
-    float* dzf = nullptr;
+    __bf16* acts = nullptr;     // five layer inputs, tile order
+    __bf16* dz = nullptr;       // four hidden gradients, tile order
+    uint2* relu = nullptr;      // ReLU patterns of the hidden outputs
+    float* dbp = nullptr;       // per-wave bias sums
     float* part = nullptr;      // split-K partial gradients [NF_GRAD_CHUNKS][5][NF_PART_LAYER]
     double* loss = nullptr;
     int num_cus = 256;
@@ -488,11 +683,13 @@ struct NeuralField {
 static void nf_free_train(NeuralField* nf)
 {
     for (void* p : {(void*)nf->xh, (void*)nf->tgt, (void*)nf->out, (void*)nf->dout,
-                    (void*)nf->acts, (void*)nf->dzf, (void*)nf->part})
+                    (void*)nf->acts, (void*)nf->dz, (void*)nf->relu, (void*)nf->dbp,
+                    (void*)nf->part})
         if (p)
             (void)hipFree(p);
-    nf->xh = nf->tgt = nf->out = nf->dout = nf->dzf = nf->part = nullptr;
-    nf->acts = nullptr;
+    nf->xh = nf->tgt = nf->out = nf->dout = nf->dbp = nf->part = nullptr;
+    nf->acts = nf->dz = nullptr;
+    nf->relu = nullptr;
     nf->cap = 0;
 }
 
@@ -653,7 +850,9 @@ static hipError_t nf_ensure_cap(NeuralField* nf, int64_t n)
     al((void**)&nf->out, ld * 12);
     al((void**)&nf->dout, ld * 12);
     al((void**)&nf->acts, (size_t)5 * NF_WIDTH * ld * 2);
-    al((void**)&nf->dzf, (size_t)4 * NF_WIDTH * ld * 4);
+    al((void**)&nf->dz, (size_t)4 * NF_WIDTH * ld * 2);
+    al((void**)&nf->relu, (size_t)4 * (ld / 32) * 64 * sizeof(uint2));
+    al((void**)&nf->dbp, (size_t)(ld / 64) * NF_DBP * 4);
     al((void**)&nf->part, (size_t)NF_GRAD_CHUNKS * 5 * NF_PART_LAYER * 4);
     if (e == hipSuccess)
         nf->cap = ld;
@@ -670,23 +869,27 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
     hipError_t e = hipMemsetAsync(nf->loss, 0, 8, s);
     if (e != hipSuccess)
         return e;
-    k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, nf->acts, nf->out);
+    k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, nf->acts, nf->relu,
+                                           nf->out);
     k_nf_loss<<<256, 256, 0, s>>>(nf->out, nf->tgt, n, nf->loss);
-    k_nf_bwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->acts,
-                                           nf->dzf, nf->dout, (float)(1.0 / (double)n));
-    // split over at most NF_GRAD_CHUNKS chunks of a multiple of 16 points
-    int64_t chunk = (n + NF_GRAD_CHUNKS - 1) / NF_GRAD_CHUNKS;
-    chunk = (chunk + 15) & ~int64_t(15);
-    if (chunk < 256)
-        chunk = 256;
-    const int nchunks = (int)((n + chunk - 1) / chunk);
+    k_nf_bwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->relu,
+                                           nf->dz, nf->dout, nf->dbp, (float)(1.0 / (double)n));
+    // the tiles of whole waves, split over at most NF_GRAD_CHUNKS chunks of an
+    // even number (whole waves) of at least 8 tiles
+    const int64_t ntl = 2 * ((n + 63) / 64);
+    int64_t chunk = (ntl + NF_GRAD_CHUNKS - 1) / NF_GRAD_CHUNKS;
+    chunk = (chunk + 1) & ~int64_t(1);
+    if (chunk < 8)
+        chunk = 8;
+    const int nchunks = (int)((ntl + chunk - 1) / chunk);
     NFGradIn gi;
     for (int k = 0; k < 4; ++k)
-        gi.g[k] = nf->dzf + (int64_t)k * NF_WIDTH * ld;
-    gi.g[4] = nf->dout;
+        gi.dz[k] = nf->dz + (int64_t)k * NF_WIDTH * ld;
+    gi.dout = nf->dout;
     for (int k = 0; k < 5; ++k)
         gi.a[k] = nf->acts + (int64_t)k * NF_WIDTH * ld;
-    k_nf_wgrad<<<dim3(nchunks, 5), 256, 0, s>>>(gi, n, ld, chunk, nf->part);
+    gi.dbp = nf->dbp;
+    k_nf_wgrad<<<dim3(nchunks, 5), 512, 0, s>>>(gi, ntl, chunk, nf->part);
     k_nf_wgrad_reduce<<<(NF_NPARAM + 255) / 256, 256, 0, s>>>(nf->part, nchunks, nf->grad);
     return hipGetLastError();
 }

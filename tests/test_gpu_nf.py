@@ -56,19 +56,21 @@ def rel_l2(a, b):
     return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def test_nf_loss_and_gradients_match_oracle(P, N):
+@pytest.mark.parametrize("n", [3000, 37, 20011])
+def test_nf_loss_and_gradients_match_oracle(P, N, n):
+    """3000: several waves and a ragged tail; 37: one partial wave; 20011: 63
+    chunks of the split weight-gradient sum, each over an odd and an even half."""
     w = I.W_SMALL
     grid = w.make_grid().astype(np.float32)
     ctx = make_ctx(P, grid, w.spacing_m)
     F = I.nf_frequencies()
     params = init_params()
     ctx.nf_init(F, params, I.NG_T)
-    n = 3000                                   # several waves and a ragged tail
     rng = np.random.default_rng(3)
     box = 32 * w.spacing_m
     pos = (rng.random((n, 3)) * 3 - 1) * box   # several periods, both signs
     target = rng.standard_normal((n, 3)).astype(np.float32)
-    say("nf loss/grad")
+    say(f"nf loss/grad, {n} points")
     out, grad, loss = ctx.nf_loss_grad(pos, target)
     xh = N.normalized_position(pos, (32, 32, 32), w.spacing_m).astype(np.float32)
     ws, bs = N.unflatten(params)
