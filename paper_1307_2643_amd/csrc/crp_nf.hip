@@ -114,28 +114,31 @@ __global__ void k_nf_xhat(NFGeom G, int64_t n, const double* pos, float* xh)
 }
 
 // Training samples: uniform points in one period of the grid (Philox draws
-// keyed by the run seed and the sample's index) and the grid's trilinear
-// field there (FP32 weights and sums), in units of b_scale.
-__global__ void k_nf_sample(GridView g, NFGeom G, int64_t n, uint64_t seed, uint64_t offset,
-                            float* xh, float* tgt)
+// keyed by the run seed and the sample's index) as xhat (FP32) and position,
+// then the grid's trilinear field there (FP32 weights and sums) in units of
+// b_scale.
+__device__ __forceinline__ void nf_sample_xhat(const NFGeom& G, uint64_t seed, uint64_t idx,
+                                               float xh[3], double p[3])
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    const U64x4 w = philox4x64_10(offset + (uint64_t)i, 0, 0, 0, seed, 0x4e46u);
-    double p[3];
+    const U64x4 w = philox4x64_10(idx, 0, 0, 0, seed, 0x4e46u);
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double u = (double)(w.w[a] >> 11) * 0x1p-53;
-        xh[3 * i + a] = (float)u;
+        xh[a] = (float)u;
         p[a] = G.origin[a] + u * G.box[a];
     }
+}
+
+__device__ __forceinline__ void nf_sample_target(const GridView& g, const NFGeom& G,
+                                                 const double p[3], float tgt[3])
+{
     const GridField<float, 0> F{g};
     float B[3];
     F.fp32(p, B);
     const float inv = 1.0f / G.b_scale;
-    tgt[3 * i] = B[0] * inv;
-    tgt[3 * i + 1] = B[1] * inv;
-    tgt[3 * i + 2] = B[2] * inv;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        tgt[c] = B[c] * inv;
 }
 
 // -------------------------------------------------------------------------
@@ -226,13 +229,17 @@ __device__ __forceinline__ bool nf_on(const uint2 mk, int m, int j)
 
 constexpr int NF_DBP = 4 * NF_WIDTH + 4;     // per-wave bias sums: dZ_1..dZ_4, dOut, pad
 
-// Training forward for the points in xh (whole waves of 64 points, two tiles;
-// points past n repeat point n - 1): the outputs, the input of every layer in
-// tile order (acts: five layers of [tile][128][32] bf16) and the ReLU pattern
-// of the four hidden outputs (relu: [4][tile][64 lanes]) for the backward.
+// Training forward (whole waves of 64 points, two tiles; points past n repeat
+// point n - 1): the outputs, the input of every layer in tile order (acts:
+// five layers of [tile][128][32] bf16) and the ReLU pattern of the four hidden
+// outputs (relu: [4][tile][64 lanes]) for the backward.  The points are the
+// caller's (xh) or, with `sample`, drawn here (indices offset.. of the Philox
+// stream seed) with their targets (tgt) from the grid, read after the network
+// so that the gathers' latency is hidden behind it.
 __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64_t n, int64_t ld,
-                                                const float* xh, __bf16* acts, uint2* relu,
-                                                float* out)
+                                                const float* xh, bool sample, GridView grid,
+                                                uint64_t seed, uint64_t offset, float* tgt,
+                                                __bf16* acts, uint2* relu, float* out)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img);
@@ -248,12 +255,28 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
         const int64_t T0 = base >> 5;
+        const int64_t me = base + lane;
+        float sx[3] = {0.f, 0.f, 0.f};
+        double sp[3] = {0.0, 0.0, 0.0};
+        if (sample)
+            nf_sample_xhat(G, seed, offset + (uint64_t)(me < n ? me : n - 1), sx, sp);
         bf16x8 a[2][8], b[2][8];
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int64_t p = base + 32 * cb + rr;
             const int64_t q = p < n ? p : n - 1;
-            nf_embed_fp64(v.freq, xh[3 * q], xh[3 * q + 1], xh[3 * q + 2], g, a[cb]);
+            float x0, x1, x2;
+            if (sample) {
+                const int src = (int)(q - base);
+                x0 = __shfl(sx[0], src);
+                x1 = __shfl(sx[1], src);
+                x2 = __shfl(sx[2], src);
+            } else {
+                x0 = xh[3 * q];
+                x1 = xh[3 * q + 1];
+                x2 = xh[3 * q + 2];
+            }
+            nf_embed_fp64(v.freq, x0, x1, x2, g, a[cb]);
         }
         auto keep = [&](int L, const bf16x8 h[2][8]) {
             __bf16* dst = acts + (int64_t)L * NF_WIDTH * ld;
@@ -279,11 +302,18 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
         keep(4, a);
         float o[3];
         nf_output(v.w5, v.bias + 4 * NF_WIDTH, a, o);
-        const int64_t me = base + lane;
-        if (me < n)
+        if (me < n) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 out[3 * me + c] = o[c];
+            if (sample) {
+                float t[3];
+                nf_sample_target(grid, G, sp, t);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    tgt[3 * me + c] = t[c];
+            }
+        }
     }
 }
 
@@ -295,11 +325,12 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
 // bias gradients, each wave's sums over its 64 points (dbp: [wave][NF_DBP],
 // dZ_1..dZ_4 by 128 features, then the three outputs).  The sums take dZ as
 // bf16(dZ) + bf16(dZ - bf16(dZ)), within 2^-17 of the FP32 value, both parts
-// transposed exactly on the matrix cores.
+// transposed exactly on the matrix cores.  Adds the loss mean_p |out - tgt|^2
+// (FP64; one atomic per wave) to *loss.
 __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int64_t n,
                                                 int64_t ld, const float* out, const float* tgt,
                                                 const uint2* relu, __bf16* dz, float* dout,
-                                                float* dbp, float inv_n)
+                                                float* dbp, double* loss, float inv_n)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img_t);
@@ -318,14 +349,23 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
         float* db = dbp + (base >> 6) * NF_DBP;
         // dOut of this lane's own point, in tile order, and its wave sums
         float d[3] = {0.f, 0.f, 0.f}, dr[3] = {0.f, 0.f, 0.f};
+        double sq = 0.0;
         const int64_t me = base + lane;
         if (me < n) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                d[c] = 2.0f * (out[3 * me + c] - tgt[3 * me + c]) * inv_n;
+                const float oc = out[3 * me + c], tc = tgt[3 * me + c];
+                d[c] = 2.0f * (oc - tc) * inv_n;
                 dr[c] = (float)(__bf16)d[c];
+                const double e = (double)oc - (double)tc;
+                sq += e * e;
             }
         }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+            sq += __shfl_xor(sq, o);
+        if (lane == 0)
+            atomicAdd(loss, sq / (double)n);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             dout[((T0 + g) * 3 + c) * 32 + nf_tile_pos(rr)] = d[c];
@@ -434,6 +474,25 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                     dzb[cb][m] = nxt[cb][m];
         }
     }
+}
+
+// Sum of n values p[0], p[stride], ... in index order, eight loads in flight.
+__device__ __forceinline__ float nf_sum_strided(const float* p, int64_t stride, int n)
+{
+    float s = 0.0f;
+    int c = 0;
+    for (; c + 8 <= n; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = p[(int64_t)(c + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            s += v[u];
+    }
+    for (; c < n; ++c)
+        s += p[(int64_t)c * stride];
+    return s;
 }
 
 // Weight and bias gradients of all five layers in one launch, split over the
@@ -575,12 +634,10 @@ __device__ inline void nf_wgrad_block(const NFGradIn& in, int L, int64_t t0, int
     // bias partials: the chunk's per-wave sums in order
     const int nb = out_layer ? 3 : NF_WIDTH;
     const int off = out_layer ? 4 * NF_WIDTH : L * NF_WIDTH;
-    for (int f = (int)threadIdx.x; f < nb; f += (int)blockDim.x) {
-        float s = 0.0f;
-        for (int64_t wv = t0 >> 1; wv < (t1 >> 1); ++wv)
-            s += in.dbp[wv * NF_DBP + off + f];
-        out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + f] = s;
-    }
+    for (int f = (int)threadIdx.x; f < nb; f += (int)blockDim.x)
+        out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + f] =
+            nf_sum_strided(in.dbp + (t0 >> 1) * NF_DBP + off + f, NF_DBP,
+                           (int)((t1 >> 1) - (t0 >> 1)));
 }
 
 __global__ void __launch_bounds__(512) k_nf_wgrad(NFGradIn in, int64_t ntl, int64_t chunk,
@@ -608,48 +665,63 @@ __global__ void k_nf_wgrad_reduce(const float* part, int nchunks, float* grad)
     // layer: W5 [3][128] then b5 [3], also as in its partial
     const int L = e < NF_W5 ? e / NF_LAYER_PARAMS : 4;
     const int k = e < NF_W5 ? e % NF_LAYER_PARAMS : e - NF_W5;
-    float s = 0.0f;
-    for (int c = 0; c < nchunks; ++c)
-        s += part[((int64_t)c * 5 + L) * NF_PART_LAYER + k];
-    grad[e] = s;
+    grad[e] = nf_sum_strided(part + (int64_t)L * NF_PART_LAYER + k, (int64_t)5 * NF_PART_LAYER,
+                             nchunks);
 }
 
-// Mean squared error sum_c (out - tgt)^2 averaged over points.
-__global__ void k_nf_loss(const float* out, const float* tgt, int64_t n, double* loss)
+// Physical row of logical row l in a 128-row weight image (inverse of
+// nf_logical_row).
+__device__ __forceinline__ int nf_phys_row(int l)
 {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double d = (double)out[i] - (double)tgt[i];
-        s += d * d;
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        atomicAdd(loss, red[0] / (double)n);
+    const int t = l & 31;
+    const int i = 8 * (t >> 4) + (t & 7), g = (t >> 3) & 1;
+    return 32 * (l >> 5) + 8 * (i >> 2) + 4 * g + (i & 3);
 }
 
-// Adam (Kingma & Ba) with bias correction on the FP32 masters.
-__global__ void k_nf_adam(float* p, const float* gr, float* m, float* v, int n, float lr,
-                          float c1, float c2)
+// One Adam step (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias
+// corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t) of every FP32 master with
+// its gradient summed over the nchunks partials (chunks in order; the flat
+// gradient itself is a one-chunk partial), then the parameter's bf16 copies in
+// the forward and backward images, placed as k_nf_pack places them: the
+// gradient reduction, the update and the repacking in one pass.
+__global__ void k_nf_update(const float* part, int nchunks, float* p, float* m, float* v,
+                            float lr, float c1, float c2, char* fwd, char* bwd)
 {
-    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    if (i >= n)
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= NF_NPARAM)
         return;
+    const int L = e < NF_W5 ? e / NF_LAYER_PARAMS : 4;
+    const int k = e < NF_W5 ? e % NF_LAYER_PARAMS : e - NF_W5;
+    const float gs = nf_sum_strided(part + (int64_t)L * NF_PART_LAYER + k,
+                                    (int64_t)5 * NF_PART_LAYER, nchunks);
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float g = gr[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * g;
-    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
-    m[i] = mi;
-    v[i] = vi;
+    const float mi = b1 * m[e] + (1.0f - b1) * gs;
+    const float vi = b2 * v[e] + (1.0f - b2) * gs * gs;
+    m[e] = mi;
+    v[e] = vi;
     const float mh = mi / c1, vh = vi / c2;
-    p[i] = p[i] - lr * mh / (sqrtf(vh) + eps);
+    const float pn = p[e] - lr * mh / (sqrtf(vh) + eps);
+    p[e] = pn;
+    __bf16* wf = (__bf16*)fwd;
+    __bf16* wb = (__bf16*)bwd;
+    float* bf = (float*)(fwd + 4 * NF_IMG_LAYER * 2 + 3 * NF_WIDTH * 2);
+    float* bb = (float*)(bwd + 4 * NF_IMG_LAYER * 2 + 3 * NF_WIDTH * 2);
+    if (L < 4) {
+        if (k < NF_IMG_LAYER) {
+            const int o = k / NF_WIDTH, i = k % NF_WIDTH;    // W_L[o][i]
+            wf[L * NF_IMG_LAYER + nf_img_off(nf_phys_row(o), i)] = (__bf16)pn;
+            wb[L * NF_IMG_LAYER + nf_img_off(nf_phys_row(i), o)] = (__bf16)pn;
+        } else {
+            bf[L * NF_WIDTH + (k - NF_IMG_LAYER)] = pn;
+            bb[L * NF_WIDTH + (k - NF_IMG_LAYER)] = pn;
+        }
+    } else if (k < 3 * NF_WIDTH) {
+        wf[4 * NF_IMG_LAYER + k] = (__bf16)pn;
+        wb[4 * NF_IMG_LAYER + k] = (__bf16)pn;
+    } else {
+        bf[4 * NF_WIDTH + (k - 3 * NF_WIDTH)] = pn;
+        bb[4 * NF_WIDTH + (k - 3 * NF_WIDTH)] = pn;
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -859,21 +931,22 @@ static hipError_t nf_ensure_cap(NeuralField* nf, int64_t n)
     return e;
 }
 
-// Forward + backward + gradients for the points already in nf->xh / nf->tgt.
-static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
+// Forward, backward and the split weight gradients (chunk partials in
+// nf->part; their count in *nchunks).  The points are those in nf->xh /
+// nf->tgt, or with `sample` drawn in the forward (indices offset.. of the
+// Philox stream seed, targets from the grid g).  The loss is added to *loss.
+static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, const GridView& g, int64_t n,
+                             bool sample, uint64_t seed, uint64_t offset, double* loss,
+                             int* nchunks)
 {
     hipStream_t s = nf->stream;
     const int64_t ld = nf->cap;
     const int nb = nf_eval_blocks(nf, n);
-    // (the gradient is written whole by the reduction)
-    hipError_t e = hipMemsetAsync(nf->loss, 0, 8, s);
-    if (e != hipSuccess)
-        return e;
-    k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, nf->acts, nf->relu,
-                                           nf->out);
-    k_nf_loss<<<256, 256, 0, s>>>(nf->out, nf->tgt, n, nf->loss);
+    k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, sample, g, seed, offset,
+                                           nf->tgt, nf->acts, nf->relu, nf->out);
     k_nf_bwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->relu,
-                                           nf->dz, nf->dout, nf->dbp, (float)(1.0 / (double)n));
+                                           nf->dz, nf->dout, nf->dbp, loss,
+                                           (float)(1.0 / (double)n));
     // the tiles of whole waves, split over at most NF_GRAD_CHUNKS chunks of an
     // even number (whole waves) of at least 8 tiles
     const int64_t ntl = 2 * ((n + 63) / 64);
@@ -881,7 +954,7 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
     chunk = (chunk + 1) & ~int64_t(1);
     if (chunk < 8)
         chunk = 8;
-    const int nchunks = (int)((ntl + chunk - 1) / chunk);
+    *nchunks = (int)((ntl + chunk - 1) / chunk);
     NFGradIn gi;
     for (int k = 0; k < 4; ++k)
         gi.dz[k] = nf->dz + (int64_t)k * NF_WIDTH * ld;
@@ -889,26 +962,21 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, int64_t n)
     for (int k = 0; k < 5; ++k)
         gi.a[k] = nf->acts + (int64_t)k * NF_WIDTH * ld;
     gi.dbp = nf->dbp;
-    k_nf_wgrad<<<dim3(nchunks, 5), 512, 0, s>>>(gi, ntl, chunk, nf->part);
-    k_nf_wgrad_reduce<<<(NF_NPARAM + 255) / 256, 256, 0, s>>>(nf->part, nchunks, nf->grad);
+    k_nf_wgrad<<<dim3(*nchunks, 5), 512, 0, s>>>(gi, ntl, chunk, nf->part);
     return hipGetLastError();
 }
 
-// One Adam step of the masters with the gradient in nf->grad (step count
-// t + 1 for the bias corrections, formed in FP64 and rounded once), then the
-// bf16 images are repacked.
-static hipError_t nf_adam_launch(NeuralField* nf, double lr)
+// One Adam step of the masters with the gradient summed over nchunks
+// partials (step count t + 1 for the bias corrections, formed in FP64 and
+// rounded once), the bf16 images updated in the same pass.
+static hipError_t nf_update_launch(NeuralField* nf, const float* part, int nchunks, double lr)
 {
     nf->t += 1;
     const float c1 = (float)(1.0 - std::pow(0.9, (double)nf->t));
     const float c2 = (float)(1.0 - std::pow(0.999, (double)nf->t));
-    k_nf_adam<<<(NF_NPARAM + 255) / 256, 256, 0, nf->stream>>>(nf->master, nf->grad, nf->am,
-                                                                 nf->av, NF_NPARAM, (float)lr, c1,
-                                                                 c2);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess)
-        e = nf_pack(nf);
-    return e;
+    k_nf_update<<<(NF_NPARAM + 255) / 256, 256, 0, nf->stream>>>(
+        part, nchunks, nf->master, nf->am, nf->av, (float)lr, c1, c2, nf->img_fwd, nf->img_bwd);
+    return hipGetLastError();
 }
 
 crp_status nf_adam_step(NeuralField* nf, const float* grad, double lr, std::string& err)
@@ -916,7 +984,7 @@ crp_status nf_adam_step(NeuralField* nf, const float* grad, double lr, std::stri
     hipError_t e = hipMemcpyAsync(nf->grad, grad, NF_NPARAM * 4, hipMemcpyHostToDevice,
                                   nf->stream);
     if (e == hipSuccess)
-        e = nf_adam_launch(nf, lr);
+        e = nf_update_launch(nf, nf->grad, 1, lr);
     if (e == hipSuccess)
         e = hipStreamSynchronize(nf->stream);
     if (e != hipSuccess) {
@@ -944,8 +1012,15 @@ crp_status nf_loss_grad(NeuralField* nf, const GridView& g, int64_t n, const dou
         k_nf_xhat<<<(int)((n + 255) / 256), 256, 0, s>>>(G, n, dpos, nf->xh);
         e = hipGetLastError();
     }
+    int nchunks = 0;
     if (e == hipSuccess)
-        e = nf_fwd_bwd(nf, G, n);
+        e = hipMemsetAsync(nf->loss, 0, 8, s);
+    if (e == hipSuccess)
+        e = nf_fwd_bwd(nf, G, g, n, false, 0, 0, nf->loss, &nchunks);
+    if (e == hipSuccess) {
+        k_nf_wgrad_reduce<<<(NF_NPARAM + 255) / 256, 256, 0, s>>>(nf->part, nchunks, nf->grad);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess && out)
         e = hipMemcpyAsync(out, nf->out, n * 12, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && grad)
@@ -976,23 +1051,29 @@ crp_status nf_train(NeuralField* nf, const GridView& g, int64_t steps, int64_t b
     hipStream_t s = nf->stream;
     hipError_t e = nf_ensure_cap(nf, batch);
     const NFGeom G = nf_geom(nf, g);
-    std::vector<double> losses((size_t)(steps > 0 ? steps : 1));
+    // the losses of all steps stay on the device until the end
+    double* dloss = nullptr;
+    const size_t lbytes = (size_t)(steps > 0 ? steps : 1) * 8;
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&dloss, lbytes);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(dloss, 0, lbytes, s);
     for (int64_t it = 0; it < steps && e == hipSuccess; ++it) {
-        k_nf_sample<<<(int)((batch + 255) / 256), 256, 0, s>>>(g, G, batch, seed,
-                                                                (uint64_t)(it * batch), nf->xh,
-                                                                nf->tgt);
-        e = hipGetLastError();
-        if (e == hipSuccess)
-            e = nf_fwd_bwd(nf, G, batch);
+        int nchunks = 0;
+        e = nf_fwd_bwd(nf, G, g, batch, true, seed, (uint64_t)(it * batch), dloss + it, &nchunks);
         if (e == hipSuccess) {
             const double frac = steps > 1 ? (double)it / (double)(steps - 1) : 1.0;
-            e = nf_adam_launch(nf, lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * frac)));
+            e = nf_update_launch(nf, nf->part, nchunks,
+                                 lr1 + 0.5 * (lr0 - lr1) * (1.0 + std::cos(M_PI * frac)));
         }
-        if (e == hipSuccess && loss_out)
-            e = hipMemcpyAsync(&losses[(size_t)it], nf->loss, 8, hipMemcpyDeviceToHost, s);
     }
+    std::vector<double> losses((size_t)(steps > 0 ? steps : 1));
+    if (e == hipSuccess && loss_out && steps > 0)
+        e = hipMemcpyAsync(losses.data(), dloss, (size_t)steps * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
+    if (dloss)
+        (void)hipFree(dloss);
     if (e != hipSuccess) {
         err = std::string("nf_train: ") + hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? CRP_ENOMEM : CRP_EDEVICE;

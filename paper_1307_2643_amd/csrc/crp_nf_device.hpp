@@ -84,13 +84,27 @@ __device__ __attribute__((always_inline)) inline NFView nf_view_lds(char* base, 
     return v;
 }
 
-// Cooperative copy of the global network image (same layout) into LDS.
+// Cooperative copy of the global network image (same layout) into LDS, eight
+// 16-byte loads of a thread in flight before their LDS writes (one at a time,
+// each write would wait for its load: ~33 memory latencies per block).
 __device__ __attribute__((always_inline)) inline void nf_stage_lds(char* dst, const char* src)
 {
+    constexpr int U = 8;
     const int4* s = (const int4*)src;
     int4* d = (int4*)dst;
     const int n16 = (int)(NF_LDS_BYTES / 16);
-    for (int i = threadIdx.x; i < n16; i += blockDim.x)
+    const int nt = (int)blockDim.x;
+    int i = (int)threadIdx.x;
+    for (; i + (U - 1) * nt < n16; i += U * nt) {
+        int4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = s[i + u * nt];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            d[i + u * nt] = v[u];
+    }
+    for (; i < n16; i += nt)
         d[i] = s[i];
 }
 

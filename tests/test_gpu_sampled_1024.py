@@ -326,3 +326,57 @@ def test_neural_field_full_size(P, big):
     assert rms < 0.35
     assert dist <= 0.02
     assert len(fn["id"]) >= m and len(fg["id"]) >= m
+
+
+def test_neural_field_narrow_band_under_one_percent(P, big):
+    """The learned form at its stated error: on a 1024^3 FP32 field of the band
+    2..3 cycles per box (seed 3, 1 nG RMS, 10 kpc cells), whose 48 modes the 64
+    Fourier features can hold, the network trained on 3e9 points (45,780 steps
+    of 65,536, lr 3e-3 -> 1e-5) by the library's own kernels is within 1% RMS
+    of the grid's field on held-out points, and 2e5 distance-workload
+    candidates propagated with it have a deflection-angle histogram within 2%
+    (total variation, 36 bins) of the grid run's."""
+    import torch
+    wd = I.W_DIST1024
+    m = 200_000
+    grid = I.turbulent_grid(wd.grid_n, wd.spacing_m, 2.0, 3.0, wd.brms_T, 3, np.float32,
+                            torch.device("cuda:0"))
+    prm = P.params_for(wd, P.MIX, device=0, field_mode=P.FIELD_NEURAL, queue_capacity=2 * m,
+                       neutral_capacity=1 << 20)
+    ctx = P.Context(prm)
+    ctx.set_field_grid(grid, wd.spacing_m)
+    ctx.set_tables(big["tables"])
+    ctx.nf_init(I.nf_frequencies(nmin=2.0, nmax=3.0, seed=505), I.nf_init_flat(509), wd.brms_T)
+    say("training the network on 3e9 points of the 2..3 band")
+    losses = ctx.nf_train(45780, 65536, 3e-3, 1e-5, 506)
+    assert np.all(np.isfinite(losses))
+    pos = I.uniform_points(200_000, wd.grid_n * wd.spacing_m, 507)
+    Bn = ctx.eval_field(pos, P.EVAL_NEURAL)
+    Bg = ctx.eval_field(pos, P.MIX)
+    rms = float(np.sqrt(((Bn - Bg) ** 2).sum(1).mean()) / wd.brms_T)
+    say(f"narrow band: RMS field error {rms:.4f} of B_rms")
+    assert rms <= 0.01
+    inj = I.inject_distances(m, 508)
+    ctx.inject(inj)
+    assert ctx.propagate(0)
+    fn = ctx.read_finished()
+    ctx.close()
+    gprm = P.params_for(wd, P.MIX, device=0, queue_capacity=2 * m, neutral_capacity=1 << 20)
+    cg = P.Context(gprm)
+    cg.set_field_grid(grid, wd.spacing_m)
+    cg.set_tables(big["tables"])
+    cg.inject(inj)
+    assert cg.propagate(0)
+    fg = cg.read_finished()
+    cg.close()
+    del grid
+    torch.cuda.empty_cache()
+
+    def hist(f):
+        th = np.degrees(np.arccos(np.clip((f["u"] * f["u0"]).sum(1), -1, 1)))
+        return np.histogram(th, bins=36, range=(0, 180))[0] / len(th)
+
+    dist = float(0.5 * np.abs(hist(fn) - hist(fg)).sum())
+    say(f"narrow band: deflection histogram distance {dist:.4f}")
+    assert dist <= 0.02
+    assert len(fn["id"]) >= m and len(fg["id"]) >= m
