@@ -227,19 +227,81 @@ __device__ __forceinline__ bool nf_on(const uint2 mk, int m, int j)
     return (((m < 4 ? mk.x : mk.y) >> (8 * (m & 3) + j)) & 1u) != 0;
 }
 
-constexpr int NF_DBP = 4 * NF_WIDTH + 4;     // per-wave bias sums: dZ_1..dZ_4, dOut, pad
+constexpr int NF_DBP = 4 * NF_WIDTH + 4;     // per-tile bias sums: dZ_1..dZ_4, dOut, pad
 
-// Training forward (whole waves of 64 points, two tiles; points past n repeat
-// point n - 1): the outputs, the input of every layer in tile order (acts:
-// five layers of [tile][128][32] bf16) and the ReLU pattern of the four hidden
+// The training forward gives each wave one 32-point tile (a column block of
+// the MFMA layout) and runs 512-thread blocks: one block per CU (the network
+// image fills the LDS) but two waves per SIMD, whose latencies then hide
+// behind each other's work.  (The backward, whose MFMA chains are denser,
+// measured faster with two column blocks per wave sharing each weight load,
+// as in the stepper's whole-wave evaluation.)
+constexpr int NF_TRAIN_BLOCK = 512;
+
+// One hidden layer for one column block: out = relu(W in + b) as bf16.
+__device__ __forceinline__ void nf_layer1(const __bf16* wimg, const float* bias,
+                                          const bf16x8 in[8], bf16x8 out[8])
+{
+    wimg = nf_launder(wimg);
+    bias = nf_launder(bias);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int rr = lane & 31;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        floatx16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = bias[32 * r + 16 * (i >> 3) + 8 * g + (i & 7)];
+        const int row = 32 * r + rr;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const bf16x8 a = *(const bf16x8*)(wimg + nf_img_off(row, 16 * m + 8 * g));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, in[m], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            out[2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc[i]);
+    }
+}
+
+// Output layer for one column block: lanes 0..31 receive the three outputs of
+// their point (rows 0..2 of the result, registers 0..2 of group 0).
+__device__ __forceinline__ void nf_output1(const __bf16* w5, const float* b5, const bf16x8 h[8],
+                                           float out[3])
+{
+    w5 = nf_launder(w5);
+    b5 = nf_launder(b5);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int row = lane & 31;
+    const bool live = row < 3;
+    const __bf16* wrow = w5 + (live ? row : 0) * NF_WIDTH + 8 * g;
+    floatx16 acc = {};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        bf16x8 a = *(const bf16x8*)(wrow + 16 * m);
+        if (!live)
+            a = bf16x8{};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, h[m], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        out[c] = acc[c] + b5[c];
+}
+
+// Training forward, one 32-point tile per wave (points past n repeat point
+// n - 1): the outputs, the input of every layer in tile order (acts: five
+// layers of [tile][128][32] bf16) and the ReLU pattern of the four hidden
 // outputs (relu: [4][tile][64 lanes]) for the backward.  The points are the
 // caller's (xh) or, with `sample`, drawn here (indices offset.. of the Philox
 // stream seed) with their targets (tgt) from the grid, read after the network
 // so that the gathers' latency is hidden behind it.
-__global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64_t n, int64_t ld,
-                                                const float* xh, bool sample, GridView grid,
-                                                uint64_t seed, uint64_t offset, float* tgt,
-                                                __bf16* acts, uint2* relu, float* out)
+__global__ void __launch_bounds__(NF_TRAIN_BLOCK) k_nf_fwd(const char* img, NFGeom G, int64_t n,
+                                                           int64_t ld, const float* xh,
+                                                           bool sample, GridView grid,
+                                                           uint64_t seed, uint64_t offset,
+                                                           float* tgt, __bf16* acts, uint2* relu,
+                                                           float* out)
 {
     extern __shared__ __attribute__((aligned(16))) char nf_lds[];
     nf_stage_lds(nf_lds, img);
@@ -253,65 +315,55 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
     nf_ident(Ilo, Ihi);
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-        const int64_t T0 = base >> 5;
-        const int64_t me = base + lane;
-        float sx[3] = {0.f, 0.f, 0.f};
+    for (int64_t T = wave; T * 32 < n; T += nwaves) {
+        const int64_t p = T * 32 + rr;              // this lane's point (both groups)
+        const int64_t q = p < n ? p : n - 1;
+        float x0, x1, x2;
         double sp[3] = {0.0, 0.0, 0.0};
-        if (sample)
-            nf_sample_xhat(G, seed, offset + (uint64_t)(me < n ? me : n - 1), sx, sp);
-        bf16x8 a[2][8], b[2][8];
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            const int64_t p = base + 32 * cb + rr;
-            const int64_t q = p < n ? p : n - 1;
-            float x0, x1, x2;
-            if (sample) {
-                const int src = (int)(q - base);
-                x0 = __shfl(sx[0], src);
-                x1 = __shfl(sx[1], src);
-                x2 = __shfl(sx[2], src);
-            } else {
-                x0 = xh[3 * q];
-                x1 = xh[3 * q + 1];
-                x2 = xh[3 * q + 2];
-            }
-            nf_embed_fp64(v.freq, x0, x1, x2, g, a[cb]);
+        if (sample) {
+            float sx[3];
+            nf_sample_xhat(G, seed, offset + (uint64_t)q, sx, sp);
+            x0 = sx[0];
+            x1 = sx[1];
+            x2 = sx[2];
+        } else {
+            x0 = xh[3 * q];
+            x1 = xh[3 * q + 1];
+            x2 = xh[3 * q + 2];
         }
-        auto keep = [&](int L, const bf16x8 h[2][8]) {
+        bf16x8 a[8], b[8];
+        nf_embed_fp64(v.freq, x0, x1, x2, g, a);
+        auto keep = [&](int L, const bf16x8 h[8]) {
             __bf16* dst = acts + (int64_t)L * NF_WIDTH * ld;
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const floatx16 t = nf_transpose(h[cb][2 * q], h[cb][2 * q + 1], Ilo, Ihi);
-                    nf_store_tile(dst + ((T0 + cb) * NF_WIDTH + 32 * q + rr) * 32 + 16 * g, t);
-                }
-                if (L > 0)
-                    relu[((int64_t)(L - 1) * ntile + T0 + cb) * 64 + lane] = nf_relu_bits(h[cb]);
+            for (int qq = 0; qq < 4; ++qq) {
+                const floatx16 t = nf_transpose(h[2 * qq], h[2 * qq + 1], Ilo, Ihi);
+                nf_store_tile(dst + (T * NF_WIDTH + 32 * qq + rr) * 32 + 16 * g, t);
             }
+            if (L > 0)
+                relu[((int64_t)(L - 1) * ntile + T) * 64 + lane] = nf_relu_bits(h);
         };
         keep(0, a);
-        nf_layer(v.w[0], v.bias, a, b);
+        nf_layer1(v.w[0], v.bias, a, b);
         keep(1, b);
-        nf_layer(v.w[1], v.bias + NF_WIDTH, b, a);
+        nf_layer1(v.w[1], v.bias + NF_WIDTH, b, a);
         keep(2, a);
-        nf_layer(v.w[2], v.bias + 2 * NF_WIDTH, a, b);
+        nf_layer1(v.w[2], v.bias + 2 * NF_WIDTH, a, b);
         keep(3, b);
-        nf_layer(v.w[3], v.bias + 3 * NF_WIDTH, b, a);
+        nf_layer1(v.w[3], v.bias + 3 * NF_WIDTH, b, a);
         keep(4, a);
         float o[3];
-        nf_output(v.w5, v.bias + 4 * NF_WIDTH, a, o);
-        if (me < n) {
+        nf_output1(v.w5, v.bias + 4 * NF_WIDTH, a, o);
+        if (g == 0 && p < n) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                out[3 * me + c] = o[c];
+                out[3 * p + c] = o[c];
             if (sample) {
                 float t[3];
                 nf_sample_target(grid, G, sp, t);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    tgt[3 * me + c] = t[c];
+                    tgt[3 * p + c] = t[c];
             }
         }
     }
@@ -322,8 +374,10 @@ __global__ void __launch_bounds__(256) k_nf_fwd(const char* img, NFGeom G, int64
 // W_k^T bf16(dZ_k) by MFMA with the transposed images.  For the weight
 // gradients it stores bf16(dZ_k) in tile order (dz: four layers of
 // [tile][128][32]) and dOut in tile order (dout: [tile][3][32], FP32); for the
-// bias gradients, each wave's sums over its 64 points (dbp: [wave][NF_DBP],
-// dZ_1..dZ_4 by 128 features, then the three outputs).  The sums take dZ as
+// bias gradients, each tile's sums over its 32 points (dbp: [tile][NF_DBP],
+// dZ_1..dZ_4 by 128 features, then the three outputs).  Two tiles per wave:
+// its 64 lanes hold one point each for dOut, and two column blocks in the
+// layers, so that each weight load from LDS feeds two MFMAs.  The sums take dZ as
 // bf16(dZ) + bf16(dZ - bf16(dZ)), within 2^-17 of the FP32 value, both parts
 // transposed exactly on the matrix cores.  Adds the loss mean_p |out - tgt|^2
 // (FP64; one atomic per wave) to *loss.
@@ -346,7 +400,6 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
         const int64_t T0 = base >> 5;
-        float* db = dbp + (base >> 6) * NF_DBP;
         // dOut of this lane's own point, in tile order, and its wave sums
         float d[3] = {0.f, 0.f, 0.f}, dr[3] = {0.f, 0.f, 0.f};
         double sq = 0.0;
@@ -371,16 +424,16 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
             dout[((T0 + g) * 3 + c) * 32 + nf_tile_pos(rr)] = d[c];
             float s = d[c];
 #pragma unroll
-            for (int o = 32; o >= 1; o >>= 1)
+            for (int o = 16; o >= 1; o >>= 1)
                 s += __shfl_xor(s, o);
-            if (lane == 0)
-                db[4 * NF_WIDTH + c] = s;
+            if (rr == 0)
+                dbp[(T0 + g) * NF_DBP + 4 * NF_WIDTH + c] = s;    // tile T0 + g
         }
         // one hidden layer's gradient tile (k-blocks 2q, 2q + 1 of column
         // block cb, FP32 values s[16] in result order) kept for the weight and
         // bias gradients
         auto keep = [&](int k, int cb, int q, const bf16x8& h0, const bf16x8& h1,
-                        const bf16x8& l0, const bf16x8& l1, float& dbs) {
+                        const bf16x8& l0, const bf16x8& l1) {
             const floatx16 th = nf_transpose(h0, h1, Ilo, Ihi);
             const floatx16 tl = nf_transpose(l0, l1, Ilo, Ihi);
             nf_store_tile(dz + (int64_t)k * NF_WIDTH * ld +
@@ -390,21 +443,14 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 s += th[i] + tl[i];
-            dbs += s;
-        };
-        auto flush = [&](int k, float dbs[4]) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float s = dbs[q] + __shfl_xor(dbs[q], 32);
-                if (g == 0)
-                    db[k * NF_WIDTH + 32 * q + rr] = s;
-            }
+            s += __shfl_xor(s, 32);
+            if (g == 0)
+                dbp[(T0 + cb) * NF_DBP + k * NF_WIDTH + 32 * q + rr] = s;
         };
         bf16x8 dzb[2][8];
         // layer 4: dH4 = W5^T dOut on the vector ALU, then the ReLU mask
         {
             const __bf16* w5 = nf_launder(v.w5);
-            float dbs[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 const int src = 32 * cb + rr;
@@ -427,10 +473,9 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                             dzb[cb][m][j] = h;
                             lo[mm][j] = (__bf16)(s - (float)h);
                         }
-                    keep(3, cb, q, dzb[cb][2 * q], dzb[cb][2 * q + 1], lo[0], lo[1], dbs[q]);
+                    keep(3, cb, q, dzb[cb][2 * q], dzb[cb][2 * q + 1], lo[0], lo[1]);
                 }
             }
-            flush(3, dbs);
         }
         // layers 4 -> 1: dH_{k-1} = W_k^T dZ_k, mask with h_{k-1} > 0
 #pragma unroll 1
@@ -438,7 +483,6 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
             const __bf16* wimg = nf_launder(v.w[0] + k * NF_IMG_LAYER);
             const uint2 mk0 = relu[((int64_t)(k - 1) * ntile + T0) * 64 + lane];
             const uint2 mk1 = relu[((int64_t)(k - 1) * ntile + T0 + 1) * 64 + lane];
-            float dbs[4] = {0.f, 0.f, 0.f, 0.f};
             bf16x8 nxt[2][8];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -462,11 +506,9 @@ __global__ void __launch_bounds__(256) k_nf_bwd(const char* img_t, NFGeom G, int
                         nxt[cb][m][j] = h;
                         lo[i >> 3][j] = (__bf16)(s - (float)h);
                     }
-                    keep(k - 1, cb, r, nxt[cb][2 * r], nxt[cb][2 * r + 1], lo[0], lo[1],
-                         dbs[r]);
+                    keep(k - 1, cb, r, nxt[cb][2 * r], nxt[cb][2 * r + 1], lo[0], lo[1]);
                 }
             }
-            flush(k - 1, dbs);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -502,7 +544,7 @@ __device__ __forceinline__ float nf_sum_strided(const float* p, int64_t stride, 
 // with g_L the gradient at layer L's output (g_4: dOut, 3 rows) and a_L its
 // bf16 input, both in tile order, and writes them to part[c][L]
 // (NF_PART_LAYER floats per layer: dW row-major, then db; db from the
-// backward's per-wave sums).  MFMA 32x32x16 bf16: a tile is two K-steps, K
+// backward's per-tile sums).  MFMA 32x32x16 bf16: a tile is two K-steps, K
 // index 8 g + j of step h being tile position 16 g + 8 h + j in both operands
 // (any common order of the points gives the same sums up to rounding).
 // Eight waves: wave w forms row tile w % 4 of a hidden layer's 128 x 128
@@ -517,7 +559,7 @@ struct NFGradIn {
     const __bf16* dz[4];     // bf16 gradients of layers 1-4, tile order
     const float* dout;       // FP32 output gradient [tile][3][32]
     const __bf16* a[5];      // bf16 layer inputs, tile order
-    const float* dbp;        // per-wave bias sums [wave][NF_DBP]
+    const float* dbp;        // per-tile bias sums [tile][NF_DBP]
 };
 
 __device__ __forceinline__ bf16x8 nf_cvt8(const float4 lo, const float4 hi)
@@ -636,8 +678,7 @@ __device__ inline void nf_wgrad_block(const NFGradIn& in, int L, int64_t t0, int
     const int off = out_layer ? 4 * NF_WIDTH : L * NF_WIDTH;
     for (int f = (int)threadIdx.x; f < nb; f += (int)blockDim.x)
         out[(out_layer ? 3 : NF_WIDTH) * NF_WIDTH + f] =
-            nf_sum_strided(in.dbp + (t0 >> 1) * NF_DBP + off + f, NF_DBP,
-                           (int)((t1 >> 1) - (t0 >> 1)));
+            nf_sum_strided(in.dbp + t0 * NF_DBP + off + f, NF_DBP, (int)(t1 - t0));
 }
 
 __global__ void __launch_bounds__(512) k_nf_wgrad(NFGradIn in, int64_t ntl, int64_t chunk,
@@ -924,7 +965,7 @@ static hipError_t nf_ensure_cap(NeuralField* nf, int64_t n)
     al((void**)&nf->acts, (size_t)5 * NF_WIDTH * ld * 2);
     al((void**)&nf->dz, (size_t)4 * NF_WIDTH * ld * 2);
     al((void**)&nf->relu, (size_t)4 * (ld / 32) * 64 * sizeof(uint2));
-    al((void**)&nf->dbp, (size_t)(ld / 64) * NF_DBP * 4);
+    al((void**)&nf->dbp, (size_t)(ld / 32) * NF_DBP * 4);
     al((void**)&nf->part, (size_t)NF_GRAD_CHUNKS * 5 * NF_PART_LAYER * 4);
     if (e == hipSuccess)
         nf->cap = ld;
@@ -941,17 +982,18 @@ static hipError_t nf_fwd_bwd(NeuralField* nf, const NFGeom& G, const GridView& g
 {
     hipStream_t s = nf->stream;
     const int64_t ld = nf->cap;
-    const int nb = nf_eval_blocks(nf, n);
-    k_nf_fwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, sample, g, seed, offset,
+    // one 32-point tile per wave, eight waves per block, at most one block per CU
+    const int64_t ntl = (n + 31) / 32;
+    int nb = (int)((ntl + NF_TRAIN_BLOCK / 64 - 1) / (NF_TRAIN_BLOCK / 64));
+    if (nb > nf->num_cus)
+        nb = nf->num_cus;
+    k_nf_fwd<<<nb, NF_TRAIN_BLOCK, NF_LDS_BYTES, s>>>(nf->img_fwd, G, n, ld, nf->xh, sample, g, seed, offset,
                                            nf->tgt, nf->acts, nf->relu, nf->out);
-    k_nf_bwd<<<nb, 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->relu,
+    k_nf_bwd<<<nf_eval_blocks(nf, n), 256, NF_LDS_BYTES, s>>>(nf->img_bwd, G, n, ld, nf->out, nf->tgt, nf->relu,
                                            nf->dz, nf->dout, nf->dbp, loss,
                                            (float)(1.0 / (double)n));
-    // the tiles of whole waves, split over at most NF_GRAD_CHUNKS chunks of an
-    // even number (whole waves) of at least 8 tiles
-    const int64_t ntl = 2 * ((n + 63) / 64);
+    // the tiles, split over at most NF_GRAD_CHUNKS chunks of at least 8 tiles
     int64_t chunk = (ntl + NF_GRAD_CHUNKS - 1) / NF_GRAD_CHUNKS;
-    chunk = (chunk + 1) & ~int64_t(1);
     if (chunk < 8)
         chunk = 8;
     *nchunks = (int)((ntl + chunk - 1) / chunk);
