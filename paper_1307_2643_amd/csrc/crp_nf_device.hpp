@@ -247,6 +247,58 @@ __device__ __attribute__((always_inline)) inline void nf_output(const __bf16* w5
     }
 }
 
+// One hidden layer for one column block: out = relu(W in + b) as bf16.
+__device__ __forceinline__ void nf_layer1(const __bf16* wimg, const float* bias,
+                                          const bf16x8 in[8], bf16x8 out[8])
+{
+    wimg = nf_launder(wimg);
+    bias = nf_launder(bias);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int rr = lane & 31;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        floatx16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = bias[32 * r + 16 * (i >> 3) + 8 * g + (i & 7)];
+        const int row = 32 * r + rr;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const bf16x8 a = *(const bf16x8*)(wimg + nf_img_off(row, 16 * m + 8 * g));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, in[m], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            out[2 * r + (i >> 3)][i & 7] = (__bf16)nf_relu(acc[i]);
+    }
+}
+
+// Output layer for one column block: lanes 0..31 receive the three outputs of
+// their point (rows 0..2 of the result, registers 0..2 of group 0).
+__device__ __forceinline__ void nf_output1(const __bf16* w5, const float* b5, const bf16x8 h[8],
+                                           float out[3])
+{
+    w5 = nf_launder(w5);
+    b5 = nf_launder(b5);
+    const int lane = (int)(threadIdx.x & 63u);
+    const int g = lane >> 5;
+    const int row = lane & 31;
+    const bool live = row < 3;
+    const __bf16* wrow = w5 + (live ? row : 0) * NF_WIDTH + 8 * g;
+    floatx16 acc = {};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        bf16x8 a = *(const bf16x8*)(wrow + 16 * m);
+        if (!live)
+            a = bf16x8{};
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, h[m], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        out[c] = acc[c] + b5[c];
+}
+
 // Normalised position of a point in [0, 1)^3 (FP64, then FP32).
 __device__ __attribute__((always_inline)) inline void nf_xhat(const NFView& v, const double x[3], float xh[3])
 {
