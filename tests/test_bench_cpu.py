@@ -38,12 +38,16 @@ def test_traffic_summary_scales_by_the_copy(tmp_path):
     # the copy reads half its bytes as counted (FETCH_SIZE), writes all of them;
     # two propagation launches (the larger is the timed one) and a kernel of
     # another instantiation that must be ignored
+    # later copies (the 4 GiB copy-bandwidth probe, record read-backs) are
+    # other sizes: the calibration is the run's first copy dispatch
     _csv(tmp_path / "fetch" / "fetch_counter_collection.csv",
          [(1, copy, "FETCH_SIZE", gib_kib / 2), (2, prop, "FETCH_SIZE", 1000.0),
-          (3, prop, "FETCH_SIZE", 3000.0), (4, other, "FETCH_SIZE", 9e9)])
+          (3, prop, "FETCH_SIZE", 3000.0), (4, other, "FETCH_SIZE", 9e9),
+          (5, copy, "FETCH_SIZE", 4 * gib_kib / 2), (6, copy, "FETCH_SIZE", 7.0)])
     _csv(tmp_path / "write" / "write_counter_collection.csv",
          [(1, copy, "WRITE_SIZE", gib_kib), (2, prop, "WRITE_SIZE", 10.0),
-          (3, prop, "WRITE_SIZE", 20.0), (4, other, "WRITE_SIZE", 9e9)])
+          (3, prop, "WRITE_SIZE", 20.0), (4, other, "WRITE_SIZE", 9e9),
+          (5, copy, "WRITE_SIZE", 4 * gib_kib), (6, copy, "WRITE_SIZE", 7.0)])
     r = _run("--summarize-pmc", str(tmp_path))
     assert r.returncode == 0, r.stderr
     out = json.loads(r.stdout)
