@@ -409,9 +409,11 @@ crp_status crp_eval_field_noalloc(crp_ctx* ctx, int64_t n, const double* pos_m, 
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);
 crp_status crp_get_launch(crp_ctx* ctx, crp_launch* launch);
 
-/* Autotuner: times candidate launch shapes (block 128 / 256, as many blocks
- * per compute unit as fit or 3, refill 4 / 16, linear or corner layout), each
- * twice, on a copy of the pending queue (restored after each trial, so the
+/* Autotuner: times candidate launch shapes, each twice, in two stages: block
+ * 128 / 256, as many blocks per compute unit as fit or 3, refill 4 / 16, on
+ * the linear and the corner layout; then, around the fastest of those, refill
+ * 1 and 64 and 2 blocks per compute unit.  The trials run on a copy of the
+ * pending queue (restored after each trial, so the
  * pending work is unchanged) run for max_cycles cycles (<= 0: to completion),
  * keeps the fastest in the context and appends it to cache_path (NULL: no
  * file) under a key of (device name, grid shape, dtype, precision, field

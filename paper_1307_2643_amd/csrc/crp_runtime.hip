@@ -1935,19 +1935,12 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     }
     const crp_launch orig = ctx->launch;
     const int64_t fin0 = ctx->fin_unread, neu0 = ctx->neu_unread, traj0 = ctx->traj_unread;
-    std::vector<crp_launch> cands;
-    const bool corner_ok = ctx->grid_dtype == CRP_F32;
-    for (int layout = 0; layout < (corner_ok ? 2 : 1); ++layout)
-        for (const crp_launch& l : {crp_launch{128, 0, 4, 0}, crp_launch{128, 0, 16, 0},
-                                    crp_launch{128, 3, 4, 0}, crp_launch{256, 0, 4, 0},
-                                    crp_launch{256, 0, 16, 0}})
-            cands.push_back(crp_launch{l.block, l.blocks_per_cu, l.refill, layout});
     crp_launch bestl = orig;
     double bestr = -1.0;
     crp_status st = CRP_OK;
     // every shape is timed twice on the same work and keeps its better rate
     // (a single short trial is too noisy to separate shapes a few % apart)
-    for (const crp_launch& l : cands) {
+    auto trial = [&](const crp_launch& l) {
         for (int rep = 0; rep < 2 && st == CRP_OK; ++rep) {
             // restore the queue (the park buffer swap may have moved it)
             ctx->q = QueueSoA();
@@ -1975,8 +1968,24 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
                 bestl = l;
             }
         }
-        if (st != CRP_OK)
-            break;
+    };
+    // stage 1: block size, occupancy and refill on both layouts
+    const bool corner_ok = ctx->grid_dtype == CRP_F32;
+    for (int layout = 0; layout < (corner_ok ? 2 : 1) && st == CRP_OK; ++layout)
+        for (const crp_launch& l : {crp_launch{128, 0, 4, 0}, crp_launch{128, 0, 16, 0},
+                                    crp_launch{128, 3, 4, 0}, crp_launch{256, 0, 4, 0},
+                                    crp_launch{256, 0, 16, 0}})
+            if (st == CRP_OK)
+                trial(crp_launch{l.block, l.blocks_per_cu, l.refill, layout});
+    // stage 2, around the best: the extreme refill thresholds (claim as soon as
+    // one lane idles, or only when the whole wave has) and two blocks per CU
+    if (st == CRP_OK) {
+        const crp_launch c = bestl;
+        for (const crp_launch& l : {crp_launch{c.block, c.blocks_per_cu, 1, c.layout},
+                                    crp_launch{c.block, c.blocks_per_cu, 64, c.layout},
+                                    crp_launch{c.block, 2, c.refill, c.layout}})
+            if (st == CRP_OK && !(l.blocks_per_cu == c.blocks_per_cu && l.refill == c.refill))
+                trial(l);
     }
     // restore the pending work exactly as it was
     queue_layout((char*)ctx->qmem[0], ctx->park.cap, &ctx->q);
