@@ -574,6 +574,21 @@ struct NestedField {
     const PatchView* P = nullptr;
     int np = 0;
     float* stage = nullptr;   // COOP: the wave's LDS staging area
+    // the first patch's parameters, kept in (scalar) registers for the common
+    // single-patch case, so that its test reads no LDS
+    const float* c0 = nullptr;
+    int n0[3] = {0, 0, 0}, off0[3] = {0, 0, 0};
+    double ref0 = 1.0;
+    __device__ inline void set_first(const PatchView& q)
+    {
+        c0 = q.corner;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            n0[a] = q.n[a];
+            off0[a] = q.off[a];
+        }
+        ref0 = q.refine;
+    }
     // COOP: the corner record of the cell that holds p on its level, and the
     // offsets t within that cell
     __device__ inline const float* record(const double p[3], double t[3]) const
@@ -583,6 +598,26 @@ struct NestedField {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
             t[a] = c.t[a];
+        if (np == 1) {
+            double r[3];
+            bool in = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                r[a] = ((double)(c.i0[a] - off0[a]) + c.t[a]) * ref0;
+                in = in && r[a] >= 0.0 && r[a] < (double)(n0[a] - 1);
+            }
+            if (in) {
+                int i[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double fl = floor(r[a]);
+                    i[a] = (int)fl;
+                    t[a] = r[a] - fl;
+                }
+                rec = c0 + (((int64_t)i[0] * n0[1] + i[1]) * n0[2] + i[2]) * 32;
+            }
+            return rec;
+        }
         for (int k = np - 1; k >= 0; --k) {
             const PatchView& q = P[k];
             double r[3];

@@ -307,6 +307,7 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
         F.g = PP->grid;
         F.P = nest_lds;
         F.np = PP->nest.np;
+        F.set_first(PP->nest.p[0]);
         if constexpr (LAYOUT == 6)
             F.stage = (float*)(stage_mem + (t >> 6) * COOP_STAGE_FLOAT4);
     } else {
