@@ -43,5 +43,48 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# The host runtime under AddressSanitizer and UndefinedBehaviorSanitizer: the
+# library's sources with their host code instrumented (device code as in the
+# library: the sanitizers are host-only here), linked with the C-ABI driver
+# tests/sanitize/runtime_driver.cpp into one executable for the GPU test.
+SAN_DIR = os.path.join(HERE, "_sanitize")
+SAN_EXE = os.path.join(SAN_DIR, "crp_runtime_sanitized")
+SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer"]
+SAN_LINK = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    os.makedirs(SAN_DIR, exist_ok=True)
+    inc = os.path.join(HERE, "..", "include")
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    objs = []
+    for s in SOURCES:
+        obj = os.path.join(SAN_DIR, s.replace(".hip", ".o"))
+        cmd = [hipcc()] + flags + SAN_HOST + ["-g", "-I", inc, "-c", "-o", obj,
+                                              os.path.join(CSRC, s)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        objs.append(obj)
+    # host link (no HIP source on this line): ROCm's clang, whose sanitizer
+    # runtime matches the instrumented objects
+    clang = os.path.join(os.path.dirname(hipcc()), "..", "llvm", "bin", "clang++")
+    driver = os.path.join(HERE, "..", "tests", "sanitize", "runtime_driver.cpp")
+    rocm_lib = os.path.join(os.path.dirname(hipcc()), "..", "lib")
+    tmp = SAN_EXE + ".tmp"
+    link = [clang, "-std=c++17", "-O1", "-g"] + SAN_LINK + [
+        "-I", inc, "-o", tmp, driver] + objs + [
+        "-L" + rocm_lib, "-lamdhip64", "-Wl,-rpath," + rocm_lib]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    os.replace(tmp, SAN_EXE)
+    return SAN_EXE
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--sanitized" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
