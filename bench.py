@@ -29,6 +29,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 GATHERS_PER_ATTEMPT = 6
 RECORD_BYTES = 8 * 3 * 4          # algorithmic bytes of one gather: 8 corners x 3 x FP32
+RECORD_BYTES_FP64 = 8 * 3 * 8     # the same for an FP64 grid
+TUNE_CYCLES_FP64 = 256            # cycles per autotuner trial on the FP64-grid workloads
 
 
 def gathers(cnt):
@@ -447,6 +449,17 @@ def copy_bandwidth(torch, dev, nbytes=1 << 32):
     return best
 
 
+def tuned_fp64_launch(args, ctx):
+    """The launch of an FP64-grid workload: the autotuner's pick on the
+    context's pending work, each trial cut to TUNE_CYCLES_FP64 cycles (about a
+    tenth of the 256^3 workload's run; the cache answers for a grid of the same
+    shape, element type and method), or the context's default with --no-tune.
+    The pending work is unchanged."""
+    if not args.no_tune:
+        ctx.tune(max_cycles=TUNE_CYCLES_FP64, cache_path=args.tune_cache)
+    return ctx.get_launch()
+
+
 def small_config_variant(args, crp, I, torch, stream, w, subset):
     """The FP64 method on a workload whose grid is FP64 and small: all of its
     candidates on the GPU (timed with the library's HIP events and by wall
@@ -466,31 +479,40 @@ def small_config_variant(args, crp, I, torch, stream, w, subset):
     ctx.set_field_grid(torch.as_tensor(grid, device=dev), w.spacing_m)
     ctx.set_tables(tables)
 
-    def run(keep):
+    def inject():
         ctx.reset_counters()
         ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
                    on_device=True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.propagate(0)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms, _ = ctx.last_timing()
-        c = ctx.counts()
-        fin = crp.sort_finished(ctx.read_finished()) if keep else None
-        ctx.discard_finished()
-        return wall, ms, c, fin
 
-    run(False)                                   # untimed first run
-    wall, ms, c, fin = run(True)
+    # untimed first run, in the launch the autotuner picks for this workload
+    inject()
+    launch = tuned_fp64_launch(args, ctx)
+    ctx.propagate(0)
+    ctx.discard_finished()
+    inject()
+    t0 = time.perf_counter()
+    ctx.propagate(0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, _ = ctx.last_timing()
+    c = ctx.counts()
+    fin = crp.sort_finished(ctx.read_finished())
+    ctx.discard_finished()
     ctx.close()
     out = {"workload": f"{w.name} ({n} candidates, FP64 method, {w.grid_n}^3 FP64 grid)",
+           "launch": launch,
            "steps_per_s": c["steps"] / wall, "steps_per_s_kernel": c["steps"] / (ms * 1e-3),
            "wall_s": wall, "kernel_ms": ms, "steps": c["steps"], "attempts": c["attempts"],
            "finished": c["finished"], "charged_sec": c["charged_sec"],
            "neutral_sec": c["neutral_sec"]}
+    # the gathers' algorithmic bytes (8 corners x 3 x FP64 = 192 B each, whether a
+    # record comes from HBM or from a cache) over the kernel time
+    gbs = gathers(c) * RECORD_BYTES_FP64 / (ms * 1e-3) / 1e9
+    out["gather_algorithmic_GBps"] = gbs
+    out["gather_frac_of_hbm_peak"] = gbs / HBM_PEAK_GBS
     log(f"[bench] {w.name}: {out['steps_per_s']:.3e} steps/s ({wall * 1e3:.1f} ms wall, "
-        f"kernel {ms:.1f} ms)")
+        f"kernel {ms:.1f} ms, {gbs:.0f} GB/s algorithmic gather bandwidth, launch {launch})")
     if not args.no_cpu:
         from oracle import oracle as O
         m = n if subset is None else subset
@@ -782,11 +804,13 @@ def paper_comparable(args, crp, I, torch, stream):
     ctx.set_field_grid(grid, w.spacing_m)
     ctx.set_tables(tables)
 
-    def run():
+    def run(tune):
         ctx.reset_counters()
         ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
                    on_device=True)
         torch.cuda.synchronize()
+        if tune:
+            tuned_fp64_launch(args, ctx)
         t0 = time.perf_counter()
         ctx.propagate(0)
         torch.cuda.synchronize()
@@ -795,10 +819,12 @@ def paper_comparable(args, crp, I, torch, stream):
         ctx.discard_finished()
         return wall, c
 
-    run()                                        # untimed first run
-    wall, c = run()
+    run(True)                                    # untimed first run (tuned launch)
+    wall, c = run(False)
+    launch = ctx.get_launch()
     ctx.close()
-    out = {"workload": f"{w.name} ({n} protons, FP64 method)", "gpu_trajectories_per_s": n / wall,
+    out = {"workload": f"{w.name} ({n} protons, FP64 method)", "launch": launch,
+           "gpu_trajectories_per_s": n / wall,
            "gpu_us_per_trajectory": 1e6 * wall / n, "gpu_steps_per_s": c["steps"] / wall,
            "steps_per_trajectory": c["steps"] / n,
            "paper_ms_per_trajectory": 1.0,

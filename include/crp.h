@@ -404,8 +404,12 @@ crp_status crp_eval_field_noalloc(crp_ctx* ctx, int64_t n, const double* pos_m, 
 
 /* Launch shape of the propagation kernel (validated; CRP_EINVAL otherwise).
  * A new context starts with {128, 0, 4, CRP_LAYOUT_LINEAR}.
- * CRP_LAYOUT_CORNER needs an FP32 grid and 128 bytes per cell of extra
- * device memory (built on first use). */
+ * CRP_LAYOUT_CORNER keeps, beside the linear grid, one record per cell with
+ * the cell's 8 corner vectors in the grid's element type (built on first use,
+ * at most 2^32 - 1 cells): 128 bytes per cell for an FP32 grid (24 floats and
+ * a pad), 192 bytes for an FP64 grid (24 doubles).  The field values read are
+ * the same in either layout, so results do not depend on it.  An FP64 grid
+ * with refinement patches is read from the linear arrays in either layout. */
 crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* launch);
 crp_status crp_get_launch(crp_ctx* ctx, crp_launch* launch);
 

@@ -205,7 +205,8 @@ __device__ inline Rates species_rates(const TableView& T, int A, int Z, double E
 // -------------------------------------------------------------------------
 struct GridView {
     const void* data;       // linear [nx][ny][nz][3] (float or double)
-    const float* corner;    // corner records [nx][ny][nz][32] (float) or null
+    const float* corner;    // FP32 grid: corner records [nx][ny][nz][32] (float) or null
+    const double* corner64; // FP64 grid: corner records [nx][ny][nz][24] (double) or null
     int n[3];
     int mask[3];            // n-1 if n is a power of two, else -1
     int64_t stride[3];      // elements: ny*nz*3, nz*3, 3
@@ -438,6 +439,76 @@ __device__ inline void gather_corner_coop(const float* corner, uint32_t cell, fl
     coop_consume(stage, v);
 }
 
+// FP64 corner records: the 8 corner vectors as 24 doubles, 192 bytes with no
+// pad, so that every record spans exactly two 128-byte lines.  The wave's 64
+// records x 12 sixteen-byte chunks take twelve loads, chunk c of record r
+// landing in float4 slot 12 r + c of the staging area (12 KiB per wave).
+constexpr int COOP_STAGE64_FLOAT4 = 768;
+
+template <class GT>
+constexpr int coop_stage_float4 = sizeof(GT) == 8 ? COOP_STAGE64_FLOAT4 : COOP_STAGE_FLOAT4;
+
+__device__ inline void coop_issue(const double* corner, uint32_t cell, float* stage, bool need)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    float4* st = (float4*)stage;
+    const uint64_t needm = __ballot(need);
+#pragma unroll
+    for (int j = 0; j < 12; ++j) {
+        const int idx = 64 * j + lane;            // 0..767
+        const int r = idx / 12, c = idx - 12 * r;  // record (= owning lane), chunk
+        const uint32_t rc = (uint32_t)__shfl((int)cell, r);
+        const float4* src = (const float4*)(corner + (uint64_t)rc * 24u) + c;
+        if ((needm >> r) & 1ull)
+            __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)(st + 64 * j), 16,
+                                             0, 0);
+    }
+}
+
+__device__ inline void coop_consume(const float* stage, double v[8][3])
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double f[24];
+    const double2* my = (const double2*)stage + 12 * lane;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const double2 x = my[q];
+        f[2 * q + 0] = x.x;
+        f[2 * q + 1] = x.y;
+    }
+    // the staging area is rewritten by the wave's next gather
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k][0] = f[3 * k + 0];
+        v[k][1] = f[3 * k + 1];
+        v[k][2] = f[3 * k + 2];
+    }
+}
+
+__device__ inline void gather_corner_coop(const double* corner, uint32_t cell, float* stage,
+                                          double v[8][3], bool need)
+{
+    coop_issue(corner, cell, stage, need);
+    coop_consume(stage, v);
+}
+
+// The corner records of a grid's element type.
+template <class GT>
+__device__ inline const GT* corner_records(const GridView& g)
+{
+    if constexpr (sizeof(GT) == 8)
+        return g.corner64;
+    else
+        return g.corner;
+}
+
 __device__ inline int64_t cell_index(const GridView& g, const Cell& c)
 {
     return ((int64_t)c.i0[0] * g.n[1] + c.i0[1]) * g.n[2] + c.i0[2];
@@ -481,7 +552,8 @@ __device__ inline void interp_fp32(const double t[3], const GT v[8][3], float B[
 }
 
 // Field sources used by the stepper.  LAYOUT: 0 linear, 1 corner records
-// (per lane), 2 corner records gathered cooperatively by the whole wave.
+// (per lane, FP32 grids), 2 corner records gathered cooperatively by the whole
+// wave (FP32 or FP64 records of the grid's element type).
 template <class GT, int LAYOUT>
 struct GridField {
     GridView g;
@@ -491,7 +563,7 @@ struct GridField {
     __device__ inline void corners(const Cell& c, GT v[8][3], bool need) const
     {
         if constexpr (LAYOUT == 2) {
-            gather_corner_coop(g.corner, (uint32_t)cell_index(g, c), stage, v, need);
+            gather_corner_coop(corner_records<GT>(g), (uint32_t)cell_index(g, c), stage, v, need);
         } else if (need) {
             if constexpr (LAYOUT == 1)
                 gather_corner(g, c, v);
@@ -531,19 +603,19 @@ struct GridField {
     {
         static_assert(LAYOUT == 2, "split evaluation needs the cooperative layout");
         const Cell c = locate(g, p);
-        coop_issue(g.corner, (uint32_t)cell_index(g, c), stage, need);
+        coop_issue(corner_records<GT>(g), (uint32_t)cell_index(g, c), stage, need);
     }
     __device__ inline void fp32_prefetched(const double p[3], float B[3]) const
     {
         const Cell c = locate(g, p);
-        float v[8][3];
+        GT v[8][3];
         coop_consume(stage, v);
         interp_fp32(c.t, v, B);
     }
     __device__ inline void fp64_prefetched(const double p[3], double B[3]) const
     {
         const Cell c = locate(g, p);
-        float v[8][3];
+        GT v[8][3];
         coop_consume(stage, v);
         interp_fp64(c.t, v, B);
     }

@@ -263,8 +263,8 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
     extern __shared__ __attribute__((aligned(16))) double lds[];
     __shared__ LaneShared<BS> S;              // per-lane cold state
     __shared__ unsigned long long bc[WC_COUNT];   // block bookkeeping counters
-    // LDS staging of the wave-cooperative corner gather (LAYOUT 2 only)
-    __shared__ float4 stage_mem[wave_gather<LAYOUT> ? BS / 64 * COOP_STAGE_FLOAT4 : 1];
+    // LDS staging of the wave-cooperative corner gather (LAYOUT 2 and 6 only)
+    __shared__ float4 stage_mem[wave_gather<LAYOUT> ? BS / 64 * coop_stage_float4<GT> : 1];
     // patch table of the multi-resolution grid (LAYOUT 5 only)
     __shared__ PatchView nest_lds[LAYOUT == 5 || LAYOUT == 6 ? MAX_PATCHES : 1];
     const int t = (int)threadIdx.x;
@@ -312,7 +312,7 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
             F.stage = (float*)(stage_mem + (t >> 6) * COOP_STAGE_FLOAT4);
     } else {
         F.g = PP->grid;
-        F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * COOP_STAGE_FLOAT4 : 0));
+        F.stage = (float*)(stage_mem + (LAYOUT == 2 ? (t >> 6) * coop_stage_float4<GT> : 0));
     }
     const StepParams sp = PP->sp;
     const int lane = lane_id();
@@ -890,13 +890,15 @@ __global__ void __launch_bounds__(BS, (min_waves<MODE, LAYOUT>))
 }
 
 // Explicit instantiations: FP64 / mixed stage arithmetic x grid element type x
-// grid layout (corner records exist for FP32 grids only).
+// grid layout (per-lane corner records and multi-resolution corner records
+// exist for FP32 grids only).
 #define CRP_INST(MODE, GT, LAYOUT)                                                          \
     template __global__ void k_propagate<MODE, GT, LAYOUT, 128, false>(const PropParams*); \
     template __global__ void k_propagate<MODE, GT, LAYOUT, 256, false>(const PropParams*); \
     template __global__ void k_propagate<MODE, GT, LAYOUT, 128, true>(const PropParams*);  \
     template __global__ void k_propagate<MODE, GT, LAYOUT, 256, true>(const PropParams*);
 CRP_INST(MODE_FP64, double, 0)
+CRP_INST(MODE_FP64, double, 2)
 CRP_INST(MODE_FP64, double, 4)
 CRP_INST(MODE_FP64, double, 5)
 CRP_INST(MODE_FP64, float, 5)
@@ -908,6 +910,7 @@ CRP_INST(MODE_MIX, double, 4)
 CRP_INST(MODE_FP64, float, 0)
 CRP_INST(MODE_FP64, float, 2)
 CRP_INST(MODE_MIX, double, 0)
+CRP_INST(MODE_MIX, double, 2)
 CRP_INST(MODE_MIX, float, 0)
 CRP_INST(MODE_MIX, float, 2)
 #undef CRP_INST
@@ -1040,8 +1043,6 @@ template __global__ void k_eval_field<float, 0>(GridView, int64_t, const double*
 template __global__ void k_eval_field<float, 1>(GridView, int64_t, const double*, double*, int);
 
 // -------------------------------------------------------------------------
-// Corner-replicated layout: record of cell (i,j,k) = the 8 corner vectors
-// (c = dx + 2 dy + 4 dz) of an FP32 linear grid, padded to 128 bytes.
 // The analytic field at n positions (FP64).
 __global__ void k_eval_analytic(AnalyticParams a, int64_t n, const double* __restrict__ pos,
                                 double* __restrict__ B)
@@ -1095,35 +1096,49 @@ __global__ void __launch_bounds__(128) k_gather_ceiling(const float* corner, uin
 }
 
 // -------------------------------------------------------------------------
-__global__ void k_corner_relayout(GridView g, float* out)
+// Corner-replicated layout: record of cell (i,j,k) = the 8 corner vectors
+// (c = dx + 2 dy + 4 dz) of the linear grid, as 24 values of the grid's
+// element type: FP32 padded to 128 bytes (32 floats), FP64 unpadded (192 bytes).
+template <class GT>
+__global__ void k_corner_relayout(GridView g, GT* out)
 {
+    constexpr int RL = sizeof(GT) == 8 ? 24 : 32;   // elements per record
     const int64_t ncell = (int64_t)g.n[0] * g.n[1] * g.n[2];
-    const float* G = (const float*)g.data;
+    const GT* G = (const GT*)g.data;
     for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < ncell;
          cell += (int64_t)gridDim.x * blockDim.x) {
         const int k = (int)(cell % g.n[2]);
         const int j = (int)((cell / g.n[2]) % g.n[1]);
         const int i = (int)(cell / ((int64_t)g.n[1] * g.n[2]));
-        float rec[32];
+        GT rec[RL];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int ii = (i + (c & 1)) % g.n[0];
             const int jj = (j + ((c >> 1) & 1)) % g.n[1];
             const int kk = (k + ((c >> 2) & 1)) % g.n[2];
-            const float* p = G + (int64_t)ii * g.stride[0] + (int64_t)jj * g.stride[1] +
-                             (int64_t)kk * 3;
+            const GT* p = G + (int64_t)ii * g.stride[0] + (int64_t)jj * g.stride[1] +
+                          (int64_t)kk * 3;
             rec[3 * c] = p[0];
             rec[3 * c + 1] = p[1];
             rec[3 * c + 2] = p[2];
         }
 #pragma unroll
-        for (int q = 24; q < 32; ++q)
-            rec[q] = 0.0f;
-        float4* o = (float4*)(out + cell * 32);
+        for (int q = 24; q < RL; ++q)
+            rec[q] = (GT)0;
+        if constexpr (sizeof(GT) == 8) {
+            double2* o = (double2*)(out + cell * RL);
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            o[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+            for (int q = 0; q < RL / 2; ++q)
+                o[q] = make_double2(rec[2 * q], rec[2 * q + 1]);
+        } else {
+            float4* o = (float4*)(out + cell * RL);
+#pragma unroll
+            for (int q = 0; q < RL / 4; ++q)
+                o[q] = make_float4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
+        }
     }
 }
+template __global__ void k_corner_relayout<float>(GridView, float*);
+template __global__ void k_corner_relayout<double>(GridView, double*);
 
 }  // namespace crp

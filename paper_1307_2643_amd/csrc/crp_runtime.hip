@@ -35,7 +35,8 @@ __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id
                          const int32_t* A, const int32_t* Z, const double* E,
                          const double* pos, const double* dir, const double* lmax,
                          uint64_t seed, double hmin, int mix);
-__global__ void k_corner_relayout(GridView g, float* out);
+template <class GT>
+__global__ void k_corner_relayout(GridView g, GT* out);
 __global__ void k_gather_ceiling(const float* corner, uint32_t ncell, int iters, float* sink);
 __global__ void k_eval_analytic(AnalyticParams a, int64_t n, const double* pos, double* B);
 __global__ void k_observe(ObsParams p);
@@ -62,7 +63,8 @@ struct crp_ctx {
     int64_t gn[3] = {0, 0, 0};
     double spacing = 0.0;
     double origin[3] = {0, 0, 0};
-    float* corner = nullptr;
+    float* corner = nullptr;       // corner records of an FP32 grid (128 B per cell)
+    double* corner64 = nullptr;    // corner records of an FP64 grid (192 B per cell)
     // refinement patches of the grid (multi-resolution)
     NestView nest{};
     void* patch_owned[MAX_PATCHES] = {nullptr, nullptr, nullptr, nullptr};
@@ -238,6 +240,7 @@ GridView make_view(const crp_ctx* ctx)
     GridView g;
     g.data = ctx->grid;
     g.corner = ctx->corner;
+    g.corner64 = ctx->corner64;
     for (int a = 0; a < 3; ++a) {
         g.n[a] = (int)ctx->gn[a];
         g.mask[a] = is_pow2(ctx->gn[a]) ? (int)(ctx->gn[a] - 1) : -1;
@@ -353,18 +356,32 @@ hipError_t copy_d2h(T* host, const T* dev, int64_t k, hipStream_t s)
 // Corner records of the base grid and of every refinement patch (built on
 // first use).  A patch's record of cell (i,j,k) holds its vertices i..i+1 etc.;
 // the records of its last vertex planes are built too (from wrapped indices)
-// but never read, since level selection keeps r < n - 1.
+// but never read, since level selection keeps r < n - 1.  An FP64 grid has
+// records of its base grid only (192 bytes per cell); its patches are always
+// read from their linear arrays.
 crp_status ensure_corner(crp_ctx* ctx)
 {
-    if (ctx->grid_dtype != CRP_F32)
-        return fail(ctx, CRP_EINVAL, "corner layout needs an FP32 grid");
+    if (ctx->grid_dtype == CRP_F64) {
+        if (!ctx->corner64) {
+            const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
+            if (ncell >= (1ll << 32))
+                return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
+            HIPCHK(ctx, hipMalloc((void**)&ctx->corner64, (size_t)ncell * 192));
+            GridView g = make_view(ctx);
+            k_corner_relayout<double><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g,
+                                                                                ctx->corner64);
+            HIPCHK(ctx, hipGetLastError());
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        return CRP_OK;
+    }
     if (!ctx->corner) {
         const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
         if (ncell >= (1ll << 32))
             return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
         HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
         GridView g = make_view(ctx);
-        k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
+        k_corner_relayout<float><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
         HIPCHK(ctx, hipGetLastError());
     }
     for (int k = 0; k < ctx->nest.np; ++k) {
@@ -384,7 +401,8 @@ crp_status ensure_corner(crp_ctx* ctx)
         g.stride[2] = 3;
         g.inv_spacing = 1.0;
         g.dtype = 0;
-        k_corner_relayout<<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->patch_corner[k]);
+        k_corner_relayout<float><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g,
+                                                                           ctx->patch_corner[k]);
         HIPCHK(ctx, hipGetLastError());
         q.corner = ctx->patch_corner[k];
     }
@@ -410,6 +428,10 @@ void free_corner(crp_ctx* ctx)
     if (ctx->corner) {
         (void)hipFree(ctx->corner);
         ctx->corner = nullptr;
+    }
+    if (ctx->corner64) {
+        (void)hipFree(ctx->corner64);
+        ctx->corner64 = nullptr;
     }
 }
 
@@ -477,11 +499,14 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
     // refinement patches: levels selected per lane
     const bool nested = !neural && !analytic && ctx->nest.np > 0;
     const int layout = ctx->launch.layout;
-    if (layout == CRP_LAYOUT_CORNER && !neural && !analytic) {
+    // (the multi-resolution kernel of an FP64 grid reads linear arrays only)
+    if (layout == CRP_LAYOUT_CORNER && !neural && !analytic &&
+        (ctx->grid_dtype == CRP_F32 || !nested)) {
         crp_status st = ensure_corner(ctx);
         if (st != CRP_OK)
             return st;
         P.grid.corner = ctx->corner;
+        P.grid.corner64 = ctx->corner64;
         P.nest = ctx->nest;        // now with the patches' corner records
     }
     const int bs = ctx->launch.block;
@@ -502,12 +527,16 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         else if (analytic)
             bpc = mix ? resident_blocks<MODE_MIX, double, 4>(bs, lds)
                       : resident_blocks<MODE_FP64, double, 4>(bs, lds);
+        else if (!mix && !f32 && layout == CRP_LAYOUT_CORNER)
+            bpc = resident_blocks<MODE_FP64, double, 2>(bs, lds);
         else if (!mix && !f32)
             bpc = resident_blocks<MODE_FP64, double, 0>(bs, lds);
         else if (!mix && layout == CRP_LAYOUT_CORNER)
             bpc = resident_blocks<MODE_FP64, float, 2>(bs, lds);
         else if (!mix)
             bpc = resident_blocks<MODE_FP64, float, 0>(bs, lds);
+        else if (!f32 && layout == CRP_LAYOUT_CORNER)
+            bpc = resident_blocks<MODE_MIX, double, 2>(bs, lds);
         else if (!f32)
             bpc = resident_blocks<MODE_MIX, double, 0>(bs, lds);
         else if (layout == CRP_LAYOUT_CORNER)
@@ -557,12 +586,16 @@ crp_status run_kernel(crp_ctx* ctx, int64_t max_cycles, DevCounters* dc)
         launch_propagate<MODE_MIX, double, 4>(nb, bs, lds, s, dp, traj);
     else if (analytic)
         launch_propagate<MODE_FP64, double, 4>(nb, bs, lds, s, dp, traj);
+    else if (!mix && !f32 && layout == CRP_LAYOUT_CORNER)
+        launch_propagate<MODE_FP64, double, 2>(nb, bs, lds, s, dp, traj);
     else if (!mix && !f32)
         launch_propagate<MODE_FP64, double, 0>(nb, bs, lds, s, dp, traj);
     else if (!mix && layout == CRP_LAYOUT_CORNER)
         launch_propagate<MODE_FP64, float, 2>(nb, bs, lds, s, dp, traj);
     else if (!mix)
         launch_propagate<MODE_FP64, float, 0>(nb, bs, lds, s, dp, traj);
+    else if (!f32 && layout == CRP_LAYOUT_CORNER)
+        launch_propagate<MODE_MIX, double, 2>(nb, bs, lds, s, dp, traj);
     else if (!f32)
         launch_propagate<MODE_MIX, double, 0>(nb, bs, lds, s, dp, traj);
     else if (layout == CRP_LAYOUT_CORNER)
@@ -981,7 +1014,7 @@ void crp_destroy(crp_ctx* ctx)
                     (void*)ctx->cnt,
                     (void*)ctx->d_params,
                     (void*)ctx->scratch, ctx->xfer, ctx->grid_owned, (void*)ctx->tab,
-                    (void*)ctx->corner})
+                    (void*)ctx->corner, (void*)ctx->corner64})
         if (p)
             (void)hipFree(p);
     if (ctx->ev0)
@@ -1039,8 +1072,6 @@ crp_status crp_set_field_grid(crp_ctx* ctx, const void* data, int32_t dtype, int
     for (int a = 0; a < 3; ++a)
         ctx->origin[a] = org[a];
     ctx->has_grid = true;
-    if (ctx->launch.layout == CRP_LAYOUT_CORNER && dtype != CRP_F32)
-        ctx->launch.layout = CRP_LAYOUT_LINEAR;
     return CRP_OK;
 }
 
@@ -1827,8 +1858,6 @@ crp_status crp_set_launch(crp_ctx* ctx, const crp_launch* l)
         l->blocks_per_cu > 64 || l->refill < 1 || l->refill > 64 ||
         !(l->layout == CRP_LAYOUT_LINEAR || l->layout == CRP_LAYOUT_CORNER))
         return fail(ctx, CRP_EINVAL, "set_launch: invalid launch shape");
-    if (l->layout == CRP_LAYOUT_CORNER && ctx->has_grid && ctx->grid_dtype != CRP_F32)
-        return fail(ctx, CRP_EINVAL, "set_launch: corner layout needs an FP32 grid");
     ctx->launch = *l;
     return CRP_OK;
 }
@@ -1861,6 +1890,8 @@ crp_status crp_gather_ceiling(crp_ctx* ctx, int32_t iters, double* records_per_s
         return fail(ctx, CRP_ESTATE, "gather_ceiling: set the grid first");
     if (ctx->gn[0] * ctx->gn[1] * ctx->gn[2] > (int64_t)UINT32_MAX)
         return fail(ctx, CRP_EINVAL, "gather_ceiling: at most 2^32 - 1 cells");
+    if (ctx->grid_dtype != CRP_F32)
+        return fail(ctx, CRP_EINVAL, "gather_ceiling: FP32 grids only (128-byte records)");
     HIPCHK(ctx, hipSetDevice(ctx->cfg.device));
     crp_status st = ensure_corner(ctx);
     if (st != CRP_OK)
@@ -1905,8 +1936,7 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
     if (cache_path) {
         crp_launch cached;
         double rate = 0.0;
-        if (tune_cache_lookup(cache_path, key, &cached, &rate) &&
-            (cached.layout == CRP_LAYOUT_LINEAR || ctx->grid_dtype == CRP_F32)) {
+        if (tune_cache_lookup(cache_path, key, &cached, &rate)) {
             ctx->launch = cached;
             if (best)
                 *best = cached;
@@ -1970,7 +2000,8 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
         }
     };
     // stage 1: block size, occupancy and refill on both layouts
-    const bool corner_ok = ctx->grid_dtype == CRP_F32;
+    // (the multi-resolution kernel of an FP64 grid has no corner-record form)
+    const bool corner_ok = ctx->grid_dtype == CRP_F32 || ctx->nest.np == 0;
     for (int layout = 0; layout < (corner_ok ? 2 : 1) && st == CRP_OK; ++layout)
         for (const crp_launch& l : {crp_launch{128, 0, 4, 0}, crp_launch{128, 0, 16, 0},
                                     crp_launch{128, 3, 4, 0}, crp_launch{256, 0, 4, 0},

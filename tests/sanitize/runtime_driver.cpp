@@ -456,6 +456,44 @@ void section_tune_eval_observe(const Grid& g, const Tables& t)
                 l1.refill, l1.layout);
 }
 
+// FP64 grid: the corner-record layout (192-byte records, built on first use,
+// freed and rebuilt when the grid is set again) gives the records of the
+// linear layout; the tuner tries both layouts on it.
+void section_fp64_corner(const Grid& g, const Tables& t)
+{
+    crp_config c = base_config(CRP_FP64);
+    const Inj j = make_injection(300, 21, g.n * g.spacing, 10 * MPC);
+    crp_ctx* a = make_ctx(c, g, t, false);
+    OK(inject(a, j));
+    run_to_end(a, 0, nullptr);
+    Records ra;
+    read_all(a, ra, 128);
+    crp_destroy(a);
+    crp_ctx* b = make_ctx(c, g, t, false);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1)     // a new grid drops the records; the next run rebuilds them
+            OK(crp_set_field_grid(b, g.d.data(), CRP_F64, 0, g.n, g.n, g.n, g.spacing, nullptr));
+        crp_launch l{256, 0, 4, CRP_LAYOUT_CORNER};
+        OK(crp_set_launch(b, &l));
+        OK(inject(b, j));
+        run_to_end(b, 0, nullptr);
+        Records rb;
+        read_all(b, rb, 128);
+        same_records(ra, rb, "FP64 corner records");
+    }
+    OK(inject(b, j));
+    crp_launch best;
+    double rate = 0;
+    OK(crp_tune(b, 16, nullptr, &best, &rate));
+    CHECK(rate > 0, "tune on the FP64 grid");
+    run_to_end(b, 0, nullptr);
+    double rs = 0;
+    CHECK(crp_gather_ceiling(b, 10, &rs) == CRP_EINVAL, "gather diagnostic on an FP64 grid");
+    crp_destroy(b);
+    std::printf("fp64 corner ok: %zu records, tuned %d/%d/%d/%d\n", ra.size(), best.block,
+                best.blocks_per_cu, best.refill, best.layout);
+}
+
 void section_patches(const Grid& g, const Tables& t)
 {
     crp_config c = base_config(CRP_MIX);
@@ -608,6 +646,7 @@ int main()
     section_propagate_restore(g, t, CRP_FP64);
     section_propagate_restore(g, t, CRP_MIX);
     section_tune_eval_observe(g, t);
+    section_fp64_corner(g, t);
     section_patches(g, t);
     section_neural(g, t);
     section_galactic(t);

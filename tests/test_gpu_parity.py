@@ -131,14 +131,19 @@ def test_eval_field_far_positions_exact_wrap(P, O, shape):
 # ---------------------------------------------------------------------------
 # Whole path: small workload (1000 protons, 32^3 FP64 grid, loss table).
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("layout", [0, 1], ids=["linear", "corner"])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_small_workload_parity(P, O, small_grid, precision):
+def test_small_workload_parity(P, O, small_grid, precision, layout):
+    """FP64 method on the FP64 grid, precision form on the FP32 grid; each
+    from the linear grid and from the corner records (192-byte FP64 records,
+    128-byte FP32 records), which hold the same values."""
     w = I.W_SMALL
     grid = small_grid if precision == 0 else small_grid.astype(np.float32)
     tables = w.make_tables()
     inj = w.make_injection()
-    say(f"small workload precision={precision}")
+    say(f"small workload precision={precision} layout={layout}")
     ctx = make_ctx(P, w, grid, tables, precision)
+    ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=layout)
     done, fg, ng, cg = run_gpu(ctx, inj)
     assert done
     fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
@@ -152,14 +157,23 @@ def test_small_workload_parity(P, O, small_grid, precision):
 # ---------------------------------------------------------------------------
 # Mixed nuclei with interactions, secondaries and the observer (256^3 grid).
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("precision", [0, 1])
-def test_mixed_workload_subset_parity(P, O, mixed_grid, precision):
+@pytest.mark.parametrize("precision,gdtype,launch", [
+    (0, np.float64, dict(block=128, blocks_per_cu=0, refill=4, layout=0)),
+    (0, np.float64, dict(block=128, blocks_per_cu=0, refill=4, layout=1)),
+    (0, np.float64, dict(block=256, blocks_per_cu=1, refill=16, layout=1)),
+    (1, np.float32, dict(block=128, blocks_per_cu=0, refill=4, layout=0)),
+    (1, np.float64, dict(block=256, blocks_per_cu=0, refill=4, layout=1))],
+    ids=["fp64-linear", "fp64-corner", "fp64-corner-b256", "mix-f32grid", "mix-f64grid-corner"])
+def test_mixed_workload_subset_parity(P, O, mixed_grid, precision, gdtype, launch):
+    """3000 candidates of the mixed workload; the FP64 grid's corner records
+    (192 bytes per cell) in both precision forms and both block sizes."""
     w = I.W_MIXED256
-    grid = mixed_grid if precision == 0 else mixed_grid.astype(np.float32)
+    grid = mixed_grid.astype(gdtype)
     tables = w.make_tables()
     inj = w.make_injection(3000)
-    say(f"mixed 256^3 subset precision={precision}")
+    say(f"mixed 256^3 subset precision={precision} grid={np.dtype(gdtype).name} {launch}")
     ctx = make_ctx(P, w, grid, tables, precision)
+    ctx.set_launch(**launch)
     done, fg, ng, cg = run_gpu(ctx, inj)
     assert done
     fo, no, co, _ = O.propagate(O.config_for(w, precision=precision),
