@@ -68,6 +68,9 @@ def main():
                     help="run a plain 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-pmc", type=str, default=None, metavar="DIR",
                     help="offline: per-launch HBM traffic from rocprofv3 --pmc CSV output")
+    ap.add_argument("--pmc-kernel", type=str, default=None,
+                    help="with --summarize-pmc: kernel-name prefix of the instantiation to "
+                         "summarize (default: the headline's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-nf", action="store_true", help="skip the neural-field variant")
     ap.add_argument("--nf-candidates", type=int, default=1_000_000)
@@ -97,6 +100,12 @@ def main():
                          "shape is tuned once and reused by the batching form)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the FP64 lines of the 32^3 and 256^3 workloads")
+    ap.add_argument("--fp64-grid-only", action="store_true",
+                    help="diagnostic: only the FP64 lines of the 32^3 and 256^3 workloads "
+                         "(for profiling them); prints their JSON")
+    ap.add_argument("--fp64-launch", type=str, default=None,
+                    help="force the launch of the FP64-grid workloads "
+                         "BLOCK,BLOCKS_PER_CU,REFILL,LAYOUT (no tuner)")
     ap.add_argument("--nf-sweep", type=str, default=None, metavar="NMAX,..:STEPS,..:LR",
                     help="diagnostic: neural-field RMS error on the 1024^3 grid against the "
                          "field band's n_max (band 2..n_max cycles per box) and the training "
@@ -108,7 +117,7 @@ def main():
         args.tune_cache = os.path.join(tempfile.mkdtemp(prefix="crp_bench_"), "tune_cache.txt")
 
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc)
+        summarize_pmc(args.summarize_pmc, args.pmc_kernel)
         return
 
     if args.gpus != 1:
@@ -135,6 +144,13 @@ def main():
 
     if args.nf_sweep:
         nf_sweep(args.nf_sweep, crp, I, torch, dev, stream)
+        return
+
+    if args.fp64_grid_only:
+        out = {"fp64_grid32": small_config_variant(args, crp, I, torch, stream, I.W_SMALL, None),
+               "fp64_grid256": small_config_variant(args, crp, I, torch, stream, I.W_MIXED256,
+                                                    10_000)}
+        print(json.dumps({"variant": "fp64_grid", **out}), flush=True)
         return
 
     w = I.W_MIXED1024
@@ -453,9 +469,13 @@ def tuned_fp64_launch(args, ctx):
     """The launch of an FP64-grid workload: the autotuner's pick on the
     context's pending work, each trial cut to TUNE_CYCLES_FP64 cycles (about a
     tenth of the 256^3 workload's run; the cache answers for a grid of the same
-    shape, element type and method), or the context's default with --no-tune.
+    shape, element type and method), the one --fp64-launch names, or the
+    context's default with --no-tune.
     The pending work is unchanged."""
-    if not args.no_tune:
+    if args.fp64_launch:
+        b, bpc, rf, lay = [int(v) for v in args.fp64_launch.split(",")]
+        ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
+    elif not args.no_tune:
         ctx.tune(max_cycles=TUNE_CYCLES_FP64, cache_path=args.tune_cache)
     return ctx.get_launch()
 
@@ -1057,10 +1077,13 @@ def nf_sweep(spec, crp, I, torch, dev, stream):
         torch.cuda.empty_cache()
 
 
-def summarize_pmc(d):
+def summarize_pmc(d, kernel=None):
     """Per-launch HBM read/write bytes of the propagation kernel from two
     rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch), each
-    scaled by what the same counter reads for the 1 GiB copy (--calib-copy)."""
+    scaled by what the same counter reads for the 1 GiB copy (--calib-copy).
+    kernel: the kernel-name prefix of the instantiation to summarize (default:
+    the precision form on the FP32 grid's corner records, the headline's)."""
+    kernel = kernel or "k_propagate<1, float, 2,"
     import csv
     import glob
     vals = {}
@@ -1072,13 +1095,13 @@ def summarize_pmc(d):
             # the timed propagation kernel: the precision form on the FP32 grid
             # (other instantiations run in the same process for the variant
             # lines: FP64 grids, the analytic field, the neural field)
-            grid_prop = "k_propagate<1, float, 2," in k
+            grid_prop = kernel in k
             kind = "prop" if grid_prop else ("copy" if "copyBuffer" in k else None)
             if kind:
                 vals.setdefault((kind, c), []).append((int(r["Dispatch_Id"]),
                                                        float(r["Counter_Value"])))
     gib = float(1 << 30)
-    out = {"kernel_sources_sha": kernel_sources_sha()}
+    out = {"kernel_sources_sha": kernel_sources_sha(), "kernel": kernel}
     for c, key in (("FETCH_SIZE", "read"), ("WRITE_SIZE", "write")):
         # the 1 GiB copy of --calib-copy is the run's first copy dispatch (later
         # copies, e.g. the 4 GiB copy-bandwidth probe, have other sizes)

@@ -89,20 +89,25 @@ __device__ __attribute__((always_inline)) inline NFView nf_view_lds(char* base, 
 // each write would wait for its load: ~33 memory latencies per block).
 __device__ __attribute__((always_inline)) inline void nf_stage_lds(char* dst, const char* src)
 {
-    constexpr int U = 8;
+    constexpr int U = 8;   // loads in flight per thread
     const int4* s = (const int4*)src;
     int4* d = (int4*)dst;
     const int n16 = (int)(NF_LDS_BYTES / 16);
     const int nt = (int)blockDim.x;
     int i = (int)threadIdx.x;
     for (; i + (U - 1) * nt < n16; i += U * nt) {
-        int4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            v[u] = s[i + u * nt];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            d[i + u * nt] = v[u];
+        // eight named registers (an array here was kept in scratch memory)
+        const int4 v0 = s[i], v1 = s[i + nt], v2 = s[i + 2 * nt], v3 = s[i + 3 * nt];
+        const int4 v4 = s[i + 4 * nt], v5 = s[i + 5 * nt], v6 = s[i + 6 * nt],
+                   v7 = s[i + 7 * nt];
+        d[i] = v0;
+        d[i + nt] = v1;
+        d[i + 2 * nt] = v2;
+        d[i + 3 * nt] = v3;
+        d[i + 4 * nt] = v4;
+        d[i + 5 * nt] = v5;
+        d[i + 6 * nt] = v6;
+        d[i + 7 * nt] = v7;
     }
     for (; i < n16; i += nt)
         d[i] = s[i];
