@@ -353,6 +353,27 @@ hipError_t copy_d2h(T* host, const T* dev, int64_t k, hipStream_t s)
     return hipMemcpyAsync(host, dev, k * sizeof(T), hipMemcpyDeviceToHost, s);
 }
 
+// Builds the corner records of grid g (ncell cells; 128 bytes per FP32 record,
+// 192 per FP64 record) into a new allocation; *out is set only once the
+// records are complete, so a failed build leaves nothing behind.
+template <class GT>
+crp_status build_corner_records(crp_ctx* ctx, const GridView& g, int64_t ncell, GT** out)
+{
+    const size_t rec = sizeof(GT) == 8 ? 192 : 128;
+    GT* p = nullptr;
+    HIPCHK(ctx, hipMalloc((void**)&p, (size_t)ncell * rec));
+    k_corner_relayout<GT><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, p);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return fail(ctx, CRP_EDEVICE, std::string("corner records: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return CRP_OK;
+}
+
 // Corner records of the base grid and of every refinement patch (built on
 // first use).  A patch's record of cell (i,j,k) holds its vertices i..i+1 etc.;
 // the records of its last vertex planes are built too (from wrapped indices)
@@ -361,35 +382,22 @@ hipError_t copy_d2h(T* host, const T* dev, int64_t k, hipStream_t s)
 // read from their linear arrays.
 crp_status ensure_corner(crp_ctx* ctx)
 {
-    if (ctx->grid_dtype == CRP_F64) {
-        if (!ctx->corner64) {
-            const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
-            if (ncell >= (1ll << 32))
-                return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
-            HIPCHK(ctx, hipMalloc((void**)&ctx->corner64, (size_t)ncell * 192));
-            GridView g = make_view(ctx);
-            k_corner_relayout<double><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g,
-                                                                                ctx->corner64);
-            HIPCHK(ctx, hipGetLastError());
-            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-        }
-        return CRP_OK;
-    }
+    const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
+    if (ncell >= (1ll << 32))
+        return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
+    if (ctx->grid_dtype == CRP_F64)
+        return ctx->corner64 ? CRP_OK
+                             : build_corner_records<double>(ctx, make_view(ctx), ncell,
+                                                            &ctx->corner64);
     if (!ctx->corner) {
-        const int64_t ncell = ctx->gn[0] * ctx->gn[1] * ctx->gn[2];
-        if (ncell >= (1ll << 32))
-            return fail(ctx, CRP_EINVAL, "corner layout: at most 2^32 - 1 cells");
-        HIPCHK(ctx, hipMalloc((void**)&ctx->corner, (size_t)ncell * 128));
-        GridView g = make_view(ctx);
-        k_corner_relayout<float><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g, ctx->corner);
-        HIPCHK(ctx, hipGetLastError());
+        crp_status st = build_corner_records<float>(ctx, make_view(ctx), ncell, &ctx->corner);
+        if (st != CRP_OK)
+            return st;
     }
     for (int k = 0; k < ctx->nest.np; ++k) {
         if (ctx->patch_corner[k])
             continue;
         PatchView& q = ctx->nest.p[k];
-        const int64_t ncell = (int64_t)q.n[0] * q.n[1] * q.n[2];
-        HIPCHK(ctx, hipMalloc((void**)&ctx->patch_corner[k], (size_t)ncell * 128));
         GridView g{};
         g.data = q.data;
         for (int a = 0; a < 3; ++a) {
@@ -401,12 +409,12 @@ crp_status ensure_corner(crp_ctx* ctx)
         g.stride[2] = 3;
         g.inv_spacing = 1.0;
         g.dtype = 0;
-        k_corner_relayout<float><<<ctx->num_cus * 8, 256, 0, ctx->stream>>>(g,
-                                                                           ctx->patch_corner[k]);
-        HIPCHK(ctx, hipGetLastError());
+        crp_status st = build_corner_records<float>(ctx, g, (int64_t)q.n[0] * q.n[1] * q.n[2],
+                                                    &ctx->patch_corner[k]);
+        if (st != CRP_OK)
+            return st;
         q.corner = ctx->patch_corner[k];
     }
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return CRP_OK;
 }
 
