@@ -123,6 +123,10 @@ crp_status fail(crp_ctx* ctx, crp_status st, const std::string& msg)
 {
     if (ctx)
         ctx->err = msg;
+    // a failed HIP call (an allocation that did not fit, say) stays the
+    // thread's last error until read: clear it here, so that the launch check
+    // of a later call reports only its own launch
+    (void)hipGetLastError();
     return st;
 }
 
@@ -940,6 +944,7 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
     auto bail = [&](crp_status st, const char* what, hipError_t e) {
         fprintf(stderr, "crp_create: %s: %s\n", what, hipGetErrorString(e));
         crp_destroy(ctx);
+        (void)hipGetLastError();   // as in fail()
         return st;
     };
     hipError_t e = hipSetDevice(c.device);

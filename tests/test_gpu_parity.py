@@ -381,6 +381,24 @@ def test_empty_and_capacity(P, mixed_grid):
     ctx.close()
 
 
+def test_failed_allocation_leaves_later_calls_working(P, small_grid):
+    """A device allocation that does not fit fails with CRP_ENOMEM and leaves
+    nothing behind that a later call would report: a context asking for a
+    2^40-slot queue is refused, and the next context runs a workload to
+    completion with every primary finished."""
+    w = I.W_SMALL
+    say("allocation failure, then a normal run")
+    prm = P.params_for(w, P.FP64, queue_capacity=1 << 40, neutral_capacity=1 << 12)
+    with pytest.raises(P.CrpError) as ei:
+        P.Context(prm)
+    assert ei.value.status == -3
+    ctx = make_ctx(P, w, small_grid, w.make_tables(), 0)
+    inj = w.make_injection(200)
+    done, fg, ng, cg = run_gpu(ctx, inj)
+    assert done and cg["finished"] == 200 and len(fg["id"]) == 200
+    ctx.close()
+
+
 def _spawning_injection(w, n):
     """Heavy nuclei above the channels' thresholds: many secondaries (nucleon
     loss) and neutral records (pion-like) per primary."""
