@@ -415,7 +415,10 @@ crp_status crp_get_launch(crp_ctx* ctx, crp_launch* launch);
 
 /* Autotuner: times candidate launch shapes, each twice, in two stages: block
  * 128 / 256, as many blocks per compute unit as fit or 3, refill 4 / 16, on
- * the linear and the corner layout; then, around the fastest of those, refill
+ * the linear and the corner layout (the corner layout only where its records
+ * can be built: they fit in device memory, the grid has fewer than 2^32
+ * cells, and it is not an FP64 grid with refinement patches); then, around
+ * the fastest of those, refill
  * 1 and 64 and 2 blocks per compute unit.  The trials run on a copy of the
  * pending queue (restored after each trial, so the
  * pending work is unchanged) run for max_cycles cycles (<= 0: to completion),

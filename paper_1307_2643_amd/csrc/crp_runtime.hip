@@ -2012,9 +2012,20 @@ crp_status crp_tune(crp_ctx* ctx, int64_t max_cycles, const char* cache_path, cr
             }
         }
     };
-    // stage 1: block size, occupancy and refill on both layouts
-    // (the multi-resolution kernel of an FP64 grid has no corner-record form)
-    const bool corner_ok = ctx->grid_dtype == CRP_F32 || ctx->nest.np == 0;
+    // stage 1: block size, occupancy and refill on both layouts (the
+    // multi-resolution kernel of an FP64 grid has no corner-record form; a grid
+    // whose records do not fit in device memory, or that has 2^32 cells or
+    // more, is tuned on the linear layout alone)
+    bool corner_ok = ctx->grid_dtype == CRP_F32 || ctx->nest.np == 0;
+    if (corner_ok) {
+        const crp_status cs = ensure_corner(ctx);
+        if (cs == CRP_ENOMEM || cs == CRP_EINVAL) {
+            corner_ok = false;
+            ctx->err.clear();   // not an error of the tuning
+        }
+        else if (cs != CRP_OK)
+            st = cs;
+    }
     for (int layout = 0; layout < (corner_ok ? 2 : 1) && st == CRP_OK; ++layout)
         for (const crp_launch& l : {crp_launch{128, 0, 4, 0}, crp_launch{128, 0, 16, 0},
                                     crp_launch{128, 3, 4, 0}, crp_launch{256, 0, 4, 0},
