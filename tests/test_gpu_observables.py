@@ -55,16 +55,21 @@ def compare_traj(tg, to, what):
     say(f"{what}: {len(tg['id'])} trajectory points bitwise identical")
 
 
-@pytest.mark.parametrize("precision,every,ids", [(0, 1, 1 << 30), (1, 1, 1 << 30),
-                                                 (0, 5, 700), (1, 3, 50)],
-                         ids=["fp64-every", "mix-every", "fp64-k5", "mix-k3"])
-def test_trajectory_points_parity(P, O, small_grid, precision, every, ids):
+@pytest.mark.parametrize("precision,every,ids,layout",
+                         [(0, 1, 1 << 30, 0), (1, 1, 1 << 30, 0), (0, 5, 700, 0), (1, 3, 50, 0),
+                          (0, 1, 1 << 30, 1), (1, 2, 1 << 30, 1)],
+                         ids=["fp64-every", "mix-every", "fp64-k5", "mix-k3", "fp64-every-corner",
+                              "mix-k2-corner"])
+def test_trajectory_points_parity(P, O, small_grid, precision, every, ids, layout):
+    """Every k-th step of the selected ids (the 32^3 FP64 grid, read from the
+    linear grid or from its 192-byte corner records) against the oracle."""
     w = I.W_SMALL
     inj = w.make_injection()
     cap = 1 << 21
     ctx = make_ctx(P, w, small_grid, w.make_tables(), precision, traj_every=every,
                    traj_ids=ids, traj_capacity=cap)
-    say(f"trajectory parity precision={precision} every={every} ids<{ids}")
+    ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=layout)
+    say(f"trajectory parity precision={precision} every={every} ids<{ids} layout={layout}")
     ctx.inject(inj)
     assert ctx.propagate()
     cg = ctx.counts()
@@ -81,7 +86,8 @@ def test_trajectory_points_parity(P, O, small_grid, precision, every, ids):
     compare_traj(tg, to, f"p{precision} every {every}")
 
 
-def test_trajectory_with_secondaries_and_budget(P, O, mixed_grid):
+@pytest.mark.parametrize("layout", [0, 1], ids=["linear", "corner"])
+def test_trajectory_with_secondaries_and_budget(P, O, mixed_grid, layout):
     """Mixed nuclei with secondaries and observer detections, run in slices of
     a cycle budget (parked candidates keep recording where they stopped)."""
     w = I.W_MIXED256
@@ -89,7 +95,8 @@ def test_trajectory_with_secondaries_and_budget(P, O, mixed_grid):
     cap = 1 << 22
     ctx = make_ctx(P, w, mixed_grid, w.make_tables(), P.FP64, traj_every=4,
                    traj_ids=1 << 30, traj_capacity=cap)
-    say("trajectory with secondaries, budget 150 cycles per call")
+    ctx.set_launch(block=256 if layout else 128, blocks_per_cu=0, refill=4, layout=layout)
+    say(f"trajectory with secondaries, budget 150 cycles per call, layout {layout}")
     ctx.inject(inj)
     calls = 1
     while not ctx.propagate(150):
