@@ -430,13 +430,16 @@ def _drain_run(P, ctx, inj, max_cycles=0):
     return fin, neu, ctx.counts(), waits
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_capacity_starved_run_equals_roomy_run(P, O, mixed_grid, precision):
+@pytest.mark.parametrize("precision,layout", [(0, 0), (1, 0), (0, 1)],
+                         ids=["fp64", "mix", "fp64-corner"])
+def test_capacity_starved_run_equals_roomy_run(P, O, mixed_grid, precision, layout):
     """Nothing is lost when the queue or the neutral-record buffer is too
     small: spawning candidates wait (parked just before their interaction),
     the queue doubles and the run goes on; with a full neutral buffer the
     caller reads the records and propagates again.  The records equal those
-    of a run with room to spare, bit for bit, and the oracle's."""
+    of a run with room to spare (linear layout), bit for bit, and the
+    oracle's; the starved runs read the grid in the given layout (1: the FP64
+    grid's corner records, whose wave-wide gathers skip the parked lanes)."""
     w = I.W_MIXED256
     tables = w.make_tables()
     grid = mixed_grid if precision == 0 else mixed_grid.astype(np.float32)
@@ -450,6 +453,7 @@ def test_capacity_starved_run_equals_roomy_run(P, O, mixed_grid, precision):
     for qcap, ncap, budget in ((256, 1 << 16, 0), (256, 16, 0), (300, 40, 25)):
         say(f"starved run qcap={qcap} ncap={ncap} budget={budget}")
         ctx = make_ctx(P, w, grid, tables, precision, qcap=qcap, ncap=ncap)
+        ctx.set_launch(block=128, blocks_per_cu=0, refill=4, layout=layout)
         fs, ns, cs, waits = _drain_run(P, ctx, inj, budget)
         ctx.close()
         assert cs["queue_deferred"] > 0
