@@ -466,8 +466,9 @@ def test_table_lookup_matches_numpy_interp(oracle_lib):
 
 def test_species_rate_scaling(oracle_lib):
     """Rates of a nucleus are A times the per-nucleon rate at E/A; the nucleon
-    channel needs A >= 2; the loss rate scales with Z^2/A (parity unpinned:
-    a proposal with no physical truth, checked for internal consistency)."""
+    channel needs A >= 2; the loss rate scales with Z^2/A (a reading with no
+    physical truth in the paper; this restates it, and the two propagation
+    tests below pin its implementation against the laws it implies)."""
     O = oracle_lib
     tab = I.tables_full()
     T = O.TablesRef(tab)
@@ -481,6 +482,85 @@ def test_species_rate_scaling(oracle_lib):
         assert np.isclose(r[0], A * tp, rtol=1e-13)
         assert np.isclose(r[1], (A * tn) if A >= 2 else 0.0, rtol=1e-13)
         assert np.isclose(r[3], Z * Z / A * bp, rtol=1e-13)
+
+
+def test_species_interaction_scaling_in_propagation(oracle_lib):
+    """The species scaling of the interaction rates (per nucleon at E/A, A
+    times per nucleus, the nucleon channel for A >= 2 only), checked through
+    propagation against the laws it implies: iron's first pion-like event
+    lies at an exponential path length of mean 1 / (56 t_pi); helium under
+    the nucleon-loss channel alone follows a linear death process (rate A t_n
+    at mass A, none at A = 1), so its mass after a path l is binomial in
+    p = exp(-t_n l) with the masses below 2 merged; protons never take the
+    nucleon channel.  A dropped factor A or a rate at E instead of E/A fails
+    one of them."""
+    O = oracle_lib
+    g = O.GridRef(uniform_grid((0, 0, 0.0)), I.MPC_M)
+    rng = np.random.default_rng(21)
+    n = 20000
+    cfg = O.make_config(seed=91, kappa_pi=1e-12, e_floor=1.0)
+
+    def nuclei(A, Z, E, lmax, m=n):
+        return I.Injection(np.arange(m, dtype=np.uint32), np.full(m, A, np.int32),
+                           np.full(m, Z, np.int32), np.full(m, E), np.zeros((m, 3)),
+                           I.isotropic(rng, m), np.full(m, lmax))
+
+    # iron, pion-like channel only: first events exponential with rate 56 t_pi
+    a = 1.0 / (500 * I.MPC_M)
+    t = O.TablesRef(I.tables_constant(t_pi=a))
+    _, neu, cnt, _ = O.propagate(cfg, g, t, nuclei(56, 26, 56 * 1e20, 100 * I.MPC_M),
+                                 nthreads=8, neu_cap=100 * n)
+    assert cnt["neu_dropped"] == 0
+    first = neu["m"] == 1
+    assert abs(int(first.sum()) - n) <= 5          # P(no event in 100 Mpc) = e^-11.2
+    L1 = np.linalg.norm(neu["x"][first], axis=1)
+    ks = stats.kstest(L1 * 56 * a, "expon")
+    assert ks.statistic < 1.63 / math.sqrt(first.sum())
+
+    # helium, nucleon-loss channel only: final mass after l = 10 Mpc
+    c = 1.0 / (20 * I.MPC_M)
+    ell = 10 * I.MPC_M
+    t = O.TablesRef(I.tables_constant(t_n=c))
+    fin, _, cnt, _ = O.propagate(cfg, g, t, nuclei(4, 2, 4e20, ell), nthreads=8,
+                                 neu_cap=100 * n)
+    Af = fin["A"][fin["lineage"] == 0]
+    assert len(Af) == n and cnt["inter_pi"] == 0
+    p = math.exp(-c * ell)
+    expect = np.array([p ** 4, 4 * p ** 3 * (1 - p), 6 * p ** 2 * (1 - p) ** 2])
+    expect = np.append(expect, 1.0 - expect.sum()) * n
+    seen = np.array([np.sum(Af == 4), np.sum(Af == 3), np.sum(Af == 2), np.sum(Af == 1)])
+    assert seen.sum() == n
+    assert stats.chisquare(seen, expect).pvalue > 1e-3
+
+    # protons: the nucleon channel is off whatever its rate
+    fin, _, cnt, _ = O.propagate(cfg, g, t, nuclei(1, 1, 1e20, 100 * I.MPC_M, 2000), nthreads=8)
+    assert cnt["inter_n"] == 0 and cnt["events"] == 0
+    assert np.all(fin["E"] == 1e20) and np.all(fin["A"] == 1)
+
+
+def test_species_loss_scaling_in_propagation(oracle_lib):
+    """The continuous loss of a nucleus (Z^2/A times the proton's relative
+    rate at E/A) through propagation: with beta_p = b at and above 2e19 eV per
+    nucleon and 0 well below, every species above the threshold ends at
+    E0 exp(-(Z^2/A) b L) within the (2,2) Pade factor's error (z^5/720 per
+    step of loss z), and iron at 1e18 eV per nucleon keeps its energy exactly
+    although its total energy (5.6e19 eV) is above the threshold."""
+    O = oracle_lib
+    e = I.table_nodes()
+    b = 0.005 / I.MPC_M
+    tab = O.TablesRef(I.Tables(e, 0.0 * e, 0.0 * e, np.where(e >= 2e19, b, 0.0)))
+    g = O.GridRef(uniform_grid((0, 0, 0.0)), I.MPC_M)
+    L = 10 * I.MPC_M
+    cfg = O.make_config(hmax=I.MPC_M)
+    for A, Z in I.SPECIES_AZ:
+        fin, _, cnt, _ = O.propagate(cfg, g, tab, one(O, A=A, Z=Z, E=A * 1e20, lmax=L))
+        beta = Z * Z / A * b
+        rel = fin["E"][0] / (A * 1e20 * math.exp(-beta * fin["L"][0])) - 1.0
+        z = beta * I.MPC_M                            # the largest step's loss
+        assert abs(rel) <= cnt["steps"] * (1.2 * z ** 5 / 720 + 1e-15), (A, rel)
+        assert fin["E"][0] / A > 3e19                 # stayed above the threshold
+    fin, _, cnt, _ = O.propagate(cfg, g, tab, one(O, A=56, Z=26, E=56 * 1e18, lmax=L))
+    assert fin["E"][0] == 56 * 1e18 and fin["L"][0] == L
 
 
 def test_controller_factor_exact_quantisation(oracle_lib):
