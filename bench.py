@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0
 GATHERS_PER_ATTEMPT = 6
 RECORD_BYTES = 8 * 3 * 4          # algorithmic bytes of one gather: 8 corners x 3 x FP32
 RECORD_BYTES_FP64 = 8 * 3 * 8     # the same for an FP64 grid
-TUNE_CYCLES_FP64 = 256            # cycles per autotuner trial on the FP64-grid workloads
+TUNE_CYCLES_FP64 = 256
+TUNE_N_HEADLINE = 2_000_000       # candidates of the timed batch the headline's tuning runs            # cycles per autotuner trial on the FP64-grid workloads
 
 
 def gathers(cnt):
@@ -96,8 +97,9 @@ def main():
                     help="batches of 1e7 candidates at distances 1..1000 Mpc in the batching "
                          "form (10 = the 1e8-candidate stream; 0 skips it)")
     ap.add_argument("--tune-cache", type=str, default=None,
-                    help="autotuner cache file (default: a new file for this run, so the "
-                         "shape is tuned once and reused by the batching form)")
+                    help="autotuner cache file (default: a new file for this run); the "
+                         "headline's shape is kept in FILE.headline, the batching form's and "
+                         "the FP64-grid workloads' in FILE")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the FP64 lines of the 32^3 and 256^3 workloads")
     ap.add_argument("--fp64-grid-only", action="store_true",
@@ -199,19 +201,17 @@ def main():
         ctx.set_launch(block=b, blocks_per_cu=bpc, refill=rf, layout=lay)
     elif not args.no_tune:
         t0 = time.time()
-        # calibration on the batching workload's distribution: 1e6 candidates
-        # at distances 1..1000 Mpc (the first of its batches), run to completion
-        # in every trial (its tail and secondaries included); the shape goes to
-        # the tuner cache, where the batching form finds it
-        cal = I.inject_distances(1_000_000, 404)
-        ctx.inject(cal)
-        tuned, rate = ctx.tune(max_cycles=0, cache_path=args.tune_cache)
-        ctx.discard_finished()
+        # the timed workload's own launch: the autotuner on the batch's first
+        # TUNE_N_HEADLINE candidates (the same mix, spectrum and field), every
+        # trial run to completion, tail and secondaries included; its cache file
+        # is its own (the batching form tunes on its own distribution)
+        inject(ctx, min(TUNE_N_HEADLINE, n))
+        tuned, rate = ctx.tune(max_cycles=0, cache_path=args.tune_cache + ".headline")
         while not ctx.propagate(0):
             pass
         ctx.discard_finished()
-        log(f"[bench] autotuner picked {tuned} ({rate:.3e} steps/s on the calibration "
-            f"batch) in {time.time() - t0:.1f}s")
+        log(f"[bench] autotuner picked {tuned} ({rate:.3e} steps/s on the batch's first "
+            f"{min(TUNE_N_HEADLINE, n)} candidates) in {time.time() - t0:.1f}s")
     launch = ctx.get_launch()
 
     def one_step(c):
@@ -895,8 +895,8 @@ def batching_variant(args, crp, I, torch, grid, tables, stream):
                    lmax=d[6][s], on_device=True)
 
     # the launch shape tuned on this workload's calibration batch (from the
-    # tuner cache when the headline's tuning wrote it; else tuned here), then
-    # that batch once more, untimed, as a warm-up
+    # tuner cache when an earlier run with the same cache file tuned it; else
+    # tuned here), then that batch once more, untimed, as a warm-up
     log("[bench] batching: inputs on the device; tuning on 1e6 candidates")
     inject(batches[0], 1_000_000)
     tuned, rate = ctx.tune(max_cycles=0, cache_path=args.tune_cache)

@@ -114,10 +114,12 @@ def _check_whole_batch(P, fin, neu, cnt, n):
 
 
 def test_autotuned_launch(P, big):
-    """The benchmark's tuning step, on the same calibration batch."""
+    """The benchmark's tuning step for this workload: the batch's first
+    TUNE_N_HEADLINE candidates, every trial run to completion."""
+    from bench import TUNE_N_HEADLINE
     ctx = _context(P, big, P.MIX)
-    _inject(ctx, big["d_inj"], 6_000_000)
-    say("autotuning on 6e6 candidates")
+    _inject(ctx, big["d_inj"], TUNE_N_HEADLINE)
+    say(f"autotuning on {TUNE_N_HEADLINE} candidates")
     tuned, rate = ctx.tune(max_cycles=0, cache_path=None)
     ctx.close()
     big["launch"] = dict(tuned)
