@@ -58,6 +58,7 @@ enum { CRP_LAYOUT_LINEAR = 0, CRP_LAYOUT_CORNER = 1 };  /* grid layout in HBM   
 enum { CRP_ACTIVE = 0, CRP_OBSERVED = 1, CRP_MAX_TRAJ = 2, CRP_ENERGY_FLOOR = 3,
        CRP_BOUNDARY = 4 };
 enum { CRP_CHAN_PI = 0, CRP_CHAN_N = 1 };
+enum { CRP_ORDER_LONGEST_FIRST = 0, CRP_ORDER_AS_GIVEN = 1 };   /* crp_config.inject_order */
 
 /* Run configuration (copied at crp_create). */
 typedef struct {
@@ -86,7 +87,13 @@ typedef struct {
     int32_t charge_sign;      /* +1 (or 0): forward tracking; -1: backtracking, i.e. the
                                  antiparticle (charge -Z) from the observer along the
                                  reversed arrival direction (section 4) */
-    int32_t pad_;
+    int32_t inject_order;     /* CRP_ORDER_LONGEST_FIRST (0): crp_inject queues each
+                                 batch in order of decreasing lmax * Z / E (the path
+                                 length in units of the rigidity, which grows with the
+                                 number of curvature-limited steps), so that the
+                                 persistent kernel starts the longest trajectories
+                                 first; CRP_ORDER_AS_GIVEN (1): in the caller's order.
+                                 Results do not depend on it. */
     double boundary_center[3];/* spherical boundary centre, m */
     double boundary_radius;   /* m; 0 disables it.  A candidate at or beyond the radius
                                  after a cycle stops with status CRP_BOUNDARY */
@@ -272,7 +279,10 @@ crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e_nodes_eV,
  * (m), dir [n][3] with | |dir| - 1 | <= 1e-12, lmax > 0 (m, trajectory
  * length limit); values finite; |pos| + lmax < 2^30 grid cells.  Pointers are
  * host memory (on_device = 0) or device memory (on_device = 1).  Injected
- * candidates start with L = 0, step h_min, event count 0, lineage 0.
+ * candidates start with L = 0, step h_min, event count 0, lineage 0.  The
+ * batch is queued in the order crp_config.inject_order selects (sorted on the
+ * device by a stable radix sort, in a grow-only buffer of 24 bytes per
+ * candidate kept by the context; batches of 2^32 or more are queued as given).
  * Errors: CRP_EINVAL (first bad index in crp_last_error; only checked for
  * host input), CRP_EQUEUE (capacity), CRP_ESTATE (no field yet).  With the
  * analytic field the grid-cell bound on |pos| + lmax does not apply. */

@@ -26,6 +26,7 @@ EVAL_ANALYTIC = 16 + FIELD_ANALYTIC
 EVAL_NOALLOC_MAX = 262144          # CRP_EVAL_NOALLOC_MAX
 F32, F64 = 0, 1
 LAYOUT_LINEAR, LAYOUT_CORNER = 0, 1
+ORDER_LONGEST_FIRST, ORDER_AS_GIVEN = 0, 1
 ACTIVE, OBSERVED, MAX_TRAJ, ENERGY_FLOOR, BOUNDARY = 0, 1, 2, 3, 4
 NF_NPARAM = 66435
 
@@ -57,7 +58,7 @@ class Config(C.Structure):
                 ("e_floor", C.c_double), ("obs_center", C.c_double * 3),
                 ("obs_radius", C.c_double), ("seed", C.c_uint64),
                 ("queue_capacity", C.c_int64), ("neutral_capacity", C.c_int64),
-                ("charge_sign", C.c_int32), ("pad_", C.c_int32),
+                ("charge_sign", C.c_int32), ("inject_order", C.c_int32),
                 ("boundary_center", C.c_double * 3), ("boundary_radius", C.c_double),
                 ("traj_every", C.c_int32), ("traj_ids", C.c_uint32),
                 ("traj_capacity", C.c_int64)]
@@ -278,7 +279,7 @@ class Params:
     queue_capacity: int = 1 << 16
     neutral_capacity: int = 1 << 16
     charge_sign: int = 1
-    pad_: int = 0
+    inject_order: int = 0                    # ORDER_LONGEST_FIRST
     boundary_center: tuple = (0.0, 0.0, 0.0)
     boundary_radius: float = 0.0
     traj_every: int = 0

@@ -944,36 +944,53 @@ __global__ void k_validate(int64_t n, const uint32_t* id, const int32_t* A, cons
         atomicMin(first_bad, (unsigned long long)i);
 }
 
+// Queue slot base + i takes input candidate perm[i] (perm null: candidate i).
 __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id,
                          const int32_t* A, const int32_t* Z, const double* E,
                          const double* pos, const double* dir, const double* lmax,
-                         uint64_t seed, double hmin, int mix)
+                         const uint32_t* perm, uint64_t seed, double hmin, int mix)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    const int64_t s = perm ? (int64_t)perm[i] : i;
     Cand c;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        c.x[a] = pos[3 * i + a];
-        const double d = dir[3 * i + a];
+        c.x[a] = pos[3 * s + a];
+        const double d = dir[3 * s + a];
         c.u[a] = mix ? (double)(float)d : d;
         c.u0[a] = c.u[a];
     }
-    c.E = E[i];
-    c.E0 = E[i];
+    c.E = E[s];
+    c.E0 = E[s];
     c.L = 0.0;
-    c.Lmax = lmax[i];
+    c.Lmax = lmax[s];
     c.hctrl = hmin;
-    c.id = id[i];
+    c.id = id[s];
     c.lineage = 0;
     c.m = 0;
     c.nsteps = 0;
     c.nrej = 0;
-    c.A = A[i];
-    c.Z = Z[i];
+    c.A = A[s];
+    c.Z = Z[s];
     c.tau = optical_depth(event_draw(seed, c.id, 0, 0).w[1]);
     store_cand(q, base + i, c);
+}
+
+// Sort keys of the longest-expected-path-first injection order: w = lmax * Z / E
+// (> 0 and finite for a validated candidate) descending, i.e. the bitwise
+// complement of w's IEEE pattern ascending (positive doubles order like their
+// bit patterns); idx = 0..n-1, the payload the sort permutes.
+__global__ void k_inject_keys(int64_t n, const int32_t* Z, const double* E, const double* lmax,
+                              unsigned long long* keys, uint32_t* idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const double w = lmax[i] * (double)Z[i] / E[i];
+    keys[i] = ~(unsigned long long)__double_as_longlong(w);
+    idx[i] = (uint32_t)i;
 }
 
 // -------------------------------------------------------------------------

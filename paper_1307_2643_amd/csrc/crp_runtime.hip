@@ -5,6 +5,7 @@
 // launches the kernels on the context's stream and converts errors into
 // crp_status codes (no exception crosses the ABI).
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -34,7 +35,9 @@ __global__ void k_validate(int64_t n, const uint32_t* id, const int32_t* A, cons
 __global__ void k_inject(QueueSoA q, int64_t base, int64_t n, const uint32_t* id,
                          const int32_t* A, const int32_t* Z, const double* E,
                          const double* pos, const double* dir, const double* lmax,
-                         uint64_t seed, double hmin, int mix);
+                         const uint32_t* perm, uint64_t seed, double hmin, int mix);
+__global__ void k_inject_keys(int64_t n, const int32_t* Z, const double* E, const double* lmax,
+                              unsigned long long* keys, uint32_t* idx);
 template <class GT>
 __global__ void k_corner_relayout(GridView g, GT* out);
 __global__ void k_gather_ceiling(const float* corner, uint32_t ncell, int iters, float* sink);
@@ -92,6 +95,8 @@ struct crp_ctx {
     unsigned long long* scratch = nullptr;   // small device scratch (validation)
     void* xfer = nullptr;                    // read-back staging (grow-only)
     size_t xfer_bytes = 0;
+    void* order_mem = nullptr;               // injection-order sort buffers (grow-only)
+    size_t order_bytes = 0;
 
     int64_t pending = 0;
     int64_t fin_unread = 0, neu_unread = 0, traj_unread = 0;
@@ -917,6 +922,7 @@ crp_status crp_create(const crp_config* cfg, void* stream, crp_ctx** out)
         !(c.field_mode == CRP_FIELD_GRID || c.field_mode == CRP_FIELD_NEURAL ||
           c.field_mode == CRP_FIELD_ANALYTIC) ||
         !(c.charge_sign == -1 || c.charge_sign == 0 || c.charge_sign == 1) ||
+        !(c.inject_order == CRP_ORDER_LONGEST_FIRST || c.inject_order == CRP_ORDER_AS_GIVEN) ||
         !(c.boundary_radius >= 0) || !std::isfinite(c.boundary_radius) ||
         !std::isfinite(c.boundary_center[0]) || !std::isfinite(c.boundary_center[1]) ||
         !std::isfinite(c.boundary_center[2]) ||
@@ -1026,7 +1032,8 @@ void crp_destroy(crp_ctx* ctx)
     for (void* p : {ctx->qmem[0], ctx->qmem[1], ctx->fmem, ctx->nmem, ctx->tmem, ctx->obs_mem,
                     (void*)ctx->cnt,
                     (void*)ctx->d_params,
-                    (void*)ctx->scratch, ctx->xfer, ctx->grid_owned, (void*)ctx->tab,
+                    (void*)ctx->scratch, ctx->xfer, ctx->order_mem, ctx->grid_owned,
+                    (void*)ctx->tab,
                     (void*)ctx->corner, (void*)ctx->corner64})
         if (p)
             (void)hipFree(p);
@@ -1252,6 +1259,44 @@ static std::string bad_candidate(int64_t i, const int32_t* A, const int32_t* Z, 
     return buf;
 }
 
+// The longest-expected-path-first order of a validated batch (device arrays):
+// a stable radix sort of the keys of k_inject_keys; *perm (in the context's
+// grow-only buffer) lists the input index of each queue slot in turn.
+crp_status inject_order_perm(crp_ctx* ctx, int64_t n, const int32_t* Z, const double* E,
+                             const double* lmax, const uint32_t** perm)
+{
+    const int ni = (int)n;
+    size_t tmp = 0;
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (unsigned long long*)nullptr,
+                                                   (unsigned long long*)nullptr,
+                                                   (uint32_t*)nullptr, (uint32_t*)nullptr, ni, 0,
+                                                   64, ctx->stream));
+    const size_t kb = ((size_t)n * 8 + 255) & ~(size_t)255;
+    const size_t ib = ((size_t)n * 4 + 255) & ~(size_t)255;
+    const size_t need = 2 * kb + 2 * ib + tmp;
+    if (need > ctx->order_bytes) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->order_mem)
+            (void)hipFree(ctx->order_mem);
+        ctx->order_mem = nullptr;
+        ctx->order_bytes = 0;
+        HIPCHK(ctx, hipMalloc(&ctx->order_mem, need));
+        ctx->order_bytes = need;
+    }
+    char* p = (char*)ctx->order_mem;
+    auto* keys = (unsigned long long*)p;
+    auto* keys_sorted = (unsigned long long*)(p + kb);
+    auto* idx = (uint32_t*)(p + 2 * kb);
+    auto* idx_sorted = (uint32_t*)(p + 2 * kb + ib);
+    void* temp = p + 2 * kb + 2 * ib;
+    k_inject_keys<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, Z, E, lmax, keys, idx);
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(temp, tmp, keys, keys_sorted, idx, idx_sorted,
+                                                   ni, 0, 64, ctx->stream));
+    *perm = idx_sorted;
+    return CRP_OK;
+}
+
 crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t* A,
                       const int32_t* Z, const double* E, const double* pos, const double* dir,
                       const double* lmax, int32_t on_device)
@@ -1339,8 +1384,17 @@ crp_status crp_inject(crp_ctx* ctx, int64_t n, const uint32_t* id, const int32_t
             return fail(ctx, CRP_EINVAL,
                         "inject: candidate " + std::to_string(bad) + " is invalid (device input)");
     }
+    const uint32_t* perm = nullptr;
+    if (ctx->cfg.inject_order == CRP_ORDER_LONGEST_FIRST && n > 1 && n <= INT32_MAX) {
+        const crp_status st = inject_order_perm(ctx, n, d_Z, d_E, d_lmax, &perm);
+        if (st != CRP_OK) {
+            if (stage)
+                (void)hipFree(stage);
+            return st;
+        }
+    }
     k_inject<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(
-        ctx->q, ctx->pending, n, d_id, d_A, d_Z, d_E, d_pos, d_dir, d_lmax, ctx->cfg.seed,
+        ctx->q, ctx->pending, n, d_id, d_A, d_Z, d_E, d_pos, d_dir, d_lmax, perm, ctx->cfg.seed,
         ctx->cfg.hmin, ctx->cfg.precision == CRP_MIX ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)

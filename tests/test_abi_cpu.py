@@ -107,7 +107,8 @@ def test_create_rejects_bad_configs_before_any_device_call():
            dict(obs_radius=-1.0), dict(obs_center=(0.0, math.nan, 0.0)),
            dict(boundary_radius=math.inf), dict(queue_capacity=0),
            dict(neutral_capacity=(1 << 40) + 1), dict(traj_every=1, traj_capacity=0),
-           dict(field_mode=crp.FIELD_NEURAL, precision=crp.FP64)]
+           dict(field_mode=crp.FIELD_NEURAL, precision=crp.FP64), dict(inject_order=2),
+           dict(inject_order=-1)]
     for kw in bad:
         assert status(**kw) == -1, kw
     assert status() in (0, -2)

@@ -290,6 +290,41 @@ def test_launch_shape_invariance(P, mixed_grid, launch):
         assert rc[k] == gc[k]
 
 
+def test_injection_order_longest_first(P, mixed_grid):
+    """crp_inject queues a batch in decreasing lmax * Z / E (ties in the
+    caller's order), from host arrays and from device arrays alike; the run's
+    records and counters equal those of the caller's order bit for bit."""
+    import torch
+    w = I.W_MIXED256
+    grid = mixed_grid.astype(np.float32)
+    tables = w.make_tables()
+    inj = I.inject_distances(3000, 77, dmax_m=40 * I.MPC_M)
+    key = inj.lmax * inj.Z / inj.E
+    order = np.argsort(-key, kind="stable")
+    runs = {}
+    for name, kw, on_dev in (("sorted", {}, False), ("sorted-device", {}, True),
+                             ("as-given", dict(inject_order=P.ORDER_AS_GIVEN), False)):
+        say(f"injection order: {name}")
+        ctx = make_ctx(P, w, grid, tables, 1, **kw)
+        if on_dev:
+            d = [torch.as_tensor(a, device="cuda:0") for a in
+                 (inj.id.view(np.int32), inj.A, inj.Z, inj.E, inj.pos, inj.dir, inj.lmax)]
+            ctx.inject(id=d[0], A=d[1], Z=d[2], E=d[3], pos=d[4], dir=d[5], lmax=d[6],
+                       on_device=True)
+        else:
+            ctx.inject(inj)
+        queued = ctx.peek_pending()["id"]
+        expect = inj.id if name == "as-given" else inj.id[order]
+        assert np.array_equal(queued, expect), name
+        assert ctx.propagate()
+        runs[name] = (ctx.read_finished(), ctx.counts())
+        ctx.close()
+    for name in ("sorted-device", "as-given"):
+        _assert_identical(runs["sorted"][0], runs[name][0])
+        for k in CNT_KEYS:
+            assert runs["sorted"][1][k] == runs[name][1][k], (name, k)
+
+
 def test_batch_split_and_budget_invariance(P, mixed_grid):
     w = I.W_MIXED256
     tables = w.make_tables()
