@@ -323,6 +323,14 @@ def test_injection_order_longest_first(P, mixed_grid):
         _assert_identical(runs["sorted"][0], runs[name][0])
         for k in CNT_KEYS:
             assert runs["sorted"][1][k] == runs[name][1][k], (name, k)
+    # ties keep the caller's order (a stable sort): five energies, one lmax
+    tie = I.Injection(inj.id, inj.A, inj.Z, 1e19 * (1 + inj.id % 5).astype(np.float64), inj.pos,
+                      inj.dir, np.full(len(inj.id), 30 * I.MPC_M))
+    ctx = make_ctx(P, w, grid, tables, 1)
+    ctx.inject(tie)
+    key = tie.lmax * tie.Z / tie.E
+    assert np.array_equal(ctx.peek_pending()["id"], tie.id[np.argsort(-key, kind="stable")])
+    ctx.close()
 
 
 def test_batch_split_and_budget_invariance(P, mixed_grid):
