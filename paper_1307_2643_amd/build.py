@@ -32,15 +32,56 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+OBJ_DIR = os.path.join(HERE, "_obj")
+
+
+def _run_parallel(cmds, verbose: bool) -> None:
+    """Runs the commands, at most CRP_BUILD_JOBS (default: the CPU count, at
+    most 16) at a time; raises CalledProcessError for the first that fails."""
+    jobs = int(os.environ.get("CRP_BUILD_JOBS", os.cpu_count() or 4))
+    jobs = max(1, min(jobs, 16, len(cmds)))
+    pending, running, failed = list(cmds), [], None
+    while pending or running:
+        while pending and failed is None and len(running) < jobs:
+            cmd = pending.pop(0)
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            running.append((cmd, subprocess.Popen(cmd)))
+        cmd, proc = running.pop(0)
+        if proc.wait() != 0 and failed is None:
+            failed = subprocess.CalledProcessError(proc.returncode, cmd)
+            pending.clear()
+    if failed is not None:
+        raise failed
+
+
+def _lib_objects():
+    """(compile commands, object paths) of libcrp.so's sources."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    flags = [f for f in FLAGS if f != "-shared"]
+    inc = os.path.join(HERE, "..", "include")
+    cmds, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(OBJ_DIR, s.replace(".hip", ".o"))
+        cmds.append([hipcc()] + flags + ["-I", inc, "-c", "-o", obj, os.path.join(CSRC, s)])
+        objs.append(obj)
+    return cmds, objs
+
+
+def _link_lib(objs, verbose: bool) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build(verbose: bool = False) -> str:
+    cmds, objs = _lib_objects()
+    _run_parallel(cmds, verbose)
+    return _link_lib(objs, verbose)
 
 
 # The host runtime under AddressSanitizer and UndefinedBehaviorSanitizer: the
@@ -55,19 +96,28 @@ SAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=unde
 SAN_LINK = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 
-def build_sanitized(verbose: bool = False) -> str:
+def _sanitized_objects():
+    """(compile commands, object paths) of the sanitizer build's sources."""
     os.makedirs(SAN_DIR, exist_ok=True)
     inc = os.path.join(HERE, "..", "include")
     flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
-    objs = []
+    cmds, objs = [], []
     for s in SOURCES:
         obj = os.path.join(SAN_DIR, s.replace(".hip", ".o"))
-        cmd = [hipcc()] + flags + SAN_HOST + ["-g", "-I", inc, "-c", "-o", obj,
-                                              os.path.join(CSRC, s)]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([hipcc()] + flags + SAN_HOST + ["-g", "-I", inc, "-c", "-o", obj,
+                                                    os.path.join(CSRC, s)])
         objs.append(obj)
+    return cmds, objs
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    cmds, objs = _sanitized_objects()
+    _run_parallel(cmds, verbose)
+    return _link_sanitized(objs, verbose)
+
+
+def _link_sanitized(objs, verbose: bool) -> str:
+    inc = os.path.join(HERE, "..", "include")
     # host link (no HIP source on this line): ROCm's clang, whose sanitizer
     # runtime matches the instrumented objects
     clang = os.path.join(os.path.dirname(hipcc()), "..", "llvm", "bin", "clang++")
@@ -84,7 +134,16 @@ def build_sanitized(verbose: bool = False) -> str:
     return SAN_EXE
 
 
+def build_all(verbose: bool = False):
+    """libcrp.so and the sanitizer build, their objects compiled in one pool."""
+    lib_cmds, lib_objs = _lib_objects()
+    san_cmds, san_objs = _sanitized_objects()
+    _run_parallel(lib_cmds + san_cmds, verbose)
+    return _link_lib(lib_objs, verbose), _link_sanitized(san_objs, verbose)
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
     if "--sanitized" in sys.argv:
-        print(build_sanitized(verbose="-v" in sys.argv))
+        print(build_all(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
