@@ -458,12 +458,15 @@ void section_tune_eval_observe(const Grid& g, const Tables& t)
 
 // FP64 grid: the corner-record layout (192-byte records, built on first use,
 // freed and rebuilt when the grid is set again) gives the records of the
-// linear layout; the tuner tries both layouts on it.
+// linear layout; the tuner tries both layouts on it.  The reference run queues
+// the batch in the caller's order, the others longest expected path first.
 void section_fp64_corner(const Grid& g, const Tables& t)
 {
     crp_config c = base_config(CRP_FP64);
     const Inj j = make_injection(300, 21, g.n * g.spacing, 10 * MPC);
+    c.inject_order = CRP_ORDER_AS_GIVEN;
     crp_ctx* a = make_ctx(c, g, t, false);
+    c.inject_order = CRP_ORDER_LONGEST_FIRST;
     OK(inject(a, j));
     run_to_end(a, 0, nullptr);
     Records ra;
