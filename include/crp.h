@@ -282,7 +282,7 @@ crp_status crp_set_tables(crp_ctx* ctx, int32_t n, const double* e_nodes_eV,
  * candidates start with L = 0, step h_min, event count 0, lineage 0.  The
  * batch is queued in the order crp_config.inject_order selects (sorted on the
  * device by a stable radix sort, in a grow-only buffer of 24 bytes per
- * candidate kept by the context; batches of 2^32 or more are queued as given).
+ * candidate kept by the context; batches of 2^31 or more are queued as given).
  * Errors: CRP_EINVAL (first bad index in crp_last_error; only checked for
  * host input), CRP_EQUEUE (capacity), CRP_ESTATE (no field yet).  With the
  * analytic field the grid-cell bound on |pos| + lmax does not apply. */
