@@ -31,7 +31,7 @@ GATHERS_PER_ATTEMPT = 6
 RECORD_BYTES = 8 * 3 * 4          # algorithmic bytes of one gather: 8 corners x 3 x FP32
 RECORD_BYTES_FP64 = 8 * 3 * 8     # the same for an FP64 grid
 TUNE_CYCLES_FP64 = 256
-TUNE_N_HEADLINE = 2_000_000       # candidates of the timed batch the headline's tuning runs            # cycles per autotuner trial on the FP64-grid workloads
+TUNE_N_HEADLINE = 5_000_000       # candidates of the timed batch the headline's tuning runs            # cycles per autotuner trial on the FP64-grid workloads
 
 
 def gathers(cnt):
